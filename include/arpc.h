@@ -1,0 +1,146 @@
+/*
+ * arpc.h - C ABI of the MI355X (gfx950) accelerated randomly pivoted Cholesky library.
+ *
+ * The operation follows Epperly, Tropp & Webber, "Embrace rejection: kernel
+ * matrix approximation by accelerated randomly pivoted Cholesky" (arXiv
+ * 2410.03969):
+ *   - the problem statement of Section 1 (low-rank psd approximation: given a
+ *     psd N x N matrix A and a rank k, return F (N x k) with A ~ F F^T),
+ *   - the kernel matrix A(i,j) = kappa(x_i, x_j) built from points (Section 1.2),
+ *   - accelerated RPCholesky, standard implementation (Alg. 2, Section 2.3),
+ *     with RejectionSampleSubmatrix (Alg. 1, Section 2.2) inside every round.
+ *
+ * Every call returns an arpc_status; nothing throws or aborts across the ABI.
+ * Pointers documented as "device" must point to memory of the current HIP
+ * device; the library never frees memory it did not allocate.
+ */
+#ifndef ARPC_H
+#define ARPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum arpc_status {
+  ARPC_OK = 0,           /* k pivots produced */
+  ARPC_EARLY_STOP = 1,   /* informational: the residual became (numerically) zero
+                            before k pivots; k_out < k, see arpc_factor */
+  ARPC_EINVAL = -1,      /* invalid argument (sizes, pointers, alignment, workspace) */
+  ARPC_ENOMEM = -2,      /* an allocation or admission could not be satisfied */
+  ARPC_EBUSY = -3,       /* a queue or slot table is full */
+  ARPC_EDEVICE = -4,     /* a HIP runtime call failed */
+  ARPC_ENUMERIC = -5,    /* the points contain NaN or Inf */
+  ARPC_ECANCELED = -6    /* the job was cancelled */
+} arpc_status;
+
+/* Kernel functions (Section 1.2 and Section 3).  The Laplace kernel uses the
+ * l2 distance; Matern-3/2 is (1 + sqrt3 r/s) exp(-sqrt3 r/s). */
+typedef enum arpc_kernel {
+  ARPC_GAUSSIAN = 0,     /* exp(-|x-y|^2 / (2 s^2)) */
+  ARPC_LAPLACE_L2 = 1,   /* exp(-|x-y| / s) */
+  ARPC_MATERN32 = 2,
+  ARPC_MATERN52 = 3      /* (1 + sqrt5 r/s + 5 r^2/(3 s^2)) exp(-sqrt5 r/s) */
+} arpc_kernel;
+
+/* Arithmetic of the N-sized steps.  In every mode the residual diagonal, the
+ * b x b residual submatrix, its Cholesky factor and the acceptance tests are
+ * FP64. */
+typedef enum arpc_prec {
+  ARPC_FP64 = 0,    /* F stored FP64; update GEMM and triangular solve in FP64 */
+  ARPC_FP32 = 1,    /* F stored FP32; update GEMM and solve in FP32 */
+  ARPC_BF16X3 = 2,  /* F stored FP32; update GEMM on BF16 matrix cores with a
+                       hi/lo split of both operands (three products), FP32 accumulation */
+  ARPC_BF16 = 3     /* F stored FP32; update GEMM with BF16-rounded operands, FP32 accumulation */
+} arpc_prec;
+
+typedef struct arpc_problem {
+  int64_t N;          /* number of points, 1 <= N <= 2^31 - 1 */
+  int64_t d;          /* dimension, 1 <= d <= 4096 */
+  int64_t k;          /* target rank, 1 <= k <= N */
+  int64_t b;          /* proposals per round (block size), 1 <= b <= 1024 */
+  int32_t kernel;     /* arpc_kernel */
+  int32_t prec;       /* arpc_prec */
+  double bandwidth;   /* sigma (length scale), finite and > 0 */
+  uint64_t seed;      /* key of the uniform stream */
+  int64_t max_rounds; /* 0: run until k pivots; > 0: stop after this many rounds */
+} arpc_problem;
+
+enum {
+  ARPC_KC_INIT = 0, ARPC_KC_PROPOSE, ARPC_KC_GATHER, ARPC_KC_REJECT, ARPC_KC_PREP,
+  ARPC_KC_COLGEMM, ARPC_KC_TRSM, ARPC_KC_DIAG, ARPC_KC_FINISH, ARPC_NUM_KC
+};
+
+typedef struct arpc_stats {
+  int64_t k_out;        /* pivots produced */
+  int64_t rounds;       /* rounds run */
+  int64_t proposals;    /* b * rounds */
+  int32_t status;       /* ARPC_OK or ARPC_EARLY_STOP */
+  int32_t reserved;
+  double trace_A;       /* sum of diag A */
+  double trace_resid;   /* sum of the final residual diagonal */
+  double ms_total;      /* host wall time of the call */
+  double ms_kernel[ARPC_NUM_KC];   /* summed kernel time per class (profiling on) */
+  int64_t launches[ARPC_NUM_KC];   /* launches per class (profiling on) */
+  double flops_colgemm; /* algorithmic flops of the update GEMM, sum_r 2 N k_r s_r */
+  double flops_trsm;    /* algorithmic flops of the triangular solve, sum_r N s_r^2 */
+} arpc_stats;
+
+/* Human-readable name of a status code (static storage). */
+const char* arpc_status_str(int status);
+
+/* Library version string (static storage). */
+const char* arpc_version(void);
+
+/* Bytes of device workspace that arpc_factor needs for *problem.
+ * Returns ARPC_EINVAL for an invalid problem. */
+arpc_status arpc_workspace_size(const arpc_problem* problem, size_t* bytes);
+
+/* Accelerated RPCholesky (Alg. 2 with Alg. 1) of the kernel matrix of X.
+ *
+ *  X       device, N x d row-major FP64 points (read only).
+ *  F       device, N x k column-major output, FP64 for ARPC_FP64 and FP32 for
+ *          the other modes; column j belongs to pivots[j].  Caller-allocated.
+ *  pivots  device, k int64 outputs, 0-based row indices in acceptance order.
+ *  ws      device workspace of at least arpc_workspace_size bytes, 256-byte aligned.
+ *  stream  hipStream_t (NULL = default stream) on which all work is enqueued.
+ *  stats   host, may be NULL.
+ *
+ * Round r draws its b proposals from uniform words 2br..2br+b-1 and its b
+ * acceptance tests from words 2br+b..2br+2b-1 of the Philox4x64-10 stream
+ * keyed by problem->seed (block q of four words at counter q+1, uniform =
+ * (word >> 11) * 2^-53).
+ *
+ * Blocks the calling thread until the factorization is complete (the host
+ * checks the device-side round state between batches of rounds).  Returns
+ * ARPC_OK, or ARPC_EARLY_STOP when the residual trace reached zero or a round
+ * accepted nothing; then columns k_out..k-1 of F are zero and
+ * pivots[k_out..k-1] = -1.  Errors: ARPC_EINVAL, ARPC_ENUMERIC (non-finite
+ * point), ARPC_EDEVICE. */
+arpc_status arpc_factor(const arpc_problem* problem, const double* X, void* F,
+                        int64_t* pivots, void* ws, size_t ws_bytes, void* stream,
+                        arpc_stats* stats);
+
+/* Same as arpc_factor with the uniform stream replaced by an explicit device
+ * array U of nU FP64 values in [0,1) (word p = U[p]).  If the run needs more
+ * than nU words it stops after the last complete round and returns
+ * ARPC_EINVAL. */
+arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, void* F,
+                                 int64_t* pivots, void* ws, size_t ws_bytes, void* stream,
+                                 const double* U, int64_t nU, arpc_stats* stats);
+
+/* Host evaluation of the library's uniform stream: out[i] = uniform of word
+ * start + i for key seed.  out is host memory of n doubles. */
+arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out);
+
+/* Per-kernel timing with HIP events, recorded into arpc_stats.ms_kernel
+ * (process-wide switch; off by default). */
+void arpc_set_profiling(int on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARPC_H */

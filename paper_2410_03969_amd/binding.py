@@ -1,0 +1,162 @@
+"""Thin ctypes binding of libarpc.so (argument marshalling only).
+
+Names mirror the C ABI in include/arpc.h.  Every computation runs in the HIP
+library; PyTorch is used only to allocate device memory and to obtain the
+current HIP stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libarpc.so")
+
+ARPC_OK, ARPC_EARLY_STOP = 0, 1
+ARPC_EINVAL, ARPC_ENOMEM, ARPC_EBUSY, ARPC_EDEVICE, ARPC_ENUMERIC, ARPC_ECANCELED = -1, -2, -3, -4, -5, -6
+KERNEL_CLASSES = ["init", "propose", "gather", "reject", "prep", "colgemm", "trsm", "diag", "finish"]
+NUM_KC = len(KERNEL_CLASSES)
+
+EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_factor",
+           "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling"]
+
+
+class ArpcProblem(C.Structure):
+    _fields_ = [("N", C.c_int64), ("d", C.c_int64), ("k", C.c_int64), ("b", C.c_int64),
+                ("kernel", C.c_int32), ("prec", C.c_int32), ("bandwidth", C.c_double),
+                ("seed", C.c_uint64), ("max_rounds", C.c_int64)]
+
+
+class ArpcStats(C.Structure):
+    _fields_ = [("k_out", C.c_int64), ("rounds", C.c_int64), ("proposals", C.c_int64),
+                ("status", C.c_int32), ("reserved", C.c_int32), ("trace_A", C.c_double),
+                ("trace_resid", C.c_double), ("ms_total", C.c_double),
+                ("ms_kernel", C.c_double * NUM_KC), ("launches", C.c_int64 * NUM_KC),
+                ("flops_colgemm", C.c_double), ("flops_trsm", C.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("ms_kernel", "launches")}
+        d["ms_kernel"] = dict(zip(KERNEL_CLASSES, list(self.ms_kernel)))
+        d["launches"] = dict(zip(KERNEL_CLASSES, list(self.launches)))
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libarpc.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_2410_03969_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.arpc_status_str.restype = C.c_char_p
+        L.arpc_status_str.argtypes = [C.c_int]
+        L.arpc_version.restype = C.c_char_p
+        L.arpc_workspace_size.restype = C.c_int
+        L.arpc_workspace_size.argtypes = [C.POINTER(ArpcProblem), C.POINTER(C.c_size_t)]
+        L.arpc_factor.restype = C.c_int
+        L.arpc_factor.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(ArpcStats)]
+        L.arpc_factor_uniforms.restype = C.c_int
+        L.arpc_factor_uniforms.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_int64,
+                                           C.POINTER(ArpcStats)]
+        L.arpc_stream_uniforms_host.restype = C.c_int
+        L.arpc_stream_uniforms_host.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_void_p]
+        L.arpc_set_profiling.restype = None
+        L.arpc_set_profiling.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def make_problem(p) -> ArpcProblem:
+    """From a workloads.Problem (or any object with the same fields)."""
+    return ArpcProblem(N=p.N, d=p.d, k=p.k, b=p.b, kernel=p.kernel, prec=p.prec,
+                       bandwidth=float(p.sigma), seed=int(p.seed),
+                       max_rounds=int(getattr(p, "max_rounds", 0) or 0))
+
+
+def arpc_status_str(status: int) -> str:
+    return lib().arpc_status_str(int(status)).decode()
+
+
+def arpc_version() -> str:
+    return lib().arpc_version().decode()
+
+
+def arpc_workspace_size(problem: ArpcProblem) -> int:
+    n = C.c_size_t(0)
+    st = lib().arpc_workspace_size(C.byref(problem), C.byref(n))
+    if st != ARPC_OK:
+        raise ValueError(f"arpc_workspace_size: {arpc_status_str(st)}")
+    return int(n.value)
+
+
+def arpc_factor(problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: int, ws_ptr: int,
+                ws_bytes: int, stream: int):
+    stats = ArpcStats()
+    st = lib().arpc_factor(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(F_ptr), C.c_void_p(piv_ptr),
+                           C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream), C.byref(stats))
+    return st, stats
+
+
+def arpc_factor_uniforms(problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: int, ws_ptr: int,
+                         ws_bytes: int, stream: int, U_ptr: int, nU: int):
+    stats = ArpcStats()
+    st = lib().arpc_factor_uniforms(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(F_ptr),
+                                    C.c_void_p(piv_ptr), C.c_void_p(ws_ptr), C.c_size_t(ws_bytes),
+                                    C.c_void_p(stream), C.c_void_p(U_ptr), C.c_int64(nU), C.byref(stats))
+    return st, stats
+
+
+def arpc_stream_uniforms_host(seed: int, start: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.float64)
+    st = lib().arpc_stream_uniforms_host(C.c_uint64(seed), C.c_int64(start), C.c_int64(n),
+                                         out.ctypes.data_as(C.c_void_p))
+    if st != ARPC_OK:
+        raise ValueError(arpc_status_str(st))
+    return out
+
+
+def arpc_set_profiling(on: bool) -> None:
+    lib().arpc_set_profiling(1 if on else 0)
+
+
+# ------------------------------------------------------------ torch convenience
+def factor(X, problem, U=None, device: str = "cuda", stream=None, workspace=None):
+    """Run the factorization on the GPU.  X: numpy (N x d) or a device tensor.
+    Returns a dict with the device tensors F (N x k, column j = F[:, j]),
+    pivots, and the status and stats.  Allocation only: all arithmetic runs in
+    libarpc.so."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a GPU")
+    pr = make_problem(problem)
+    if isinstance(X, np.ndarray):
+        Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(device)
+    else:
+        Xd = X.contiguous()
+    fdt = torch.float64 if problem.prec == 0 else torch.float32
+    # column-major N x k == row-major k x N
+    Ft = torch.empty((problem.k, problem.N), dtype=fdt, device=device)
+    piv = torch.empty(problem.k, dtype=torch.int64, device=device)
+    nbytes = arpc_workspace_size(pr)
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    if U is None:
+        status, stats = arpc_factor(pr, Xd.data_ptr(), Ft.data_ptr(), piv.data_ptr(), ws.data_ptr(),
+                                    nbytes, s.cuda_stream)
+    else:
+        Ud = torch.as_tensor(np.asarray(U, dtype=np.float64)).to(device)
+        status, stats = arpc_factor_uniforms(pr, Xd.data_ptr(), Ft.data_ptr(), piv.data_ptr(),
+                                             ws.data_ptr(), nbytes, s.cuda_stream, Ud.data_ptr(),
+                                             Ud.numel())
+    if status < 0:
+        raise RuntimeError(f"arpc_factor failed: {arpc_status_str(status)}")
+    return {"F": Ft.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}

@@ -1,0 +1,332 @@
+// C ABI and host driver of the accelerated RPCholesky library.
+//
+// arpc_factor validates the problem, carves the caller's workspace, and
+// enqueues rounds of Alg. 2 (each: proposals, residual submatrix,
+// RejectionSampleSubmatrix, update GEMM, triangular solve, diagonal update)
+// in batches.  The round state lives on the device; the host only reads it
+// between batches to decide whether more rounds are needed.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/arpc.h"
+#include "arpc_common.h"
+#include "arpc_launch.h"
+
+using namespace arpc;
+
+namespace {
+
+int g_profiling = 0;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t st, u, csum, cpre, props, acc, hist, Fs, H, L, Xp, Bt, Bt2, C, P, trace, total;
+};
+
+inline int64_t nchunks_of(int64_t N) { return (N + CHUNK - 1) / CHUNK; }
+
+size_t elem_size(int prec) { return prec == ARPC_FP64 ? sizeof(double) : sizeof(float); }
+
+Layout layout_of(const arpc_problem& p) {
+  Layout l{};
+  const size_t es = elem_size(p.prec);
+  const int64_t nch = nchunks_of(p.N);
+  const int64_t nparts = (p.b + 63) / 64;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  l.st = take(sizeof(RoundState));
+  l.u = take(sizeof(double) * p.N);
+  l.csum = take(sizeof(double) * nch);
+  l.cpre = take(sizeof(double) * nch);
+  l.props = take(sizeof(int64_t) * p.b);
+  l.acc = take(sizeof(int32_t) * p.b);
+  l.hist = take(sizeof(int32_t) * (p.k + 1));
+  l.Fs = take(sizeof(double) * p.b * p.k);
+  l.H = take(sizeof(double) * p.b * p.b);
+  l.L = take(sizeof(double) * p.b * p.b);
+  l.Xp = take(sizeof(double) * p.b * p.d);
+  l.Bt = take(es * p.k * p.b);
+  l.Bt2 = take(es * p.b * p.b);
+  l.C = take(es * p.N * p.b);
+  l.P = take(sizeof(double) * nparts * p.N);
+  l.trace = take(sizeof(double));
+  l.total = off;
+  return l;
+}
+
+arpc_status validate(const arpc_problem* p) {
+  if (!p) return ARPC_EINVAL;
+  if (p->N < 1 || p->N > 2147483647LL) return ARPC_EINVAL;
+  if (p->d < 1 || p->d > 4096) return ARPC_EINVAL;
+  if (p->k < 1 || p->k > p->N) return ARPC_EINVAL;
+  if (p->b < 1 || p->b > BMAX) return ARPC_EINVAL;
+  if (p->kernel < ARPC_GAUSSIAN || p->kernel > ARPC_MATERN52) return ARPC_EINVAL;
+  if (p->prec < ARPC_FP64 || p->prec > ARPC_BF16) return ARPC_EINVAL;
+  if (!std::isfinite(p->bandwidth) || !(p->bandwidth > 0.0)) return ARPC_EINVAL;
+  if (p->max_rounds < 0) return ARPC_EINVAL;
+  return ARPC_OK;
+}
+
+KParams kparams_of(const arpc_problem& p) {
+  KParams kp{};
+  kp.kernel = p.kernel;
+  kp.sigma = p.bandwidth;
+  if (p.kernel == ARPC_GAUSSIAN) kp.c0 = 1.0 / (2.0 * p.bandwidth * p.bandwidth);
+  else if (p.kernel == ARPC_MATERN52) kp.c0 = 5.0 / (3.0 * p.bandwidth * p.bandwidth);
+  return kp;
+}
+
+// Per-kernel-class timing with HIP events on the launch stream.
+struct Profiler {
+  hipStream_t s;
+  bool on;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
+  size_t used = 0;
+  double ms[ARPC_NUM_KC] = {0};
+  int64_t n[ARPC_NUM_KC] = {0};
+  Profiler(hipStream_t st, bool enable) : s(st), on(enable) {}
+  ~Profiler() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int cls) {
+    if (!on) return;
+    marks.push_back({cls, used});
+    (void)hipEventRecord(next(), s);
+  }
+  void end() {
+    if (!on) return;
+    (void)hipEventRecord(next(), s);
+  }
+  // called after a stream synchronisation
+  void collect() {
+    if (!on) return;
+    for (auto& m : marks) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]) == hipSuccess) {
+        ms[m.first] += t;
+        n[m.first] += 1;
+      }
+    }
+    marks.clear();
+    used = 0;
+  }
+};
+
+template <typename T>
+void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, const Unif& un, char* ws,
+                   const Layout& l, const double* X, T* F, int64_t* pivots, Profiler& prof) {
+  const int b = (int)p.b, d = (int)p.d;
+  const int64_t N = p.N, k = p.k, nch = nchunks_of(N);
+  RoundState* st = (RoundState*)(ws + l.st);
+  double* u = (double*)(ws + l.u);
+  double* csum = (double*)(ws + l.csum);
+  double* cpre = (double*)(ws + l.cpre);
+  int64_t* props = (int64_t*)(ws + l.props);
+  int32_t* acc = (int32_t*)(ws + l.acc);
+  int32_t* hist = (int32_t*)(ws + l.hist);
+  double* Fs = (double*)(ws + l.Fs);
+  double* H = (double*)(ws + l.H);
+  double* L = (double*)(ws + l.L);
+  double* Xp = (double*)(ws + l.Xp);
+  T* Bt = (T*)(ws + l.Bt);
+  T* Bt2 = (T*)(ws + l.Bt2);
+  T* C = (T*)(ws + l.C);
+  double* P = (double*)(ws + l.P);
+
+  prof.begin(ARPC_KC_PROPOSE);
+  launch_propose(s, u, csum, cpre, nch, N, b, un, st, props);
+  prof.end();
+  prof.begin(ARPC_KC_GATHER);
+  launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, H, st);
+  prof.end();
+  prof.begin(ARPC_KC_REJECT);
+  launch_reject(s, H, b, props, un, st, L, acc, pivots, u, k);
+  prof.end();
+  prof.begin(ARPC_KC_PREP);
+  launch_prep<T>(s, Fs, k, acc, props, X, d, Bt, b, Xp, L, b, Bt2, k, st);
+  prof.end();
+  prof.begin(ARPC_KC_COLGEMM);
+  launch_colgemm<T>(s, F, N, Bt, b, X, d, Xp, kp, C, b, st);
+  prof.end();
+  prof.begin(ARPC_KC_TRSM);
+  launch_trsm<T>(s, C, N, Bt2, b, F, P, st);
+  prof.end();
+  prof.begin(ARPC_KC_DIAG);
+  launch_diag(s, u, csum, P, (int)((b + 63) / 64), N, nch, st);
+  prof.end();
+  prof.begin(ARPC_KC_FINISH);
+  launch_finish(s, st, b, k, p.max_rounds, hist);
+  prof.end();
+}
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) return ARPC_EDEVICE; \
+  } while (0)
+
+template <typename T>
+arpc_status run(const arpc_problem& p, const double* X, T* F, int64_t* pivots, char* ws, const Layout& l,
+                hipStream_t s, const Unif& un, arpc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const KParams kp = kparams_of(p);
+  const int64_t N = p.N, nch = nchunks_of(N);
+  RoundState* st = (RoundState*)(ws + l.st);
+  Profiler prof(s, g_profiling != 0);
+
+  HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
+  prof.begin(ARPC_KC_INIT);
+  launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, N, (int)p.d, kp, st, nch);
+  prof.end();
+  HIPCHK(hipGetLastError());
+
+  RoundState h{};
+  int64_t known_k = 0, enqueued = 0;
+  for (;;) {
+    // the fewest rounds that could still be needed (every round accepts <= b)
+    int64_t batch = (p.k - known_k + p.b - 1) / p.b;
+    if (batch < 1) batch = 1;
+    if (p.max_rounds > 0 && enqueued + batch > p.max_rounds) batch = p.max_rounds - enqueued;
+    if (batch < 1) batch = 1;
+    for (int64_t r = 0; r < batch; ++r) enqueue_round<T>(s, p, kp, un, ws, l, X, F, pivots, prof);
+    enqueued += batch;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&h, st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    prof.collect();
+    if (h.status != ST_RUNNING) break;
+    known_k = h.k_r;
+  }
+  if (h.nonfinite) return ARPC_ENUMERIC;
+
+  // final residual trace and round history
+  double* tr = (double*)(ws + l.trace);
+  launch_trace(s, (double*)(ws + l.csum), nch, tr);
+  double trace_resid = 0.0;
+  HIPCHK(hipMemcpyAsync(&trace_resid, tr, sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> hist((size_t)h.round + 1, 0);
+  if (h.round > 0)
+    HIPCHK(hipMemcpyAsync(hist.data(), ws + l.hist, sizeof(int32_t) * h.round, hipMemcpyDeviceToHost, s));
+  const int64_t k_out = h.k_r;
+  if (k_out < p.k) {
+    HIPCHK(hipMemsetAsync(F + k_out * N, 0, sizeof(T) * (size_t)(p.k - k_out) * N, s));
+    HIPCHK(hipMemsetAsync(pivots + k_out, 0xff, sizeof(int64_t) * (size_t)(p.k - k_out), s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+
+  arpc_status ret = (k_out == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE))
+                        ? ARPC_OK
+                        : ARPC_EARLY_STOP;
+  if (h.status == ST_NOUNIF) ret = ARPC_EINVAL;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->k_out = k_out;
+    stats->rounds = h.round;
+    stats->proposals = h.proposals;
+    stats->status = (ret == ARPC_EINVAL) ? ARPC_EINVAL : ret;
+    stats->trace_A = h.trace_A;
+    stats->trace_resid = trace_resid;
+    double kr = 0.0, fg = 0.0, ft = 0.0;
+    for (int64_t r = 0; r < h.round; ++r) {
+      const double sr = hist[r];
+      fg += 2.0 * (double)N * kr * sr;
+      ft += (double)N * sr * sr;
+      kr += sr;
+    }
+    stats->flops_colgemm = fg;
+    stats->flops_trsm = ft;
+    for (int c = 0; c < ARPC_NUM_KC; ++c) {
+      stats->ms_kernel[c] = prof.ms[c];
+      stats->launches[c] = prof.n[c];
+    }
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return ret;
+}
+
+arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t* pivots, void* ws,
+                        size_t ws_bytes, void* stream, const Unif& un, arpc_stats* stats) {
+  arpc_status v = validate(p);
+  if (v != ARPC_OK) return v;
+  if (!X || !F || !pivots || !ws) return ARPC_EINVAL;
+  if (((uintptr_t)X & 7) || ((uintptr_t)F & 7) || ((uintptr_t)pivots & 7) || ((uintptr_t)ws & 255))
+    return ARPC_EINVAL;
+  const Layout l = layout_of(*p);
+  if (ws_bytes < l.total) return ARPC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (p->prec == ARPC_FP64)
+    return run<double>(*p, X, (double*)F, pivots, (char*)ws, l, s, un, stats);
+  if (p->prec == ARPC_FP32)
+    return run<float>(*p, X, (float*)F, pivots, (char*)ws, l, s, un, stats);
+  return ARPC_EINVAL;  // BF16 modes are provided by the matrix-core path
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* arpc_status_str(int status) {
+  switch (status) {
+    case ARPC_OK: return "ok";
+    case ARPC_EARLY_STOP: return "early stop: residual reached zero before k pivots";
+    case ARPC_EINVAL: return "invalid argument";
+    case ARPC_ENOMEM: return "out of memory";
+    case ARPC_EBUSY: return "busy";
+    case ARPC_EDEVICE: return "HIP runtime error";
+    case ARPC_ENUMERIC: return "non-finite input";
+    case ARPC_ECANCELED: return "cancelled";
+    default: return "unknown status";
+  }
+}
+
+const char* arpc_version(void) { return "arpc-gfx950 0.1"; }
+
+arpc_status arpc_workspace_size(const arpc_problem* problem, size_t* bytes) {
+  if (!bytes) return ARPC_EINVAL;
+  arpc_status v = validate(problem);
+  if (v != ARPC_OK) return v;
+  *bytes = layout_of(*problem).total;
+  return ARPC_OK;
+}
+
+arpc_status arpc_factor(const arpc_problem* problem, const double* X, void* F, int64_t* pivots, void* ws,
+                        size_t ws_bytes, void* stream, arpc_stats* stats) {
+  if (!problem) return ARPC_EINVAL;
+  Unif un{nullptr, 0, problem->seed};
+  return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats);
+}
+
+arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, void* F, int64_t* pivots,
+                                 void* ws, size_t ws_bytes, void* stream, const double* U, int64_t nU,
+                                 arpc_stats* stats) {
+  if (!problem || !U || nU < 0 || ((uintptr_t)U & 7)) return ARPC_EINVAL;
+  Unif un{U, nU, problem->seed};
+  return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats);
+}
+
+arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out) {
+  if (start < 0 || n < 0 || (n > 0 && !out)) return ARPC_EINVAL;
+  for (int64_t i = 0; i < n; ++i) out[i] = philox_uniform(seed, (uint64_t)(start + i));
+  return ARPC_OK;
+}
+
+void arpc_set_profiling(int on) { g_profiling = on; }
+
+}  // extern "C"

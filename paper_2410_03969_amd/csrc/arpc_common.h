@@ -1,0 +1,110 @@
+// Internal definitions shared by the kernels and the host driver of the
+// accelerated RPCholesky library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace arpc {
+
+// Rows per residual-diagonal chunk.  The diagonal-update kernel writes one
+// partial sum per chunk; the proposal kernel scans the chunk sums and then the
+// elements of a single chunk per draw.
+constexpr int CHUNK = 1024;
+// Largest block size whose b x b residual submatrix (lower triangle, FP64)
+// fits the 160 KiB of LDS of one gfx950 workgroup: 200*201/2*8 = 160800 bytes.
+constexpr int REJECT_LDS_BMAX = 200;
+constexpr int BMAX = 1024;
+
+enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_EARLY = 2, ST_NOUNIF = 3 };
+
+// Device-resident round state; every round kernel reads it so that the host
+// never has to synchronise inside a round.
+struct RoundState {
+  int64_t k_r;        // pivots held at the start of the current round
+  int64_t round;      // rounds completed
+  int64_t proposals;  // proposals consumed
+  int32_t s_r;        // pivots accepted in the current round
+  int32_t status;     // ST_*
+  double T;           // residual trace at the start of the current round
+  double trace_A;     // sum of diag A
+  int32_t nonfinite;  // set if a point has a NaN/Inf coordinate
+  int32_t lastpos;    // last chunk with a positive sum (proposal rounding fallback)
+};
+
+// Source of the uniform stream: explicit array (U != nullptr) or Philox keyed by seed.
+struct Unif {
+  const double* U;
+  int64_t nU;
+  uint64_t seed;
+};
+
+struct KParams {
+  int kernel;
+  double sigma;
+  double c0;  // kernel-specific constant (see kappa_r2)
+};
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+  return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) >> 64);
+}
+
+// Philox4x64 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11), counter
+// (q+1, 0, 0, 0) for block q, key (seed, 0); returns word p = 4q + (p mod 4).
+__host__ __device__ inline uint64_t philox_word(uint64_t seed, uint64_t p) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = (p >> 2) + 1, x1 = 0, x2 = 0, x3 = 0;
+  uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = mulhi64(M0, x0), lo0 = M0 * x0;
+    const uint64_t hi1 = mulhi64(M1, x2), lo1 = M1 * x2;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  const uint64_t w[4] = {x0, x1, x2, x3};
+  return w[p & 3];
+}
+
+__host__ __device__ inline double philox_uniform(uint64_t seed, uint64_t p) {
+  return (double)(philox_word(seed, p) >> 11) * 0x1.0p-53;
+}
+
+__device__ inline double stream_uniform(const Unif& un, int64_t p) {
+  if (un.U) return un.U[p];
+  return philox_uniform(un.seed, (uint64_t)p);
+}
+
+// Kernel value from the squared distance, in FP64 (Section 1.2 Gaussian;
+// Laplace with the l2 distance; Matern-3/2; Matern-5/2 of Section 3.2).
+__device__ inline double kappa_r2(double r2, const KParams& kp) {
+  switch (kp.kernel) {
+    case 0: return exp(-r2 * kp.c0);                 // c0 = 1/(2 sigma^2)
+    case 1: return exp(-sqrt(r2) / kp.sigma);
+    case 2: {
+      const double t = 1.7320508075688772 * sqrt(r2) / kp.sigma;
+      return (1.0 + t) * exp(-t);
+    }
+    default: {
+      const double t = 2.23606797749979 * sqrt(r2) / kp.sigma;
+      return (1.0 + t + r2 * kp.c0) * exp(-t);       // c0 = 5/(3 sigma^2)
+    }
+  }
+}
+
+// Squared distance by direct differences (a point paired with itself gives 0).
+__device__ inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
+  double s = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const double e = x[t] - y[t];
+    s += e * e;
+  }
+  return s;
+}
+
+}  // namespace arpc

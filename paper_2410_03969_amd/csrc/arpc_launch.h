@@ -1,0 +1,38 @@
+// Host-side launchers of the library's kernels (internal).
+#pragma once
+
+#include "arpc_common.h"
+
+namespace arpc {
+
+void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_t N, int d, KParams kp,
+                 RoundState* st, int64_t nchunks);
+void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
+                    int64_t N, int b, Unif un, RoundState* st, int64_t* props);
+template <typename T>
+void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
+                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* H,
+                   const RoundState* st);
+void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
+                   double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax);
+template <typename T>
+void launch_prep(hipStream_t s, const double* Fs, int64_t ldf, const int32_t* acc, const int64_t* props,
+                 const double* X, int d, T* Bt, int ldb, double* Xp, const double* L, int b, T* Bt2,
+                 int64_t kmax, const RoundState* st);
+void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int nparts, int64_t N,
+                 int64_t nchunks, const RoundState* st);
+void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist);
+void launch_trace(hipStream_t s, const double* csum, int64_t nchunks, double* out);
+
+// Update GEMM (Alg. 2 step 3, first factor): C = A(:,S_r) - F F(S_r,:)^T,
+// kernel columns evaluated from the points in the epilogue.
+template <typename T>
+void launch_colgemm(hipStream_t s, const T* F, int64_t N, const T* Bt, int ldb, const double* X, int d,
+                    const double* Xp, KParams kp, T* C, int b, const RoundState* st);
+// Triangular solve as a product with the explicit inverse: G = C Linv^T,
+// written into F(:, k_r : k_r + s_r), with FP64 partial row norms of G as stored.
+template <typename T>
+void launch_trsm(hipStream_t s, const T* C, int64_t N, const T* Bt2, int b, T* F, double* P,
+                 const RoundState* st);
+
+}  // namespace arpc

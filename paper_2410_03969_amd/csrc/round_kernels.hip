@@ -1,0 +1,519 @@
+// Round kernels of accelerated RPCholesky (Alg. 2, Section 2.3) other than the
+// two N-sized GEMMs: residual-diagonal set-up and update, proposal draws,
+// gathers at the proposals, the b x b residual submatrix, RejectionSample-
+// Submatrix (Alg. 1, Section 2.2) in one workgroup, the triangular inverse and
+// the end-of-round bookkeeping.  Every kernel reads the device-resident
+// RoundState and returns at once when the run has stopped, so the host can
+// enqueue rounds without synchronising.
+#include "arpc_common.h"
+#include "arpc_launch.h"
+
+namespace arpc {
+
+// ----------------------------------------------------------------- reductions
+// Deterministic block sum (fixed tree order) of one double per thread.
+template <int NT>
+__device__ inline double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Inclusive prefix sum across a 64-wide wavefront (fixed order).
+__device__ inline double wave_incl_scan(double v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// -------------------------------------------------------------- initialisation
+// u = diag A = kappa(0) (Alg. 2, initialisation), per-chunk sums of u, and a
+// scan of X for non-finite coordinates.
+__global__ __launch_bounds__(CHUNK) void k_init(double* __restrict__ u, double* __restrict__ csum,
+                                                const double* __restrict__ X, int64_t N, int d,
+                                                KParams kp, RoundState* st) {
+  __shared__ double sh[CHUNK];
+  const int64_t j = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+  double v = 0.0;
+  if (j < N) {
+    v = kappa_r2(0.0, kp);
+    u[j] = v;
+    bool bad = false;
+    for (int t = 0; t < d; ++t) bad |= !isfinite(X[j * d + t]);
+    if (bad) atomicOr(&st->nonfinite, 1);
+  }
+  const double s = block_sum<CHUNK>(v, sh);
+  if (threadIdx.x == 0) csum[blockIdx.x] = s;
+}
+
+// trace(A) from the chunk sums, and the initial round state.
+__global__ __launch_bounds__(1024) void k_init_state(const double* __restrict__ csum, int64_t nchunks,
+                                                     RoundState* st) {
+  __shared__ double sh[1024];
+  double v = 0.0;
+  for (int64_t c = threadIdx.x; c < nchunks; c += 1024) v += csum[c];
+  const double t = block_sum<1024>(v, sh);
+  if (threadIdx.x == 0) {
+    st->trace_A = t;
+    st->T = t;
+    st->k_r = 0;
+    st->round = 0;
+    st->proposals = 0;
+    st->s_r = 0;
+    st->status = st->nonfinite ? ST_EARLY : ST_RUNNING;
+  }
+}
+
+// ------------------------------------------------------------------- proposals
+// Inclusive prefix of the chunk sums in a fixed order (one workgroup), the
+// residual trace T = sum(u) as its last value, and the early stop when T <= 0.
+__global__ __launch_bounds__(1024) void k_scan_chunks(const double* __restrict__ csum, int64_t nchunks,
+                                                      double* __restrict__ cpre, int b, Unif un,
+                                                      RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  __shared__ double wsum[16];
+  __shared__ int64_t lastpos_sh[1024];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (un.U && 2 * (int64_t)b * (st->round + 1) > un.nU) {
+    __syncthreads();
+    if (tid == 0) st->status = ST_NOUNIF;
+    return;
+  }
+  double base = 0.0;
+  int64_t lastpos = -1;
+  for (int64_t c0 = 0; c0 < nchunks; c0 += 1024) {
+    const int64_t c = c0 + tid;
+    const double v = (c < nchunks) ? csum[c] : 0.0;
+    const double incl = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    double woff = 0.0, tot = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      if (q < w) woff += wsum[q];
+      tot += wsum[q];
+    }
+    if (c < nchunks) {
+      cpre[c] = base + (woff + incl);
+      if (v > 0.0) lastpos = c;
+    }
+    base += tot;
+    __syncthreads();
+  }
+  lastpos_sh[tid] = lastpos;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s && lastpos_sh[tid + s] > lastpos_sh[tid]) lastpos_sh[tid] = lastpos_sh[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    // base equals cpre[nchunks-1]: the segment totals were added in the same order
+    st->T = base;
+    st->lastpos = (int32_t)lastpos_sh[0];
+    if (!(base > 0.0) || lastpos_sh[0] < 0) st->status = ST_EARLY;
+  }
+}
+
+// Alg. 2 step 1: b i.i.d. draws from u / sum(u).  Draw l (uniform word
+// 2br + l) is the smallest j whose running sum exceeds U_l * T: a binary
+// search over the chunk prefix, then a wavefront scan inside the chunk.  An
+// index with u_j = 0 is never drawn; if rounding leaves no crossing, the last
+// index with u_j > 0 (in the last positive chunk) is taken.
+constexpr int PROPOSE_WAVES = 4;
+
+__global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(
+    const double* __restrict__ u, const double* __restrict__ cpre, int64_t nchunks, int64_t N,
+    int b, Unif un, const RoundState* st, int64_t* __restrict__ props) {
+  if (st->status != ST_RUNNING) return;
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * PROPOSE_WAVES + (threadIdx.x >> 6);
+  if (l >= b) return;
+  const double T = st->T;
+  const double x = stream_uniform(un, 2 * (int64_t)b * st->round + l) * T;
+  // first chunk whose inclusive prefix exceeds x
+  int64_t lo = 0, hi = nchunks;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (cpre[mid] > x) hi = mid; else lo = mid + 1;
+  }
+  const int64_t c = (lo < nchunks) ? lo : (int64_t)st->lastpos;
+  const double base = (c > 0) ? cpre[c - 1] : 0.0;
+  // lane l owns elements [16 lane, 16 lane + 16) of the chunk
+  const int64_t e0 = c * CHUNK + 16 * lane;
+  double v[16];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    v[i] = (e0 + i < N) ? u[e0 + i] : 0.0;
+    s += v[i];
+  }
+  const double incl = wave_incl_scan(s);
+  double excl = __shfl_up(incl, 1, 64);
+  if (lane == 0) excl = 0.0;
+  double run = base + excl;
+  int hit = -1, lastp = -1;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    run += v[i];
+    if (hit < 0 && v[i] > 0.0 && run > x) hit = i;
+    if (v[i] > 0.0) lastp = i;
+  }
+  const uint64_t hits = __ballot(hit >= 0);
+  int64_t pick;
+  if (hits) {
+    const int fl = __ffsll((unsigned long long)hits) - 1;
+    const int hi_ = __shfl(hit, fl, 64);
+    pick = c * CHUNK + 16 * fl + hi_;
+  } else {
+    const uint64_t pos = __ballot(lastp >= 0);
+    if (pos) {
+      const int ll = 63 - __clzll((unsigned long long)pos);
+      const int li = __shfl(lastp, ll, 64);
+      pick = c * CHUNK + 16 * ll + li;
+    } else {
+      pick = c * CHUNK;  // unreachable for a chunk with a positive sum; keeps the index valid
+    }
+  }
+  pick = pick < 0 ? 0 : (pick >= N ? N - 1 : pick);
+  if (lane == 0) props[l] = pick;
+}
+
+// ------------------------------------------------------- gathers at proposals
+// Fs(i, c) = F(props_i, c) in FP64, row-major with leading dimension ldf.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ F, int64_t N,
+                                                     const int64_t* __restrict__ props,
+                                                     double* __restrict__ Fs, int64_t ldf,
+                                                     const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int64_t kr = st->k_r;
+  const int i = blockIdx.y;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= kr) return;
+  Fs[(int64_t)i * ldf + c] = (double)F[c * N + props[i]];
+}
+
+// H = A(S',S') - F(S',:) F(S',:)^T (Alg. 2 step 2), FP64, column-major b x b
+// (ld = b).  One 16 x 16 tile per workgroup; F rows staged through LDS.
+__global__ __launch_bounds__(256) void k_gather_H(const double* __restrict__ X, int d, KParams kp,
+                                                  const int64_t* __restrict__ props, int b,
+                                                  const double* __restrict__ Fs, int64_t ldf,
+                                                  double* __restrict__ H, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int64_t kr = st->k_r;
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int i = i0 + ty, j = j0 + tx;
+  double acc = 0.0;
+  for (int64_t c0 = 0; c0 < kr; c0 += 64) {
+    for (int q = threadIdx.x; q < 16 * 64; q += 256) {
+      const int r = q >> 6, cc = q & 63;
+      const int64_t c = c0 + cc;
+      As[r][cc] = (i0 + r < b && c < kr) ? Fs[(int64_t)(i0 + r) * ldf + c] : 0.0;
+      Bs[r][cc] = (j0 + r < b && c < kr) ? Fs[(int64_t)(j0 + r) * ldf + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int cc = 0; cc < 64; ++cc) acc += As[ty][cc] * Bs[tx][cc];
+    __syncthreads();
+  }
+  if (i < b && j < b) {
+    const double* xi = X + props[i] * d;
+    const double* xj = X + props[j] * d;
+    H[(int64_t)j * b + i] = kappa_r2(sqdist(xi, xj, d), kp) - acc;
+  }
+}
+
+// ------------------------------------------------- RejectionSampleSubmatrix
+// Alg. 1 on the b x b residual submatrix, in one workgroup, right-looking and
+// in place: accepted column i is scaled by 1/sqrt(h_ii) and the trailing
+// lower triangle receives the rank-one Schur update.  Storage: the lower
+// triangle packed by columns in LDS (b <= REJECT_LDS_BMAX) or the full
+// column-major matrix in global memory.
+// Rules beyond the printed test u_i * V < h_ii: a proposal equal to one
+// already accepted in this round is rejected, and at most k - k_r proposals are
+// accepted.  Outputs: accepted local indices, the dense lower Cholesky factor
+// L of H(T,T) (column-major, ld b), the new pivots, u = 0 at the new pivots.
+struct PackedLDS {
+  double* p;
+  int b;
+  __device__ inline double& at(int j, int i) const {  // j >= i
+    return p[(int64_t)i * b - ((int64_t)i * (i - 1)) / 2 + (j - i)];
+  }
+};
+struct FullGlobal {
+  double* p;
+  int b;
+  __device__ inline double& at(int j, int i) const { return p[(int64_t)i * b + j]; }
+};
+
+template <class Store>
+__device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, Unif un,
+                            RoundState* st, double* __restrict__ Lout, int32_t* __restrict__ acc_out,
+                            int64_t* __restrict__ pivots, double* __restrict__ u, int64_t kmax,
+                            unsigned char* tk, int* dec, short* accl) {
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int64_t kr = st->k_r;
+  const int64_t round = st->round;
+  const int cap = (int)((kmax - kr) < b ? (kmax - kr) : b);
+  double uloc = 0.0, V = 0.0;
+  int prev = -1;
+  if (tid < b) {
+    uloc = S.at(tid, tid);
+    V = stream_uniform(un, 2 * (int64_t)b * round + b + tid);
+    const int64_t me = props[tid];
+    for (int q = tid - 1; q >= 0; --q)
+      if (props[q] == me) { prev = q; break; }
+    tk[tid] = 0;
+  }
+  __syncthreads();
+  int nacc = 0;
+  for (int i = 0; i < b && nacc < cap; ++i) {
+    if (tid == i) {
+      const double h = S.at(i, i);
+      const bool dup = prev >= 0 && tk[prev];
+      const bool a = !dup && (uloc * V < h);
+      tk[i] = (a || dup) ? 1 : 0;
+      dec[i & 1] = a ? 1 : 0;
+      if (a) accl[nacc] = (short)i;
+    }
+    __syncthreads();
+    if (!dec[i & 1]) continue;
+    const double sq = sqrt(S.at(i, i));
+    for (int j = i + tid; j < b; j += nthr) S.at(j, i) = S.at(j, i) / sq;
+    __syncthreads();
+    for (int l = i + 1 + w; l < b; l += nw) {
+      const double Ll = S.at(l, i);
+      for (int j = l + lane; j < b; j += 64) S.at(j, l) -= S.at(j, i) * Ll;
+    }
+    __syncthreads();
+    ++nacc;
+  }
+  __syncthreads();
+  // L = L(T,T), dense column-major
+  for (int q = tid; q < nacc * nacc; q += nthr) {
+    const int a = q % nacc, c = q / nacc;  // row a, column c
+    Lout[(int64_t)c * b + a] = (a >= c) ? S.at(accl[a], accl[c]) : 0.0;
+  }
+  for (int a = tid; a < nacc; a += nthr) {
+    const int64_t p = props[accl[a]];
+    acc_out[a] = accl[a];
+    pivots[kr + a] = p;
+    u[p] = 0.0;
+  }
+  if (tid == 0) st->s_r = nacc;
+}
+
+__global__ __launch_bounds__(1024) void k_reject_lds(const double* __restrict__ H, int b,
+                                                     const int64_t* __restrict__ props, Unif un,
+                                                     RoundState* st, double* __restrict__ Lout,
+                                                     int32_t* __restrict__ acc_out,
+                                                     int64_t* __restrict__ pivots, double* __restrict__ u,
+                                                     int64_t kmax) {
+  if (st->status != ST_RUNNING) return;
+  __shared__ double Hp[REJECT_LDS_BMAX * (REJECT_LDS_BMAX + 1) / 2];
+  __shared__ unsigned char tk[REJECT_LDS_BMAX];
+  __shared__ short accl[REJECT_LDS_BMAX];
+  __shared__ int dec[2];
+  PackedLDS S{Hp, b};
+  for (int i = 0; i < b; ++i)
+    for (int j = i + threadIdx.x; j < b; j += blockDim.x) S.at(j, i) = H[(int64_t)i * b + j];
+  __syncthreads();
+  reject_body(S, b, props, un, st, Lout, acc_out, pivots, u, kmax, tk, dec, accl);
+}
+
+__global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, int b,
+                                                        const int64_t* __restrict__ props, Unif un,
+                                                        RoundState* st, double* __restrict__ Lout,
+                                                        int32_t* __restrict__ acc_out,
+                                                        int64_t* __restrict__ pivots,
+                                                        double* __restrict__ u, int64_t kmax) {
+  if (st->status != ST_RUNNING) return;
+  __shared__ unsigned char tk[BMAX];
+  __shared__ short accl[BMAX];
+  __shared__ int dec[2];
+  FullGlobal S{H, b};
+  reject_body(S, b, props, un, st, Lout, acc_out, pivots, u, kmax, tk, dec, accl);
+}
+
+// --------------------------------------------------------- update preparation
+// B operand of the update GEMM, Bt(c, j) = F(S_r(j), c) in the GEMM type
+// (row-major, ld = ldb), and the accepted points Xp (s_r x d).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep(const double* __restrict__ Fs, int64_t ldf,
+                                              const int32_t* __restrict__ acc, const int64_t* __restrict__ props,
+                                              const double* __restrict__ X, int d,
+                                              T* __restrict__ Bt, int ldb, double* __restrict__ Xp,
+                                              const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int64_t kr = st->k_r;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < kr)
+    for (int j = 0; j < s; ++j) Bt[c * ldb + j] = (T)Fs[(int64_t)acc[j] * ldf + c];
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < s * d; q += 256) {
+      const int j = q / d, t = q % d;
+      Xp[q] = X[props[acc[j]] * d + t];
+    }
+}
+
+// Inverse of the s x s lower factor L (column-major, ld b), one column per
+// workgroup by forward substitution with wavefront dot products.  Writes
+// Bt2(t, c) = Linv(c, t) in the GEMM type (row-major, ld b): the B operand of
+// the triangular-solve product G = C Linv^T.
+template <typename T>
+__global__ __launch_bounds__(64) void k_trinv(const double* __restrict__ L, int b, T* __restrict__ Bt2,
+                                              const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int c = blockIdx.x;
+  if (c >= s) return;
+  __shared__ double x[BMAX];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < s; i += 64) x[i] = 0.0;
+  __syncthreads();
+  if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
+  __syncthreads();
+  for (int i = c + 1; i < s; ++i) {
+    double p = 0.0;
+    for (int t = c + lane; t < i; t += 64) p += L[(int64_t)t * b + i] * x[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+    if (lane == 0) x[i] = -p / L[(int64_t)i * b + i];
+    __syncthreads();
+  }
+  // row c of Bt2 holds column c of Linv: Bt2(c, i) = Linv(i, c), zero for i < c
+  for (int t = lane; t < s; t += 64) Bt2[(int64_t)c * b + t] = (t >= c) ? (T)x[t] : (T)0;
+}
+
+// ------------------------------------------------------------ diagonal update
+// u <- max(u - rowsqnorm(G), 0) (Alg. 2 step 3) from the per-column-block
+// partial row norms P (nparts x N, FP64, summed in a fixed order), and the
+// new chunk sums.
+__global__ __launch_bounds__(CHUNK) void k_diag(double* __restrict__ u, double* __restrict__ csum,
+                                                const double* __restrict__ P, int nparts, int64_t N,
+                                                const RoundState* st) {
+  if (st->status != ST_RUNNING || st->s_r == 0) return;
+  __shared__ double sh[CHUNK];
+  const int s = st->s_r;
+  const int np = (s + 63) / 64 < nparts ? (s + 63) / 64 : nparts;
+  const int64_t j = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+  double v = 0.0;
+  if (j < N) {
+    double g2 = 0.0;
+    for (int q = 0; q < np; ++q) g2 += P[(int64_t)q * N + j];
+    v = fmax(u[j] - g2, 0.0);
+    u[j] = v;
+  }
+  const double t = block_sum<CHUNK>(v, sh);
+  if (threadIdx.x == 0) csum[blockIdx.x] = t;
+}
+
+// End of round: k_r += s_r, round counters, stop conditions (k reached, an
+// empty round, the round limit).
+__global__ void k_finish(RoundState* st, int b, int64_t kmax, int64_t max_rounds,
+                         int32_t* __restrict__ hist) {
+  if (threadIdx.x != 0 || st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  hist[st->round] = s;
+  st->k_r += s;
+  st->round += 1;
+  st->proposals += b;
+  if (s == 0) st->status = ST_EARLY;
+  else if (st->k_r >= kmax) st->status = ST_DONE;
+  else if (max_rounds > 0 && st->round >= max_rounds) st->status = ST_DONE;
+}
+
+// Residual trace sum(u) from the chunk sums (end of run).
+__global__ __launch_bounds__(1024) void k_trace(const double* __restrict__ csum, int64_t nchunks,
+                                                double* __restrict__ out) {
+  __shared__ double sh[1024];
+  double v = 0.0;
+  for (int64_t c = threadIdx.x; c < nchunks; c += 1024) v += csum[c];
+  const double t = block_sum<1024>(v, sh);
+  if (threadIdx.x == 0) *out = t;
+}
+
+// ------------------------------------------------------------------ launchers
+void launch_trace(hipStream_t s, const double* csum, int64_t nchunks, double* out) {
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(1024), 0, s, csum, nchunks, out);
+}
+
+void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_t N, int d, KParams kp,
+                 RoundState* st, int64_t nchunks) {
+  hipLaunchKernelGGL(k_init, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, csum, X, N, d, kp, st);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, csum, nchunks, st);
+}
+
+void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
+                    int64_t N, int b, Unif un, RoundState* st, int64_t* props) {
+  hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, csum, nchunks, cpre, b, un, st);
+  hipLaunchKernelGGL(k_propose, dim3((b + PROPOSE_WAVES - 1) / PROPOSE_WAVES), dim3(64 * PROPOSE_WAVES), 0,
+                     s, u, cpre, nchunks, N, b, un, st, props);
+}
+
+template <typename T>
+void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
+                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* H,
+                   const RoundState* st) {
+  if (kmax > 0)
+    hipLaunchKernelGGL(k_gather_rows<T>, dim3((unsigned)((kmax + 255) / 256), b), dim3(256), 0, s, F, N,
+                       props, Fs, ldf, st);
+  const unsigned nb = (unsigned)((b + 15) / 16);
+  hipLaunchKernelGGL(k_gather_H, dim3(nb, nb), dim3(256), 0, s, X, d, kp, props, b, Fs, ldf, H, st);
+}
+template void launch_gather<double>(hipStream_t, const double*, int64_t, const double*, int, KParams,
+                                    const int64_t*, int, double*, int64_t, int64_t, double*,
+                                    const RoundState*);
+template void launch_gather<float>(hipStream_t, const float*, int64_t, const double*, int, KParams,
+                                   const int64_t*, int, double*, int64_t, int64_t, double*,
+                                   const RoundState*);
+
+void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
+                   double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
+  if (b <= REJECT_LDS_BMAX)
+    hipLaunchKernelGGL(k_reject_lds, dim3(1), dim3(1024), 0, s, H, b, props, un, st, L, acc, pivots, u, kmax);
+  else
+    hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, L, acc, pivots, u,
+                       kmax);
+}
+
+template <typename T>
+void launch_prep(hipStream_t s, const double* Fs, int64_t ldf, const int32_t* acc, const int64_t* props,
+                 const double* X, int d, T* Bt, int ldb, double* Xp, const double* L, int b, T* Bt2,
+                 int64_t kmax, const RoundState* st) {
+  hipLaunchKernelGGL(k_prep<T>, dim3((unsigned)((kmax + 255) / 256)), dim3(256), 0, s, Fs, ldf, acc, props, X,
+                     d, Bt, ldb, Xp, st);
+  hipLaunchKernelGGL(k_trinv<T>, dim3(b), dim3(64), 0, s, L, b, Bt2, st);
+}
+template void launch_prep<double>(hipStream_t, const double*, int64_t, const int32_t*, const int64_t*,
+                                  const double*, int, double*, int, double*, const double*, int, double*,
+                                  int64_t, const RoundState*);
+template void launch_prep<float>(hipStream_t, const double*, int64_t, const int32_t*, const int64_t*,
+                                 const double*, int, float*, int, double*, const double*, int, float*,
+                                 int64_t, const RoundState*);
+
+void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int nparts, int64_t N,
+                 int64_t nchunks, const RoundState* st) {
+  hipLaunchKernelGGL(k_diag, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, csum, P, nparts, N, st);
+}
+
+void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, b, kmax, max_rounds, hist);
+}
+
+}  // namespace arpc

@@ -44,6 +44,7 @@ class Problem:
     sigma: float
     seed: int = 0
     prec: int = FP64
+    max_rounds: int = 0  # 0: run until k pivots are held
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs and the same uniform stream.
+
+Bar: in FP64 mode the pivot sequence is identical and
+|F_gpu - F_oracle|_F / |F_oracle|_F <= 1e-10.  The identity and cluster
+matrices are exact in every precision, so they are compared bit for bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import (PointsAccess, array_stream, factor_from_pivots, philox_stream,
+                    rpc_accel)
+from paper_2410_03969_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FTOL = 1e-10
+
+
+def gpu_factor(X, prob, U=None):
+    from paper_2410_03969_amd import binding
+    print(f"[gpu] N={prob.N} d={prob.d} k={prob.k} b={prob.b} kernel={prob.kernel} "
+          f"prec={prob.prec} seed={prob.seed} max_rounds={prob.max_rounds}",
+          flush=True)
+    sys.stdout.flush()
+    out = binding.factor(X, prob, U=U)
+    k_out = out["stats"]["k_out"]
+    F = out["F"].cpu().numpy()[:, :k_out].astype(np.float64)
+    piv = out["pivots"].cpu().numpy()
+    return F, piv, out
+
+
+def oracle_run(X, prob, max_rounds=None, U=None):
+    stream = philox_stream(prob.seed) if U is None else array_stream(U)
+    return rpc_accel(PointsAccess(X, prob.kernel, prob.sigma), prob.k, prob.b, stream,
+                     max_rounds=max_rounds)
+
+
+def assert_parity(F, piv, out, ref, ftol=FTOL):
+    k = ref.k_out
+    assert out["stats"]["k_out"] == k
+    first_diff = np.flatnonzero(piv[:k] != ref.pivots)
+    assert first_diff.size == 0, f"pivots differ first at {first_diff[:1]}"
+    assert np.all(piv[k:] == -1)
+    err = np.linalg.norm(F - ref.F) / max(np.linalg.norm(ref.F), 1e-300)
+    assert err <= ftol, f"relative F error {err:.3e}"
+    assert out["stats"]["rounds"] == ref.rounds
+    return err
+
+
+def test_small_workload_fp64():
+    X, prob = W.small()
+    F, piv, out = gpu_factor(X, prob)
+    ref = oracle_run(X, prob)
+    err = assert_parity(F, piv, out, ref)
+    st = out["stats"]
+    assert abs(st["trace_A"] - ref.trace_A) < 1e-9
+    assert abs(st["trace_resid"] - np.sum(ref.u)) < 1e-9 * ref.trace_A
+    print(f"relF={err:.2e} rounds={st['rounds']}")
+
+
+def test_block_size_one():
+    rng = np.random.default_rng(1)
+    X = rng.random((1500, 2))
+    prob = W.Problem(N=1500, d=2, k=40, b=1, kernel=W.GAUSSIAN, sigma=0.3, seed=3)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
+@pytest.mark.parametrize("kernel", [W.GAUSSIAN, W.LAPLACE_L2, W.MATERN32, W.MATERN52])
+def test_kernels_ragged_shapes(kernel):
+    """N not a multiple of the 64-row tile nor of the 1024-row chunk, b not a
+    multiple of the 64-column tile."""
+    rng = np.random.default_rng(kernel + 10)
+    X = rng.standard_normal((5003, 5))
+    prob = W.Problem(N=5003, d=5, k=150, b=37, kernel=kernel, sigma=1.5, seed=kernel)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
+def test_large_block_global_rejection_path():
+    """b above the LDS-resident limit runs RejectionSampleSubmatrix on a
+    global-memory matrix."""
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((4000, 6))
+    prob = W.Problem(N=4000, d=6, k=500, b=260, kernel=W.GAUSSIAN, sigma=2.0, seed=5)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
+def test_lds_limit_block_size():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((3000, 4))
+    prob = W.Problem(N=3000, d=4, k=420, b=200, kernel=W.MATERN32, sigma=1.0, seed=9)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
+def simulate_identity(N, k, b, stream):
+    remaining = list(range(N))
+    piv = []
+    r = 0
+    while len(piv) < k and remaining:
+        U = stream(2 * b * r, 2 * b)[:b]
+        T = float(len(remaining))
+        props = [remaining[int(math.floor(x * T))] for x in U]
+        for p in props:
+            if len(piv) < k and p in remaining:
+                piv.append(p)
+                remaining.remove(p)
+        r += 1
+    return piv
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_identity_matrix_exact(prec):
+    """Grid points 64 apart with a unit Gaussian: A = I exactly in any format,
+    so pivots follow sampling without replacement and F is exact."""
+    X = W.grid(5, levels=5)        # 3125 points: ragged against tiles and chunks
+    N = X.shape[0]
+    prob = W.Problem(N=N, d=5, k=700, b=64, kernel=W.GAUSSIAN, sigma=1.0, seed=11, prec=prec)
+    F, piv, out = gpu_factor(X, prob)
+    want = simulate_identity(N, prob.k, prob.b, philox_stream(prob.seed))
+    assert list(piv) == want
+    assert np.array_equal(F, np.eye(N)[:, want])
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_cluster_matrix_exact(prec):
+    sizes = [500, 70, 1300, 1, 220, 9, 3000]
+    X, labels = W.clusters(sizes, d=3, seed=4)
+    prob = W.Problem(N=X.shape[0], d=3, k=30, b=8, kernel=W.GAUSSIAN, sigma=1.0, seed=2, prec=prec)
+    F, piv, out = gpu_factor(X, prob)
+    assert out["status"] == 1 and out["stats"]["k_out"] == len(sizes)
+    ref = oracle_run(X, prob)
+    assert np.array_equal(piv[:len(sizes)], ref.pivots)
+    assert np.all(piv[len(sizes):] == -1)
+    assert np.array_equal(F, ref.F)
+    assert out["stats"]["trace_resid"] == 0.0
+
+
+def test_explicit_uniform_stream_equals_seeded_stream():
+    X, prob = W.small()
+    U = philox_stream(prob.seed)(0, 2 * prob.b * 40)
+    F1, piv1, _ = gpu_factor(X, prob, U=U)
+    F2, piv2, _ = gpu_factor(X, prob)
+    assert np.array_equal(piv1, piv2) and np.array_equal(F1, F2)
+
+
+def test_adversarial_uniforms():
+    """Uniforms at the ends of [0,1): draws at the CDF extremes and acceptance
+    tests with V = 0 (accept every positive residual)."""
+    rng = np.random.default_rng(5)
+    X = rng.random((2500, 3))
+    prob = W.Problem(N=2500, d=3, k=90, b=12, kernel=W.LAPLACE_L2, sigma=0.4, seed=0)
+    U = np.tile(np.concatenate([np.r_[0.0, 1 - 2.0 ** -53, 0.5, 2.0 ** -53], rng.random(8),
+                                np.zeros(12)]), 40)
+    F, piv, out = gpu_factor(X, prob, U=U)
+    assert_parity(F, piv, out, oracle_run(X, prob, U=U))
+
+
+def test_exhausted_uniform_stream_is_an_error():
+    from paper_2410_03969_amd import binding
+    X, prob = W.small()
+    with pytest.raises(RuntimeError):
+        binding.factor(X, prob, U=np.full(2 * prob.b * 2, 0.5))
+
+
+def test_round_limit():
+    X, prob = W.small()
+    prob = prob.with_(k=100, b=7)
+    F, piv, out = gpu_factor(X, prob.with_(max_rounds=3))
+    ref = oracle_run(X, prob, max_rounds=3)
+    assert out["stats"]["rounds"] == 3 and out["status"] == 0
+    assert_parity(F, piv, out, ref)
+
+
+def test_rank_equals_size():
+    X = W.grid(3)
+    prob = W.Problem(N=64, d=3, k=64, b=10, kernel=W.GAUSSIAN, sigma=1.0, seed=1)
+    F, piv, out = gpu_factor(X, prob)
+    assert sorted(piv) == list(range(64)) and out["status"] == 0
+
+
+def test_nonfinite_points_rejected():
+    from paper_2410_03969_amd import binding
+    X, prob = W.small()
+    X = X.copy()
+    X[1234, 1] = np.nan
+    with pytest.raises(RuntimeError, match="non-finite"):
+        binding.factor(X, prob)
+
+
+def test_fp32_mode_factor_consistent_with_its_pivots():
+    """FP32 storage: the factor equals the exact FP64 factor of the pivots it
+    chose, to FP32 accuracy, on sampled rows."""
+    X, prob = W.small()
+    prob = prob.with_(prec=W.FP32)
+    F, piv, out = gpu_factor(X, prob)
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
+    assert len(set(piv.tolist())) == prob.k
+    rows = np.random.default_rng(0).choice(prob.N, 200, replace=False)
+    ref = factor_from_pivots(acc, piv[:40], rows=rows)
+    err = np.linalg.norm(F[rows, :40] - ref) / np.linalg.norm(ref)
+    assert err < 1e-4, err
+
+
+def test_laplace_workload_full_size_fp64():
+    """The N = 1e5, d = 20, k = 1000, b = 120 Laplace workload at full size."""
+    X, prob = W.laplace()
+    F, piv, out = gpu_factor(X, prob)
+    ref = oracle_run(X, prob)
+    err = assert_parity(F, piv, out, ref)
+    print(f"laplace relF={err:.2e} rounds={ref.rounds} trace_err={ref.trace_error:.4e}")
