@@ -1,0 +1,181 @@
+"""Benchmark: accelerated RPCholesky on one MI355X.
+
+One step = one complete factorization (every round of proposals, residual
+submatrix, rejection sampling, update GEMM, triangular solve and diagonal
+update) of the mixture workload: N = 1e6 points in R^8 from a 10-component
+Gaussian mixture, Gaussian kernel sigma = 2, k = 2000, b = 200.  Points are
+resident in HBM before the timed region; F, pivots and workspace are
+allocated once.
+
+Prints one JSON line: pivots/s over the timed steps, the roofline of the
+dominant kernel (the update GEMM) from HIP-event timings taken inside the
+timed region, and the CPU oracle timed on a bounded sample of the same
+workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2410_03969_amd import workloads as W  # noqa: E402
+
+PEAKS = {  # MI355X published dense peaks
+    "hbm_gbs": 8000.0,
+    "fp64_tflops": 78.6, "fp32_tflops": 157.3, "bf16_tflops": 2500.0,
+}
+PREC_BY_NAME = {v: k for k, v in W.PREC_NAMES.items()}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp32", choices=sorted(PREC_BY_NAME))
+    ap.add_argument("--workload", default="mixture", choices=["mixture", "laplace", "small", "sparse_hd"])
+    ap.add_argument("--cpu-rounds", type=int, default=2,
+                    help="rounds of the oracle timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="also run one FP64 factorization and report the trace-error ratio")
+    return ap.parse_args()
+
+
+def gemm_roofline(stats, prec):
+    """Roofline of the update GEMM from the HIP-event kernel times: the
+    algorithmic flops (2 N k_r s_r per round, counted once even where the
+    arithmetic runs as three BF16 products) against the matrix-core peak of the
+    mode, and the algorithmic HBM bytes (F read once, C written, X read) against
+    8 TB/s.  The binding roof (larger fraction) is reported first."""
+    ms = stats["ms_kernel"]["colgemm"]
+    n = stats["launches"]["colgemm"]
+    if ms <= 0 or n == 0:
+        return None, None
+    sec = ms * 1e-3
+    tflops = stats["flops_colgemm"] / sec / 1e12
+    gbs = stats["bytes_colgemm"] / sec / 1e9
+    peak = {W.FP64: PEAKS["fp64_tflops"], W.FP32: PEAKS["fp32_tflops"]}.get(prec, PEAKS["bf16_tflops"])
+    common = {"kernel": "colgemm", "avg_launch_ms": round(ms / n, 4), "launches": n}
+    mf = {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
+          "frac": round(tflops / peak, 4), "traffic": None, **common}
+    hb = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+          "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": None, **common}
+    return (mf, hb) if mf["frac"] >= hb["frac"] else (hb, mf)
+
+
+def cpu_baseline(X, prob, rounds):
+    from oracle import PointsAccess, philox_stream, rpc_accel
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = cores
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(i.get("num_threads", 1)) for i in info)
+    except Exception:
+        pass
+    t = time.perf_counter()
+    r = rpc_accel(PointsAccess(X, prob.kernel, prob.sigma), prob.k, prob.b,
+                  philox_stream(prob.seed), max_rounds=rounds)
+    dt = time.perf_counter() - t
+    return {"value": round(r.k_out / dt, 3), "unit": "pivots/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"first {rounds} rounds of the same workload ({r.k_out} pivots, "
+                      f"{dt:.1f} s; later rounds cost more per pivot)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2410_03969_amd import binding as B
+
+    B.lib()
+    gen = {"mixture": W.mixture, "laplace": W.laplace, "small": W.small,
+           "sparse_hd": W.sparse_hd}[args.workload]
+    X, prob = gen()
+    prec = PREC_BY_NAME[args.prec]
+    prob = prob.with_(prec=prec)
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    pr = B.make_problem(prob)
+    fdt = torch.float64 if prec == W.FP64 else torch.float32
+    Ft = torch.empty((prob.k, prob.N), dtype=fdt, device=dev)
+    piv = torch.empty(prob.k, dtype=torch.int64, device=dev)
+    nbytes = B.arpc_workspace_size(pr)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(profile):
+        B.arpc_set_profiling(profile)
+        st, stats = B.arpc_factor(pr, Xd.data_ptr(), Ft.data_ptr(), piv.data_ptr(), ws.data_ptr(),
+                                  nbytes, stream.cuda_stream)
+        if st < 0:
+            raise RuntimeError(B.arpc_status_str(st))
+        return stats.as_dict()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    B.arpc_set_profiling(False)
+
+    k_out = sum(r["k_out"] for r in runs)
+    last = runs[-1]
+    F = Ft[: last["k_out"]]
+    normF2 = float((F.double() ** 2).sum().item())
+    trace_err = (last["trace_A"] - normF2) / last["trace_A"]
+    # roofline over all timed steps
+    agg = dict(last)
+    agg["ms_kernel"] = {c: sum(r["ms_kernel"][c] for r in runs) for c in B.KERNEL_CLASSES}
+    agg["launches"] = {c: sum(r["launches"][c] for r in runs) for c in B.KERNEL_CLASSES}
+    for key in ("flops_colgemm", "bytes_colgemm", "flops_trsm", "bytes_trsm"):
+        agg[key] = sum(r[key] for r in runs)
+    roof, roof_alt = gemm_roofline(agg, prec)
+
+    out = {
+        "metric": "pivots/s", "value": round(k_out / elapsed, 2), "unit": "pivots/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": W.PREC_NAMES[prec], "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={prob.N} d={prob.d} "
+                               f"{W.KERNEL_NAMES[prob.kernel]} sigma={prob.sigma} "
+                               f"k={prob.k} b={prob.b}",
+                   "N": prob.N, "d": prob.d, "k": prob.k, "b": prob.b,
+                   "parallelism": "single GPU"},
+        "roofline": roof, "roofline_alt": roof_alt,
+        "rounds": last["rounds"], "acceptance": round(last["k_out"] / last["proposals"], 4),
+        "trace_error_F": trace_err,
+        "kernel_ms_per_step": {c: round(v / args.steps, 3) for c, v in agg["ms_kernel"].items()},
+    }
+    if args.compare_fp64 and prec != W.FP64:
+        p64 = prob.with_(prec=W.FP64)
+        out64 = B.factor(Xd, p64)
+        F64 = out64["F"][:, : out64["stats"]["k_out"]]
+        te64 = (out64["stats"]["trace_A"] - float((F64 ** 2).sum().item())) / out64["stats"]["trace_A"]
+        out["fp64_compare"] = {"ms": round(out64["stats"]["ms_total"], 2), "trace_error_F": te64,
+                               "ratio": trace_err / te64 if te64 > 0 else None}
+        del out64, F64
+    if args.cpu_rounds > 0:
+        out["cpu_baseline"] = cpu_baseline(X, prob, args.cpu_rounds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,6 +86,8 @@ typedef struct arpc_stats {
   int64_t launches[ARPC_NUM_KC];   /* launches per class (profiling on) */
   double flops_colgemm; /* algorithmic flops of the update GEMM, sum_r 2 N k_r s_r */
   double flops_trsm;    /* algorithmic flops of the triangular solve, sum_r N s_r^2 */
+  double bytes_colgemm; /* algorithmic HBM bytes of the update GEMM: F read, C written, X read */
+  double bytes_trsm;    /* algorithmic HBM bytes of the triangular solve: C read, G written, norms */
 } arpc_stats;
 
 /* Human-readable name of a status code (static storage). */

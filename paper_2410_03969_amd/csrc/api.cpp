@@ -9,12 +9,15 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
 #include "../../include/arpc.h"
 #include "arpc_common.h"
 #include "arpc_launch.h"
+#include "arpc_mfma.h"
 
 using namespace arpc;
 
@@ -22,10 +25,20 @@ namespace {
 
 int g_profiling = 0;
 
+// The update GEMM and triangular solve run on the matrix cores; setting
+// ARPC_GEMM=valu selects the register-tiled vector kernels instead (FP64 and
+// FP32 modes only), which serve as a cross-check.
+bool use_valu_gemm() {
+  const char* e = getenv("ARPC_GEMM");
+  return e && strcmp(e, "valu") == 0;
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t st, u, csum, cpre, props, acc, hist, Fs, H, L, Xp, Bt, Bt2, C, P, trace, total;
+  size_t st, u, csum, cpre, props, acc, hist, Fs, H, L, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, P, trace, total;
+  int part_cols;
+  bool valu;  // vector-unit GEMM kernels instead of the matrix-core ones
 };
 
 inline int64_t nchunks_of(int64_t N) { return (N + CHUNK - 1) / CHUNK; }
@@ -36,7 +49,11 @@ Layout layout_of(const arpc_problem& p) {
   Layout l{};
   const size_t es = elem_size(p.prec);
   const int64_t nch = nchunks_of(p.N);
-  const int64_t nparts = (p.b + 63) / 64;
+  const bool valu = use_valu_gemm() && p.prec <= ARPC_FP32;
+  l.valu = valu;
+  l.part_cols = valu ? 64 : mfma_part_cols(p.prec, (int)p.b);
+  const int64_t nparts = (p.b + l.part_cols - 1) / l.part_cols;
+  const size_t mb = valu ? 0 : mfma_operand_bytes(p.prec, p.k, (int)p.b);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -54,9 +71,12 @@ Layout layout_of(const arpc_problem& p) {
   l.H = take(sizeof(double) * p.b * p.b);
   l.L = take(sizeof(double) * p.b * p.b);
   l.Xp = take(sizeof(double) * p.b * p.d);
-  l.Bt = take(es * p.k * p.b);
-  l.Bt2 = take(es * p.b * p.b);
-  l.C = take(es * p.N * p.b);
+  l.Bt = take(valu ? es * p.k * p.b : 0);
+  l.Bt2 = take(valu ? es * p.b * p.b : 0);
+  l.Bm1 = take(mb);
+  l.Bm2 = take(mb);
+  l.Fb = take(valu ? 0 : mfma_blocked_bytes(p.prec, p.N, p.k));
+  l.C = take(valu ? es * p.N * p.b : mfma_blocked_bytes(p.prec, p.N, p.b));
   l.P = take(sizeof(double) * nparts * p.N);
   l.trace = take(sizeof(double));
   l.total = off;
@@ -115,14 +135,17 @@ struct Profiler {
     if (!on) return;
     (void)hipEventRecord(next(), s);
   }
-  // called after a stream synchronisation
+  // called after a stream synchronisation; ARPC_TRACE=1 also prints every
+  // launch's time to stderr
   void collect() {
     if (!on) return;
+    static const bool trace = getenv("ARPC_TRACE") != nullptr;
     for (auto& m : marks) {
       float t = 0.f;
       if (hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]) == hipSuccess) {
         ms[m.first] += t;
         n[m.first] += 1;
+        if (trace) fprintf(stderr, "arpc-trace class=%d launch=%lld ms=%.4f\n", m.first, (long long)n[m.first], t);
       }
     }
     marks.clear();
@@ -154,23 +177,38 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   prof.begin(ARPC_KC_PROPOSE);
   launch_propose(s, u, csum, cpre, nch, N, b, un, st, props);
   prof.end();
+  MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
+               (int)((b + 15) / 16 * 16), P, Fs, k, acc, L, b, k};
   prof.begin(ARPC_KC_GATHER);
   launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, H, st);
   prof.end();
   prof.begin(ARPC_KC_REJECT);
   launch_reject(s, H, b, props, un, st, L, acc, pivots, u, k);
   prof.end();
-  prof.begin(ARPC_KC_PREP);
-  launch_prep<T>(s, Fs, k, acc, props, X, d, Bt, b, Xp, L, b, Bt2, k, st);
-  prof.end();
-  prof.begin(ARPC_KC_COLGEMM);
-  launch_colgemm<T>(s, F, N, Bt, b, X, d, Xp, kp, C, b, st);
-  prof.end();
-  prof.begin(ARPC_KC_TRSM);
-  launch_trsm<T>(s, C, N, Bt2, b, F, P, st);
-  prof.end();
+  if (l.valu) {  // vector-unit kernels (cross-check path)
+    prof.begin(ARPC_KC_PREP);
+    launch_prep<T>(s, Fs, k, acc, props, X, d, Bt, b, Xp, L, b, Bt2, k, st);
+    prof.end();
+    prof.begin(ARPC_KC_COLGEMM);
+    launch_colgemm<T>(s, F, N, Bt, b, X, d, Xp, kp, C, b, st);
+    prof.end();
+    prof.begin(ARPC_KC_TRSM);
+    launch_trsm<T>(s, C, N, Bt2, b, F, P, st);
+    prof.end();
+  } else {
+    prof.begin(ARPC_KC_PREP);
+    launch_prep_xp(s, acc, props, X, d, Xp, st);
+    launch_mfma_prep(s, p.prec, mr, st);
+    prof.end();
+    prof.begin(ARPC_KC_COLGEMM);
+    launch_mfma_colgemm(s, p.prec, mr, st);
+    prof.end();
+    prof.begin(ARPC_KC_TRSM);
+    launch_mfma_trsm(s, p.prec, mr, st);
+    prof.end();
+  }
   prof.begin(ARPC_KC_DIAG);
-  launch_diag(s, u, csum, P, (int)((b + 63) / 64), N, nch, st);
+  launch_diag(s, u, csum, P, l.part_cols, N, nch, st);
   prof.end();
   prof.begin(ARPC_KC_FINISH);
   launch_finish(s, st, b, k, p.max_rounds, hist);
@@ -243,15 +281,22 @@ arpc_status run(const arpc_problem& p, const double* X, T* F, int64_t* pivots, c
     stats->status = (ret == ARPC_EINVAL) ? ARPC_EINVAL : ret;
     stats->trace_A = h.trace_A;
     stats->trace_resid = trace_resid;
-    double kr = 0.0, fg = 0.0, ft = 0.0;
+    double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0;
+    const double es = (double)sizeof(T);
     for (int64_t r = 0; r < h.round; ++r) {
       const double sr = hist[r];
       fg += 2.0 * (double)N * kr * sr;
       ft += (double)N * sr * sr;
+      if (sr > 0) {
+        bg += (double)N * (kr * es + sr * es + 8.0 * (double)p.d);
+        bt += (double)N * (2.0 * sr * es + 8.0);
+      }
       kr += sr;
     }
     stats->flops_colgemm = fg;
     stats->flops_trsm = ft;
+    stats->bytes_colgemm = bg;
+    stats->bytes_trsm = bt;
     for (int c = 0; c < ARPC_NUM_KC; ++c) {
       stats->ms_kernel[c] = prof.ms[c];
       stats->launches[c] = prof.n[c];
@@ -273,9 +318,8 @@ arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t
   hipStream_t s = (hipStream_t)stream;
   if (p->prec == ARPC_FP64)
     return run<double>(*p, X, (double*)F, pivots, (char*)ws, l, s, un, stats);
-  if (p->prec == ARPC_FP32)
-    return run<float>(*p, X, (float*)F, pivots, (char*)ws, l, s, un, stats);
-  return ARPC_EINVAL;  // BF16 modes are provided by the matrix-core path
+  if (use_valu_gemm() && p->prec > ARPC_FP32) return ARPC_EINVAL;  // vector kernels: FP64/FP32 only
+  return run<float>(*p, X, (float*)F, pivots, (char*)ws, l, s, un, stats);
 }
 
 }  // namespace

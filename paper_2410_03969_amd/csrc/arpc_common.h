@@ -82,7 +82,7 @@ __device__ inline double stream_uniform(const Unif& un, int64_t p) {
 
 // Kernel value from the squared distance, in FP64 (Section 1.2 Gaussian;
 // Laplace with the l2 distance; Matern-3/2; Matern-5/2 of Section 3.2).
-__device__ inline double kappa_r2(double r2, const KParams& kp) {
+__device__ __attribute__((always_inline)) inline double kappa_r2(double r2, const KParams& kp) {
   switch (kp.kernel) {
     case 0: return exp(-r2 * kp.c0);                 // c0 = 1/(2 sigma^2)
     case 1: return exp(-sqrt(r2) / kp.sigma);
@@ -97,8 +97,24 @@ __device__ inline double kappa_r2(double r2, const KParams& kp) {
   }
 }
 
+// The same kernel values in FP32 (used by the reduced-precision modes).
+__device__ __attribute__((always_inline)) inline float kappa_r2_f32(float r2, const KParams& kp) {
+  switch (kp.kernel) {
+    case 0: return expf(-r2 * (float)kp.c0);
+    case 1: return expf(-sqrtf(r2) / (float)kp.sigma);
+    case 2: {
+      const float t = 1.7320508f * sqrtf(r2) / (float)kp.sigma;
+      return (1.0f + t) * expf(-t);
+    }
+    default: {
+      const float t = 2.2360680f * sqrtf(r2) / (float)kp.sigma;
+      return (1.0f + t + r2 * (float)kp.c0) * expf(-t);
+    }
+  }
+}
+
 // Squared distance by direct differences (a point paired with itself gives 0).
-__device__ inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
+__device__ __attribute__((always_inline)) inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
   double s = 0.0;
   for (int t = 0; t < d; ++t) {
     const double e = x[t] - y[t];

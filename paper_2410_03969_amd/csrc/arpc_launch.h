@@ -13,13 +13,15 @@ template <typename T>
 void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
                    const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* H,
                    const RoundState* st);
+void launch_gather_H(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b,
+                     const double* Fs, int64_t ldf, double* H, const RoundState* st);
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
                    double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax);
 template <typename T>
 void launch_prep(hipStream_t s, const double* Fs, int64_t ldf, const int32_t* acc, const int64_t* props,
                  const double* X, int d, T* Bt, int ldb, double* Xp, const double* L, int b, T* Bt2,
                  int64_t kmax, const RoundState* st);
-void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int nparts, int64_t N,
+void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int part_cols, int64_t N,
                  int64_t nchunks, const RoundState* st);
 void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist);
 void launch_trace(hipStream_t s, const double* csum, int64_t nchunks, double* out);

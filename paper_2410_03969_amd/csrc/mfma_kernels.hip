@@ -1,0 +1,619 @@
+// Matrix-core versions of the two N-sized products of each round of
+// accelerated RPCholesky (Alg. 2, step 3) for gfx950:
+//   colgemm:  C = A(:, S_r) - F F(S_r,:)^T   (N x s_r, contraction over k_r)
+//   trsm:     G = C L^{-T} = C Linv^T        (N x s_r, contraction over s_r),
+//             written into F(:, k_r : k_r + s_r) with FP64 row norms of G.
+//
+// Both are computed transposed, C^T = Bm * F^T: the N-row operand (F, or C)
+// is the MFMA B operand and the small per-round operand Bm (F(S_r,:)^T, or
+// Linv) the A operand.  The N-row operands are kept in a panel-blocked copy
+// (see blk_offset) in which a lane's contraction values for one row are
+// adjacent, so each lane fetches them with 16-byte loads straight from HBM
+// into registers, double-buffered one chunk ahead.  Bm is pre-arranged in
+// contraction chunks and staged through LDS once per workgroup, double-
+// buffered and shared by the four wavefronts.  Each wavefront owns 16*NB rows
+// and all columns of its column group, so F is read from HBM once per round
+// (groups of one row panel run back to back on the same XCD and share its L2).
+//
+// Arithmetic policies:
+//   Pol64     v_mfma_f64_16x16x4f64                       (FP64 mode)
+//   Pol32     v_mfma_f32_16x16x4f32                       (FP32 mode)
+//   PolBF<3>  v_mfma_f32_16x16x32_bf16, hi*hi + hi*lo + lo*hi, both operands
+//             split into a BF16 high part and a BF16 remainder; the N-row
+//             operands are stored already split (two BF16 planes), so the
+//             contraction loop does no conversion at all
+//   PolBF<1>  the same with the high parts only
+#include "arpc_common.h"
+#include "arpc_launch.h"
+#include "arpc_mfma.h"
+
+#include <cstdlib>
+#include <utility>
+
+namespace arpc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------- policies
+// T: arithmetic type of the results; S: storage element of the blocked
+// N-row operands; SPLANES: storage planes (hi/lo); KC: contraction indices per
+// chunk; RAW: contraction values one lane supplies per chunk and plane;
+// NB: 16-row tiles per wavefront; CROW/GROW: bytes per column of a staged
+// chunk of Bm in LDS (padded) and in global memory; cmap: accumulator layout.
+struct Pol64 {
+  using T = double;
+  using S = double;
+  using Acc = d4;
+  static constexpr int KC = 16, RAW = 4, NB = 2, SPLANES = 1, PLANES = 1;
+  static constexpr int CROW = KC * 8 + 16, GROW = KC * 8;
+  // lane l of the accumulator holds column 4i + l/16 of the 16x16 tile
+  __device__ static inline int cmap(int l, int i) { return (l >> 4) + 4 * i; }
+};
+struct Pol32 {
+  using T = float;
+  using S = float;
+  using Acc = f4;
+  static constexpr int KC = 16, RAW = 4, NB = 4, SPLANES = 1, PLANES = 1;
+  static constexpr int CROW = KC * 4 + 16, GROW = KC * 4;
+  __device__ static inline int cmap(int l, int i) { return 4 * (l >> 4) + i; }
+};
+template <int PASSES>
+struct PolBF {
+  using T = float;
+  using S = __bf16;
+  using Acc = f4;
+  static constexpr int KC = 32, RAW = 8, NB = 4;
+  static constexpr int SPLANES = (PASSES == 3) ? 2 : 1, PLANES = SPLANES;
+  static constexpr int CROW = KC * 2 + 16;  // 80 bytes: conflict-free 16-byte reads
+  static constexpr int GROW = KC * 2;
+  __device__ static inline int cmap(int l, int i) { return 4 * (l >> 4) + i; }
+};
+
+// High part = round-to-nearest BF16, low part = BF16 of the remainder.
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+constexpr int PANEL_WAVES = 4;
+template <class Pol>
+constexpr int panel_rows() { return PANEL_WAVES * Pol::NB * 16; }
+
+enum { MODE_COLGEMM = 0, MODE_TRSM = 1 };
+
+// Panel-blocked layout of the N-row operands (the internal copy of F and the
+// scratch C).  Rows are grouped in panels of PH = 256; inside a panel the
+// contraction index runs in chunks of KC; a chunk holds SPLANES planes, and in
+// a plane each row stores its KC values contiguously.  One row panel of the
+// whole factor is a single contiguous region.  In the 16x16x4 products the
+// four values a lane supplies over four successive steps are adjacent indices
+// (lane group g supplies 4g .. 4g+3); the staged Bm is read the same way.
+constexpr int PH = 256;
+
+template <class Pol>
+__host__ __device__ inline size_t blk_offset(int64_t row, int64_t k, int64_t nkc, int plane) {
+  return (((size_t)((row / PH) * nkc + k / Pol::KC) * Pol::SPLANES + plane) * PH + (size_t)(row % PH)) * Pol::KC +
+         (size_t)(k % Pol::KC);
+}
+
+// Arguments of one panel product.
+struct PanelArgs {
+  const void* Bsrc;    // F (colgemm) or C (trsm), panel-blocked
+  int64_t nkc_src;     // contraction chunks per panel of Bsrc
+  int64_t N;
+  const unsigned char* Bm;  // chunked small operand (see chunk_offset)
+  int Ctot;            // padded column count of Bm (multiple of 16)
+  const double* X;     // points (colgemm epilogue)
+  int d;
+  const double* Xp;    // accepted points, s x d
+  KParams kp;
+  void* out_user;      // F, column-major, ld N (trsm only)
+  void* out_blk;       // C (colgemm) or F (trsm), panel-blocked
+  int64_t nkc_out;     // contraction chunks per panel of out_blk
+  double* P;           // partial row norms (trsm), groups x N
+  const RoundState* st;
+  int npanels;         // row panels of this kernel
+  int ngroups;         // column groups
+};
+
+// Byte offset of element (k, c) of the chunked small operand.
+template <class Pol>
+__host__ __device__ inline size_t chunk_offset(int64_t k, int c, int Ctot, int plane) {
+  const int64_t ch = k / Pol::KC, kk = k % Pol::KC;
+  const size_t esz = Pol::GROW / Pol::KC;
+  return (size_t)ch * Pol::PLANES * Ctot * Pol::GROW + (size_t)plane * Ctot * Pol::GROW +
+         (size_t)c * Pol::GROW + kk * esz;
+}
+
+// Store one value into the blocked layout (split into BF16 planes if needed).
+template <class Pol>
+__device__ inline void store_blk(typename Pol::S* __restrict__ base, int64_t row, int64_t k, int64_t nkc,
+                                 typename Pol::T v) {
+  if constexpr (Pol::SPLANES == 2) {
+    __bf16 hi, lo;
+    split_bf16((float)v, hi, lo);
+    base[blk_offset<Pol>(row, k, nkc, 0)] = hi;
+    base[blk_offset<Pol>(row, k, nkc, 1)] = lo;
+  } else {
+    base[blk_offset<Pol>(row, k, nkc, 0)] = (typename Pol::S)v;
+  }
+}
+
+// One lane's slice of the N-row operand for one chunk and one 16-row tile.
+template <class Pol>
+struct Frag;
+template <>
+struct Frag<Pol64> {
+  d4 v;
+};
+template <>
+struct Frag<Pol32> {
+  f4 v;
+};
+template <int PASSES>
+struct Frag<PolBF<PASSES>> {
+  bf8 v[PolBF<PASSES>::SPLANES];
+};
+
+// --------------------------------------------------------- the panel kernel
+// Largest dimension for which a row of X is held in registers in the
+// update-GEMM epilogue; larger dimensions stream the coordinates from memory.
+constexpr int XREG = 16;
+// 16-column blocks per epilogue window (per-wavefront LDS tile of 16*NB rows
+// x 64 columns).
+constexpr int EPI_CB = 4;
+
+template <class Pol, int NCB>
+constexpr int panel_lds_bytes() {
+  constexpr int stage = 2 * Pol::PLANES * NCB * 16 * Pol::CROW;
+  constexpr int epi = PANEL_WAVES * (Pol::NB * 16 + 1) * EPI_CB * 16 * (int)sizeof(typename Pol::T);
+  return stage > epi ? stage : epi;
+}
+
+template <class Pol, int NCB, int MODE, int PASSES>
+__global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
+  using T = typename Pol::T;
+  using S = typename Pol::S;
+  using Acc = typename Pol::Acc;
+  const RoundState* st = a.st;
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  if (s == 0) return;
+  const int64_t kr = st->k_r;
+  // Blocks are dealt round-robin to the 8 XCDs (each with its own L2).  Block
+  // b runs on XCD b % 8; the column groups of one row panel get consecutive
+  // slots on the same XCD so that the panel of F they share is read from HBM
+  // once and from that XCD's L2 afterwards.
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int grp = slot % a.ngroups;
+  const int panel = (slot / a.ngroups) * 8 + xcd;
+  if (panel >= a.npanels) return;
+  const int cb0 = grp * NCB;                        // first 16-column block of this group
+  const int ncb_tot = (s + 15) >> 4;
+  if (cb0 >= ncb_tot) return;
+  const int ncb = (ncb_tot - cb0) < NCB ? (ncb_tot - cb0) : NCB;
+  // contraction length; the inverse factor is lower triangular, so the columns
+  // of this group need t < 16 * (cb0 + ncb) only.  The blocked operands hold
+  // zeros from the contraction length up to the end of its chunk.
+  int64_t K;
+  if (MODE == MODE_COLGEMM) K = kr;
+  else K = (16 * (cb0 + ncb) < s) ? 16 * (cb0 + ncb) : s;
+  const int64_t nchunks = (K + Pol::KC - 1) / Pol::KC;
+
+  constexpr int NB = Pol::NB;
+  constexpr int WROWS = NB * 16;                     // rows per wavefront
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int64_t N = a.N;
+  const int64_t row_w = (int64_t)panel * panel_rows<Pol>() + (int64_t)w * WROWS;
+
+  constexpr int CP = NCB * 16;                       // columns staged per block
+  constexpr int STAGE = Pol::PLANES * CP * Pol::CROW; // LDS bytes per chunk
+  __shared__ __attribute__((aligned(16))) unsigned char lds[panel_lds_bytes<Pol, NCB>()];
+
+  Acc acc[NB][NCB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[nb][cb] = Acc{0, 0, 0, 0};
+
+  // ---- staging of the small operand: chunk ch -> LDS buffer, via registers;
+  // columns past this group's valid ones are zero-filled
+  const int cvalid = 16 * ncb;
+  constexpr int Q = Pol::GROW / 16;  // 16-byte pieces per column per chunk
+  constexpr int PIECES = Pol::PLANES * CP * Q;
+  constexpr int PER_T = (PIECES + 64 * PANEL_WAVES - 1) / (64 * PANEL_WAVES);
+  u4 sbuf[PER_T];
+  auto fetch = [&](int64_t ch) {
+#pragma unroll
+    for (int r = 0; r < PER_T; ++r) {
+      const int o = tid + r * 64 * PANEL_WAVES;
+      const int plane = o / (CP * Q), rem = o % (CP * Q), c = rem / Q, q = rem % Q;
+      if (o < PIECES)
+        sbuf[r] = (c < cvalid) ? *(const u4*)(a.Bm + (size_t)ch * Pol::PLANES * a.Ctot * Pol::GROW +
+                                              (size_t)plane * a.Ctot * Pol::GROW +
+                                              (size_t)(16 * cb0 + c) * Pol::GROW + q * 16)
+                               : u4{0, 0, 0, 0};
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < PER_T; ++r) {
+      const int o = tid + r * 64 * PANEL_WAVES;
+      const int plane = o / (CP * Q), rem = o % (CP * Q), c = rem / Q, q = rem % Q;
+      if (o < PIECES) *(u4*)(lds + buf * STAGE + plane * CP * Pol::CROW + c * Pol::CROW + q * 16) = sbuf[r];
+    }
+  };
+
+  // ---- this lane's slice of the N-row operand: rows row_w + 16 nb + l16,
+  // contraction indices k0 + RAW g .. k0 + RAW g + RAW - 1 of each plane.
+  // Rows past N lie in the allocated padding of the last panel and only feed
+  // outputs that are never stored.
+  const S* __restrict__ Bsrc = (const S*)a.Bsrc;
+  const int64_t myrow = row_w + l16;                 // row of tile 0
+  const S* __restrict__ rowbase = Bsrc + (size_t)(myrow / PH) * a.nkc_src * Pol::SPLANES * PH * Pol::KC +
+                                  (size_t)(myrow % PH) * Pol::KC + (size_t)(Pol::RAW * g);
+  constexpr size_t CHUNK_ELEMS = (size_t)Pol::SPLANES * PH * Pol::KC;
+  constexpr size_t PLANE_ELEMS = (size_t)PH * Pol::KC;
+  using F = Frag<Pol>;
+  auto load = [&](F (&f)[NB], int64_t ch) {
+    const S* p = rowbase + (size_t)ch * CHUNK_ELEMS;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const S* q = p + (size_t)nb * 16 * Pol::KC;   // tiles of one wavefront share a panel
+      if constexpr (Pol::KC == 32) {
+#pragma unroll
+        for (int pl = 0; pl < Pol::SPLANES; ++pl) f[nb].v[pl] = *(const bf8*)(q + pl * PLANE_ELEMS);
+      } else {
+        f[nb].v = *(const decltype(f[nb].v)*)q;
+      }
+    }
+  };
+  auto compute = [&](const F (&f)[NB], const unsigned char* Ls) {
+    if constexpr (Pol::KC == 32) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const bf8 ah = *(const bf8*)(Ls + (cb * 16 + l16) * Pol::CROW + g * 16);
+        bf8 al;
+        if (PASSES == 3) al = *(const bf8*)(Ls + CP * Pol::CROW + (cb * 16 + l16) * Pol::CROW + g * 16);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, f[nb].v[0], acc[nb][cb], 0, 0, 0);
+          if constexpr (PASSES == 3) {
+            acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, f[nb].v[1], acc[nb][cb], 0, 0, 0);
+            acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, f[nb].v[0], acc[nb][cb], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        T aq[4];
+        __builtin_memcpy(aq, Ls + (cb * 16 + l16) * Pol::CROW + 4 * g * sizeof(T), 4 * sizeof(T));
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            if constexpr (sizeof(T) == 8)
+              acc[nb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[ks], f[nb].v[ks], acc[nb][cb], 0, 0, 0);
+            else
+              acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[ks], f[nb].v[ks], acc[nb][cb], 0, 0, 0);
+          }
+      }
+    }
+  };
+
+  // ---- contraction loop: two named register buffers alternate, LDS buffer =
+  // chunk parity; one barrier per chunk
+  F fa[NB], fb[NB];
+  if (nchunks > 0) {
+    fetch(0);
+    commit(0);
+    load(fa, 0);
+  }
+  __syncthreads();
+  for (int64_t ch = 0; ch < nchunks; ch += 2) {
+    {
+      const bool more = ch + 1 < nchunks;
+      if (more) {
+        fetch(ch + 1);
+        load(fb, ch + 1);
+      }
+      compute(fa, lds);
+      if (more) commit(1);
+      __syncthreads();
+    }
+    if (ch + 1 < nchunks) {
+      const bool more = ch + 2 < nchunks;
+      if (more) {
+        fetch(ch + 2);
+        load(fa, ch + 2);
+      }
+      compute(fb, lds + STAGE);
+      if (more) commit(0);
+      __syncthreads();
+    }
+  }
+
+  // ------------------------------------------------------------- epilogue
+  // Windows of 64 columns:
+  //  A. accumulator tiles -> LDS tile E[col][row] of this wavefront;
+  //  B. each lane owns a row: kernel value (update GEMM) or row norm and the
+  //     column-major store of F (solve), result written back into E;
+  //  C. copy of E into the blocked layout, one row (64 consecutive columns)
+  //     per wavefront store.  The group that holds the last column also
+  //     writes zeros up to the end of that column's chunk.
+  constexpr int EROW = WROWS + 1;                    // padded row count of E
+  T* E = (T*)lds + w * EROW * EPI_CB * 16;
+  constexpr int LPR = 64 / WROWS;                    // lanes per row (1 or 2)
+  const int my_row = lane % WROWS, my_part = lane / WROWS;
+  const int64_t row = row_w + my_row;
+  const bool rok = row < N;
+  const int d = a.d;
+  S* __restrict__ ob = (S*)a.out_blk;
+  T* __restrict__ ou = (T*)a.out_user;
+  const int64_t cshift = (MODE == MODE_COLGEMM) ? 0 : kr;   // blocked column of column c
+  // Columns written to the blocked layout: this group's columns; the last
+  // group writes exactly up to the end of the chunk holding column s-1 (its
+  // data columns, then zeros), never past it: beyond lies the next chunk or,
+  // after the last chunk, the next row panel.
+  const int clo = 16 * cb0;
+  const int cend = (16 * (cb0 + ncb) < s) ? 16 * (cb0 + ncb) : s;  // end of this group's data columns
+  int chi = 16 * (cb0 + ncb);
+  if (cb0 + ncb >= ncb_tot) chi = (int)((cshift + s + Pol::KC - 1) / Pol::KC * Pol::KC - cshift);
+  double xr[XREG];
+  if (MODE == MODE_COLGEMM && rok && d <= XREG) {
+#pragma unroll
+    for (int t = 0; t < XREG; ++t) xr[t] = (t < d) ? a.X[row * d + t] : 0.0;
+  }
+  double g2 = 0.0;
+  for (int w0 = clo; w0 < chi; w0 += 16 * EPI_CB) {
+    const int e0 = (w0 - clo) >> 4;                  // first column block of the window
+    // A
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        if (cb >= e0 && cb < e0 + EPI_CB && cb < ncb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            E[((cb - e0) * 16 + Pol::cmap(lane, i)) * EROW + nb * 16 + l16] = (T)acc[nb][cb][i];
+    __syncthreads();
+    // valid columns in the window: this group's data columns only (a window
+    // can reach past the group into columns another workgroup owns)
+    int wv = cend - w0;
+    if (wv > 16 * EPI_CB) wv = 16 * EPI_CB;
+    // B
+    if (rok) {
+#pragma unroll 2
+      for (int cc = my_part; cc < wv; cc += LPR) {
+        const int c = w0 + cc;
+        T& v = E[cc * EROW + my_row];
+        if (MODE == MODE_COLGEMM) {
+          const double* xp = a.Xp + (int64_t)c * d;
+          double r2 = 0.0;
+          if (d <= XREG) {
+            double r2b = 0.0;
+#pragma unroll
+            for (int t = 0; t < XREG; t += 2) {
+              if (t < d) {
+                const double e = xr[t] - xp[t];
+                r2 += e * e;
+              }
+              if (t + 1 < d) {
+                const double e = xr[t + 1] - xp[t + 1];
+                r2b += e * e;
+              }
+            }
+            r2 += r2b;
+          } else {
+            r2 = sqdist(a.X + row * d, xp, d);
+          }
+          double kap;
+          if (sizeof(T) == 8) kap = kappa_r2(r2, a.kp);
+          else kap = (double)kappa_r2_f32((float)r2, a.kp);
+          v = (T)(kap - (double)v);
+        } else {
+          ou[(kr + c) * N + row] = v;
+          g2 += (double)v * (double)v;
+        }
+      }
+    }
+    __syncthreads();
+    // C
+    int wend = chi - w0;
+    if (wend > 16 * EPI_CB) wend = 16 * EPI_CB;
+    if (lane < wend) {
+      for (int rl = 0; rl < WROWS; ++rl) {
+        if (row_w + rl >= N) break;
+        const T v = (lane < wv) ? E[lane * EROW + rl] : (T)0;
+        store_blk<Pol>(ob, row_w + rl, cshift + w0 + lane, a.nkc_out, v);
+      }
+    }
+    __syncthreads();
+  }
+  if (MODE == MODE_TRSM) {
+    if (LPR == 2) g2 += __shfl_xor(g2, 32, 64);
+    if (my_part == 0 && rok) a.P[(int64_t)grp * N + row] = g2;
+  }
+}
+
+// ------------------------------------------ small operands in chunk layout
+// Bm(k, c) = F(S_r(c), k) for the update GEMM (zero outside k < k_r, c < s_r).
+template <class Pol, int PASSES>
+__global__ __launch_bounds__(256) void k_prep_bm(const double* __restrict__ Fs, int64_t ldf,
+                                                 const int32_t* __restrict__ acc, int Ctot,
+                                                 unsigned char* __restrict__ Bm, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int64_t K = st->k_r;
+  const int64_t Kpad = (K + Pol::KC - 1) / Pol::KC * Pol::KC;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t k = e / Ctot;
+  const int c = (int)(e % Ctot);
+  if (k >= Kpad) return;
+  const double v = (k < K && c < s) ? Fs[(int64_t)acc[c] * ldf + k] : 0.0;
+  if constexpr (Pol::KC == 32) {
+    __bf16 hi, lo;
+    split_bf16((float)v, hi, lo);
+    *(__bf16*)(Bm + chunk_offset<Pol>(k, c, Ctot, 0)) = hi;
+    if (PASSES == 3) *(__bf16*)(Bm + chunk_offset<Pol>(k, c, Ctot, 1)) = lo;
+  } else {
+    *(typename Pol::T*)(Bm + chunk_offset<Pol>(k, c, Ctot, 0)) = (typename Pol::T)v;
+  }
+}
+
+// Inverse of the s x s lower factor L (column-major, ld b): workgroup c
+// computes column c by forward substitution with wavefront dot products and
+// stores Linv(i, c) as element (k = c, column i) of the chunked operand of the
+// triangular-solve product.  Workgroups c >= s write the zero padding.
+template <class Pol, int PASSES>
+__global__ __launch_bounds__(64) void k_trinv_bm(const double* __restrict__ L, int b, int Ctot,
+                                                 unsigned char* __restrict__ Bm, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  __shared__ double x[BMAX];
+  if (c < s) {
+    for (int i = lane; i < s; i += 64) x[i] = 0.0;
+    __syncthreads();
+    if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
+    __syncthreads();
+    for (int i = c + 1; i < s; ++i) {
+      double p = 0.0;
+      for (int t = c + lane; t < i; t += 64) p += L[(int64_t)t * b + i] * x[t];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+      if (lane == 0) x[i] = -p / L[(int64_t)i * b + i];
+      __syncthreads();
+    }
+  }
+  for (int i = lane; i < Ctot; i += 64) {
+    const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
+    if constexpr (Pol::KC == 32) {
+      __bf16 hi, lo;
+      split_bf16((float)v, hi, lo);
+      *(__bf16*)(Bm + chunk_offset<Pol>(c, i, Ctot, 0)) = hi;
+      if (PASSES == 3) *(__bf16*)(Bm + chunk_offset<Pol>(c, i, Ctot, 1)) = lo;
+    } else {
+      *(typename Pol::T*)(Bm + chunk_offset<Pol>(c, i, Ctot, 0)) = (typename Pol::T)v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <class Pol, int PASSES, int NCB>
+static void launch_panel(hipStream_t s, const MfmaRound& r, const RoundState* st, int which) {
+  const int ncb_tot = r.Ctot / 16;
+  const int npanels = (int)((r.N + panel_rows<Pol>() - 1) / panel_rows<Pol>());
+  const int ngroups = (ncb_tot + NCB - 1) / NCB;
+  const unsigned nblocks = (unsigned)((npanels + 7) / 8) * 8u * (unsigned)ngroups;
+  const int64_t nkcF = (r.kmax + Pol::KC - 1) / Pol::KC, nkcC = (r.b + Pol::KC - 1) / Pol::KC;
+  if (which == 0) {
+    PanelArgs a1{r.Fb, nkcF, r.N, r.Bm1, r.Ctot, r.X, r.d, r.Xp, r.kp, nullptr, r.C, nkcC, nullptr, st,
+                 npanels, ngroups};
+    hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_COLGEMM, PASSES>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0, s, a1);
+  } else {
+    PanelArgs a2{r.C, nkcC, r.N, r.Bm2, r.Ctot, nullptr, 0, nullptr, r.kp, r.F, r.Fb, nkcF, r.P, st,
+                 npanels, ngroups};
+    hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_TRSM, PASSES>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0, s, a2);
+  }
+}
+
+// Column blocks per workgroup (the accumulators of one wavefront are NB x NCB
+// tiles).  Four blocks keep a wavefront within 256 registers, so two
+// wavefronts share each SIMD and one hides the other's HBM latency; wider
+// groups read F fewer times but drop to one wavefront per SIMD, which costs
+// more than the extra L2 reads.  ARPC_NCB=4|7|8|13 overrides the choice.
+inline int ncb_for(int ncb_tot) {
+  static int forced = -1;
+  if (forced < 0) {
+    const char* e = getenv("ARPC_NCB");
+    forced = e ? atoi(e) : 0;
+  }
+  if (forced == 4 || forced == 7 || forced == 8 || forced == 13) return forced;
+  (void)ncb_tot;
+  return 4;
+}
+
+template <class Pol, int PASSES>
+static void dispatch(hipStream_t s, const MfmaRound& r, const RoundState* st, int which) {
+  switch (ncb_for(r.Ctot / 16)) {
+    case 4: launch_panel<Pol, PASSES, 4>(s, r, st, which); break;
+    case 7: launch_panel<Pol, PASSES, 7>(s, r, st, which); break;
+    case 8: launch_panel<Pol, PASSES, 8>(s, r, st, which); break;
+    default: launch_panel<Pol, PASSES, 13>(s, r, st, which); break;
+  }
+}
+
+template <class Pol, int PASSES>
+static void prep_impl(hipStream_t s, const MfmaRound& r, const RoundState* st) {
+  const int64_t kpad = (r.kmax + Pol::KC - 1) / Pol::KC * Pol::KC;
+  const int64_t n = kpad * r.Ctot;
+  hipLaunchKernelGGL((k_prep_bm<Pol, PASSES>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r.Fs, r.ldf,
+                     r.acc, r.Ctot, r.Bm1, st);
+  const int nblk = (r.b + Pol::KC - 1) / Pol::KC * Pol::KC;
+  hipLaunchKernelGGL((k_trinv_bm<Pol, PASSES>), dim3(nblk), dim3(64), 0, s, r.L, r.b, r.Ctot, r.Bm2, st);
+}
+
+size_t mfma_operand_bytes(int prec, int64_t kmax, int b) {
+  const int Ctot = (b + 15) / 16 * 16;
+  auto bytes = [&](int KC, int planes, int grow) {
+    const int64_t k1 = (kmax + KC - 1) / KC, k2 = (b + KC - 1) / KC;
+    return std::pair<size_t, size_t>((size_t)k1 * planes * Ctot * grow, (size_t)k2 * planes * Ctot * grow);
+  };
+  std::pair<size_t, size_t> p;
+  switch (prec) {
+    case 0: p = bytes(16, 1, 128); break;
+    case 1: p = bytes(16, 1, 64); break;
+    case 2: p = bytes(32, 2, 64); break;
+    default: p = bytes(32, 1, 64); break;
+  }
+  return p.first > p.second ? p.first : p.second;
+}
+
+int mfma_part_cols(int prec, int b) {
+  (void)prec;
+  return 16 * ncb_for((b + 15) / 16);
+}
+
+size_t mfma_blocked_bytes(int prec, int64_t N, int64_t cols) {
+  const int KC = prec <= 1 ? 16 : 32;
+  // bytes per element: FP64 8, FP32 4, BF16 hi+lo planes 4, BF16 hi plane 2
+  const size_t esz = prec == 0 ? 8 : (prec == 3 ? 2 : 4);
+  const int64_t rows = (N + PH - 1) / PH * PH;
+  return (size_t)rows * (size_t)((cols + KC - 1) / KC * KC) * esz;
+}
+
+void launch_mfma_prep(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
+  switch (prec) {
+    case 0: prep_impl<Pol64, 1>(s, r, st); break;
+    case 1: prep_impl<Pol32, 1>(s, r, st); break;
+    case 2: prep_impl<PolBF<3>, 3>(s, r, st); break;
+    default: prep_impl<PolBF<1>, 1>(s, r, st); break;
+  }
+}
+
+void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
+  switch (prec) {
+    case 0: dispatch<Pol64, 1>(s, r, st, 0); break;
+    case 1: dispatch<Pol32, 1>(s, r, st, 0); break;
+    case 2: dispatch<PolBF<3>, 3>(s, r, st, 0); break;
+    default: dispatch<PolBF<1>, 1>(s, r, st, 0); break;
+  }
+}
+
+void launch_mfma_trsm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
+  switch (prec) {
+    case 0: dispatch<Pol64, 1>(s, r, st, 1); break;
+    case 1: dispatch<Pol32, 1>(s, r, st, 1); break;
+    case 2: dispatch<PolBF<3>, 3>(s, r, st, 1); break;
+    default: dispatch<PolBF<1>, 1>(s, r, st, 1); break;
+  }
+}
+
+}  // namespace arpc

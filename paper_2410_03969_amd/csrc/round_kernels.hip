@@ -7,6 +7,7 @@
 // enqueue rounds without synchronising.
 #include "arpc_common.h"
 #include "arpc_launch.h"
+#include "arpc_mfma.h"
 
 namespace arpc {
 
@@ -405,12 +406,12 @@ __global__ __launch_bounds__(64) void k_trinv(const double* __restrict__ L, int 
 // partial row norms P (nparts x N, FP64, summed in a fixed order), and the
 // new chunk sums.
 __global__ __launch_bounds__(CHUNK) void k_diag(double* __restrict__ u, double* __restrict__ csum,
-                                                const double* __restrict__ P, int nparts, int64_t N,
+                                                const double* __restrict__ P, int part_cols, int64_t N,
                                                 const RoundState* st) {
   if (st->status != ST_RUNNING || st->s_r == 0) return;
   __shared__ double sh[CHUNK];
   const int s = st->s_r;
-  const int np = (s + 63) / 64 < nparts ? (s + 63) / 64 : nparts;
+  const int np = (s + part_cols - 1) / part_cols;
   const int64_t j = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
   double v = 0.0;
   if (j < N) {
@@ -473,6 +474,11 @@ void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d,
   if (kmax > 0)
     hipLaunchKernelGGL(k_gather_rows<T>, dim3((unsigned)((kmax + 255) / 256), b), dim3(256), 0, s, F, N,
                        props, Fs, ldf, st);
+  launch_gather_H(s, X, d, kp, props, b, Fs, ldf, H, st);
+}
+
+void launch_gather_H(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b,
+                     const double* Fs, int64_t ldf, double* H, const RoundState* st) {
   const unsigned nb = (unsigned)((b + 15) / 16);
   hipLaunchKernelGGL(k_gather_H, dim3(nb, nb), dim3(256), 0, s, X, d, kp, props, b, Fs, ldf, H, st);
 }
@@ -507,9 +513,26 @@ template void launch_prep<float>(hipStream_t, const double*, int64_t, const int3
                                  const double*, int, float*, int, double*, const double*, int, float*,
                                  int64_t, const RoundState*);
 
-void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int nparts, int64_t N,
+void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int part_cols, int64_t N,
                  int64_t nchunks, const RoundState* st) {
-  hipLaunchKernelGGL(k_diag, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, csum, P, nparts, N, st);
+  hipLaunchKernelGGL(k_diag, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, csum, P, part_cols, N, st);
+}
+
+// Accepted points Xp(j, :) = X(S_r(j), :).
+__global__ __launch_bounds__(256) void k_prep_xp(const int32_t* __restrict__ acc, const int64_t* __restrict__ props,
+                                                 const double* __restrict__ X, int d, double* __restrict__ Xp,
+                                                 const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < s * d; q += gridDim.x * 256) {
+    const int j = q / d, t = q % d;
+    Xp[q] = X[props[acc[j]] * d + t];
+  }
+}
+
+void launch_prep_xp(hipStream_t s, const int32_t* acc, const int64_t* props, const double* X, int d, double* Xp,
+                    const RoundState* st) {
+  hipLaunchKernelGGL(k_prep_xp, dim3(8), dim3(256), 0, s, acc, props, X, d, Xp, st);
 }
 
 void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist) {

@@ -115,7 +115,10 @@ def simulate_identity(N, k, b, stream):
     return piv
 
 
-@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+ALL_PRECS = [W.FP64, W.FP32, W.BF16X3, W.BF16]
+
+
+@pytest.mark.parametrize("prec", ALL_PRECS)
 def test_identity_matrix_exact(prec):
     """Grid points 64 apart with a unit Gaussian: A = I exactly in any format,
     so pivots follow sampling without replacement and F is exact."""
@@ -128,7 +131,7 @@ def test_identity_matrix_exact(prec):
     assert np.array_equal(F, np.eye(N)[:, want])
 
 
-@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+@pytest.mark.parametrize("prec", ALL_PRECS)
 def test_cluster_matrix_exact(prec):
     sizes = [500, 70, 1300, 1, 220, 9, 3000]
     X, labels = W.clusters(sizes, d=3, seed=4)
@@ -215,3 +218,32 @@ def test_laplace_workload_full_size_fp64():
     ref = oracle_run(X, prob)
     err = assert_parity(F, piv, out, ref)
     print(f"laplace relF={err:.2e} rounds={ref.rounds} trace_err={ref.trace_error:.4e}")
+
+
+def test_vector_unit_gemm_cross_check(monkeypatch):
+    """The register-tiled vector kernels (kept as a cross-check of the matrix
+    cores) reproduce the oracle too."""
+    monkeypatch.setenv("ARPC_GEMM", "valu")
+    X, prob = W.small()
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
+@pytest.mark.parametrize("prec", [W.FP32, W.BF16X3])
+def test_reduced_precision_trace_error(prec):
+    """Reduced-precision modes keep the trace error within 1.05x of the FP64
+    run, both from the factor (tr A - |F|^2) and from the pivots alone
+    (Nystrom residual recomputed in FP64 by the oracle)."""
+    from oracle import nystrom_err
+    X, prob = W.laplace(N=20_000)
+    prob = prob.with_(k=400, b=50)
+    F64, piv64, out64 = gpu_factor(X, prob)
+    Fm, pivm, outm = gpu_factor(X, prob.with_(prec=prec))
+    trA = out64["stats"]["trace_A"]
+    te64 = (trA - np.sum(F64 ** 2)) / trA
+    tem = (trA - np.sum(Fm ** 2)) / trA
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
+    ny64 = nystrom_err(acc, piv64[:out64["stats"]["k_out"]]).sum() / trA
+    nym = nystrom_err(acc, pivm[:outm["stats"]["k_out"]]).sum() / trA
+    print(f"prec={prec} trace err F: {tem:.6e} vs fp64 {te64:.6e}; nystrom {nym:.6e} vs {ny64:.6e}")
+    assert tem <= 1.05 * te64 and nym <= 1.05 * ny64
