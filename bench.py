@@ -39,12 +39,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp32", choices=sorted(PREC_BY_NAME))
+    ap.add_argument("--prec", default="bf16", choices=sorted(PREC_BY_NAME))
     ap.add_argument("--workload", default="mixture", choices=["mixture", "laplace", "small", "sparse_hd"])
     ap.add_argument("--cpu-rounds", type=int, default=2,
                     help="rounds of the oracle timed for the CPU baseline (0 = skip)")
-    ap.add_argument("--compare-fp64", action="store_true",
-                    help="also run one FP64 factorization and report the trace-error ratio")
+    ap.add_argument("--no-compare-fp64", action="store_true",
+                    help="skip the FP64 factorization that the trace-error ratio of a "
+                         "reduced-precision mode is stated against")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the timed region, copy a device buffer of this many MiB "
+                         "once (a reference kernel for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -127,6 +131,13 @@ def main():
             raise RuntimeError(B.arpc_status_str(st))
         return stats.as_dict()
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -164,7 +175,7 @@ def main():
         "trace_error_F": trace_err,
         "kernel_ms_per_step": {c: round(v / args.steps, 3) for c, v in agg["ms_kernel"].items()},
     }
-    if args.compare_fp64 and prec != W.FP64:
+    if not args.no_compare_fp64 and prec != W.FP64:
         p64 = prob.with_(prec=W.FP64)
         out64 = B.factor(Xd, p64)
         F64 = out64["F"][:, : out64["stats"]["k_out"]]

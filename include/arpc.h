@@ -78,7 +78,9 @@ typedef struct arpc_stats {
   int64_t rounds;       /* rounds run */
   int64_t proposals;    /* b * rounds */
   int32_t status;       /* ARPC_OK or ARPC_EARLY_STOP */
-  int32_t reserved;
+  int32_t fused;        /* 1: each round's update GEMM, solve and stores ran as one
+                           kernel (ARPC_BF16X3 / ARPC_BF16 with b <= 256, d <= 16),
+                           timed under the colgemm class; 0: two kernels */
   double trace_A;       /* sum of diag A */
   double trace_resid;   /* sum of the final residual diagonal */
   double ms_total;      /* host wall time of the call */
@@ -86,8 +88,11 @@ typedef struct arpc_stats {
   int64_t launches[ARPC_NUM_KC];   /* launches per class (profiling on) */
   double flops_colgemm; /* algorithmic flops of the update GEMM, sum_r 2 N k_r s_r */
   double flops_trsm;    /* algorithmic flops of the triangular solve, sum_r N s_r^2 */
-  double bytes_colgemm; /* algorithmic HBM bytes of the update GEMM: F read, C written, X read */
-  double bytes_trsm;    /* algorithmic HBM bytes of the triangular solve: C read, G written, norms */
+  double bytes_colgemm; /* algorithmic HBM bytes of the update GEMM: blocked F read, C written,
+                           X read (fused: blocked F and X read, G written to F and to the
+                           blocked copy, row norms written) */
+  double bytes_trsm;    /* algorithmic HBM bytes of the triangular solve: C read, G written
+                           twice, norms (0 when fused) */
 } arpc_stats;
 
 /* Human-readable name of a status code (static storage). */

@@ -31,7 +31,7 @@ class ArpcProblem(C.Structure):
 
 class ArpcStats(C.Structure):
     _fields_ = [("k_out", C.c_int64), ("rounds", C.c_int64), ("proposals", C.c_int64),
-                ("status", C.c_int32), ("reserved", C.c_int32), ("trace_A", C.c_double),
+                ("status", C.c_int32), ("fused", C.c_int32), ("trace_A", C.c_double),
                 ("trace_resid", C.c_double), ("ms_total", C.c_double),
                 ("ms_kernel", C.c_double * NUM_KC), ("launches", C.c_int64 * NUM_KC),
                 ("flops_colgemm", C.c_double), ("flops_trsm", C.c_double),

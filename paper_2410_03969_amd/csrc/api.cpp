@@ -35,10 +35,30 @@ bool use_valu_gemm() {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Persistent workgroups of the fused round kernel: two per compute unit of
+// the current device.
+int fused_grid() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  return 2 * cus;
+}
+
+// ARPC_FUSED=0 turns the one-kernel round product of the BF16 modes off (the
+// two-kernel matrix-core path then runs, as for FP32), for cross-checks.
+bool fused_disabled() {
+  const char* e = getenv("ARPC_FUSED");
+  return e && strcmp(e, "0") == 0;
+}
+
 struct Layout {
   size_t st, u, csum, cpre, props, acc, hist, Fs, H, L, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, P, trace, total;
   int part_cols;
   bool valu;  // vector-unit GEMM kernels instead of the matrix-core ones
+  int ncbt;   // > 0: one-kernel round product with this column-block count
+  int grid;   // persistent workgroups of that kernel (set per call)
 };
 
 inline int64_t nchunks_of(int64_t N) { return (N + CHUNK - 1) / CHUNK; }
@@ -51,9 +71,12 @@ Layout layout_of(const arpc_problem& p) {
   const int64_t nch = nchunks_of(p.N);
   const bool valu = use_valu_gemm() && p.prec <= ARPC_FP32;
   l.valu = valu;
-  l.part_cols = valu ? 64 : mfma_part_cols(p.prec, (int)p.b);
+  l.ncbt = (!valu && !fused_disabled() && p.d <= 16) ? fused_ncbt(p.prec, (int)p.b) : -1;
+  const bool fused = l.ncbt > 0;
+  l.part_cols = valu ? 64 : (fused ? BMAX : mfma_part_cols(p.prec, (int)p.b));
   const int64_t nparts = (p.b + l.part_cols - 1) / l.part_cols;
-  const size_t mb = valu ? 0 : mfma_operand_bytes(p.prec, p.k, (int)p.b);
+  const size_t mb = valu ? 0 : (fused ? fused_operand_bytes(p.prec, p.k, (int)p.b)
+                                      : mfma_operand_bytes(p.prec, p.k, (int)p.b));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -76,7 +99,7 @@ Layout layout_of(const arpc_problem& p) {
   l.Bm1 = take(mb);
   l.Bm2 = take(mb);
   l.Fb = take(valu ? 0 : mfma_blocked_bytes(p.prec, p.N, p.k));
-  l.C = take(valu ? es * p.N * p.b : mfma_blocked_bytes(p.prec, p.N, p.b));
+  l.C = take(valu ? es * p.N * p.b : (fused ? 0 : mfma_blocked_bytes(p.prec, p.N, p.b)));
   l.P = take(sizeof(double) * nparts * p.N);
   l.trace = take(sizeof(double));
   l.total = off;
@@ -185,7 +208,17 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   prof.begin(ARPC_KC_REJECT);
   launch_reject(s, H, b, props, un, st, L, acc, pivots, u, k);
   prof.end();
-  if (l.valu) {  // vector-unit kernels (cross-check path)
+  if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
+    FusedRound fr{F, ws + l.Fb, (k + 31) / 32, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1),
+                  (unsigned char*)(ws + l.Bm2), P, b, l.ncbt, l.grid};
+    prof.begin(ARPC_KC_PREP);
+    launch_prep_xp(s, acc, props, X, d, Xp, st);
+    launch_fused_prep(s, p.prec, fr, props, acc, L, st);
+    prof.end();
+    prof.begin(ARPC_KC_COLGEMM);
+    launch_fused_round(s, p.prec, fr, st);
+    prof.end();
+  } else if (l.valu) {  // vector-unit kernels (cross-check path)
     prof.begin(ARPC_KC_PREP);
     launch_prep<T>(s, Fs, k, acc, props, X, d, Bt, b, Xp, L, b, Bt2, k, st);
     prof.end();
@@ -281,18 +314,28 @@ arpc_status run(const arpc_problem& p, const double* X, T* F, int64_t* pivots, c
     stats->status = (ret == ARPC_EINVAL) ? ARPC_EINVAL : ret;
     stats->trace_A = h.trace_A;
     stats->trace_resid = trace_resid;
+    // algorithmic traffic per round and row: the blocked copy of F read over
+    // k_r columns, the points, G stored twice (F and its blocked copy), the
+    // row norm; the two-kernel path also writes and reads C
     double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0;
     const double es = (double)sizeof(T);
+    const double eb = p.prec == ARPC_FP64 ? 8.0 : (p.prec == ARPC_BF16 ? 2.0 : 4.0);
+    const bool fused = l.ncbt > 0;
     for (int64_t r = 0; r < h.round; ++r) {
       const double sr = hist[r];
       fg += 2.0 * (double)N * kr * sr;
       ft += (double)N * sr * sr;
       if (sr > 0) {
-        bg += (double)N * (kr * es + sr * es + 8.0 * (double)p.d);
-        bt += (double)N * (2.0 * sr * es + 8.0);
+        if (fused) {
+          bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * (es + eb) + 8.0);
+        } else {
+          bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
+          bt += (double)N * (sr * (eb + es + eb) + 8.0);
+        }
       }
       kr += sr;
     }
+    stats->fused = fused ? 1 : 0;
     stats->flops_colgemm = fg;
     stats->flops_trsm = ft;
     stats->bytes_colgemm = bg;
@@ -313,8 +356,9 @@ arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t
   if (!X || !F || !pivots || !ws) return ARPC_EINVAL;
   if (((uintptr_t)X & 7) || ((uintptr_t)F & 7) || ((uintptr_t)pivots & 7) || ((uintptr_t)ws & 255))
     return ARPC_EINVAL;
-  const Layout l = layout_of(*p);
+  Layout l = layout_of(*p);
   if (ws_bytes < l.total) return ARPC_EINVAL;
+  if (l.ncbt > 0) l.grid = fused_grid();
   hipStream_t s = (hipStream_t)stream;
   if (p->prec == ARPC_FP64)
     return run<double>(*p, X, (double*)F, pivots, (char*)ws, l, s, un, stats);

@@ -113,6 +113,38 @@ __device__ __attribute__((always_inline)) inline float kappa_r2_f32(float r2, co
   }
 }
 
+// The four kernels in one branch-free FP32 form (for the fused BF16-mode
+// epilogue, where a per-element switch would multiply the code by four):
+//   t = scale * (use_r ? |x - y| : |x - y|^2),
+//   kappa = (1 + p1 t + p2 t^2) * 2^(-q t).
+// Gaussian: t = r^2 / (2 s^2), p1 = p2 = 0; Laplace: t = r / s, p1 = p2 = 0;
+// Matern-3/2: t = sqrt3 r / s, p1 = 1, p2 = 0; Matern-5/2: t = sqrt5 r / s,
+// p1 = 1, p2 = 1/3 (Section 1.2, Section 3.2).  q = log2(e).
+struct KFast {
+  float scale, p1, p2, q;
+  int use_r;
+};
+
+__host__ inline KFast kfast_of(const KParams& kp) {
+  KFast k{};
+  k.q = 1.4426950408889634f;
+  const double s = kp.sigma;
+  switch (kp.kernel) {
+    case 0: k.scale = (float)(1.0 / (2.0 * s * s)); k.use_r = 0; break;
+    case 1: k.scale = (float)(1.0 / s); k.use_r = 1; break;
+    case 2: k.scale = (float)(1.7320508075688772 / s); k.use_r = 1; k.p1 = 1.f; break;
+    default: k.scale = (float)(2.23606797749979 / s); k.use_r = 1; k.p1 = 1.f; k.p2 = 1.f / 3.f; break;
+  }
+  return k;
+}
+
+__device__ __attribute__((always_inline)) inline float kappa_fast(float r2, const KFast& k) {
+  const float u = k.use_r ? __builtin_amdgcn_sqrtf(r2) : r2;
+  const float t = u * k.scale;
+  const float poly = fmaf(fmaf(k.p2, t, k.p1), t, 1.0f);
+  return poly * __builtin_amdgcn_exp2f(-k.q * t);
+}
+
 // Squared distance by direct differences (a point paired with itself gives 0).
 __device__ __attribute__((always_inline)) inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
   double s = 0.0;

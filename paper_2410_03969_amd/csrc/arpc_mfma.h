@@ -5,6 +5,9 @@
 
 namespace arpc {
 
+// Rows per panel of the panel-blocked layout of the N-row operands.
+constexpr int PH = 256;
+
 // Device pointers and sizes of one factorization used by the matrix-core
 // update GEMM and triangular solve.
 struct MfmaRound {
@@ -27,6 +30,33 @@ struct MfmaRound {
   int b;
   int64_t kmax;
 };
+
+// Device pointers and sizes of the one-kernel round product of the BF16
+// modes (update GEMM, kernel columns, solve and stores in one launch).
+struct FusedRound {
+  void* F;                 // N x k column-major FP32 output factor
+  void* Fb;                // panel-blocked BF16 planes of F (read and written)
+  int64_t nkc;             // 32-column chunks per panel of Fb
+  int64_t N;
+  const double* X;         // N x d points
+  int d;
+  const double* Xp;        // s_r x d accepted points
+  KParams kp;
+  unsigned char* Bm1;      // F(S_r,:)^T in chunks
+  unsigned char* Bm2;      // permuted inverse factor in chunks
+  double* P;               // FP64 row norms of G (one group)
+  int b;
+  int ncbt;                // compiled column-block count (>= ceil(b/16))
+  int grid;                // persistent workgroups
+};
+
+// Column-block count of the fused path for (prec, b), or -1 when the fused
+// path does not apply (FP64/FP32 modes, b > 256).
+int fused_ncbt(int prec, int b);
+size_t fused_operand_bytes(int prec, int64_t kmax, int b);
+void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
+                       const double* L, const RoundState* st);
+void launch_fused_round(hipStream_t s, int prec, const FusedRound& r, const RoundState* st);
 
 size_t mfma_operand_bytes(int prec, int64_t kmax, int b);
 size_t mfma_blocked_bytes(int prec, int64_t N, int64_t cols);

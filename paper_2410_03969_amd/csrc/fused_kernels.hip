@@ -1,0 +1,500 @@
+// One-kernel round product for the BF16 modes (ARPC_BF16, ARPC_BF16X3) on
+// gfx950.  For a tile of 128 rows a workgroup computes, without C ever
+// leaving the registers (Alg. 2, step 3):
+//   1. C^T = Bm1 F^T on the matrix cores, Bm1 = F(S_r,:)^T, then
+//      C = A(:, S_r) - (F F(S_r,:)^T) with the kernel columns evaluated from
+//      the points in the accumulator layout;
+//   2. G^T = Linv C^T on the matrix cores, the accumulators of step 1 serving
+//      directly as the operand (see the slot permutation below);
+//   3. G into F(:, k_r : k_r + s_r) (column-major FP32), into the panel-blocked
+//      BF16 copy of F that the next rounds contract over, and the FP64 row
+//      norms of G for the residual-diagonal update.
+//
+// Workgroups are persistent (two per CU) and walk the row tiles; each F
+// element is read from HBM once per round.  Wavefront w owns 32 rows of the
+// tile and all columns; its F slices are loaded straight from HBM into
+// registers FD chunks ahead.  The small operands (Bm1 chunks, then the chunks
+// of the permuted inverse factor) stream through a two-stage LDS ring shared
+// by the four wavefronts.
+//
+// Slot permutation.  A 16x16x32 BF16 product takes, in lane (g, n), operand
+// values for contraction slots 8g .. 8g+7 of column n.  The accumulator of
+// the update GEMM holds, in lane (g, n), C(row n, 16 cb + 4g + j), j < 4.  For
+// the t-chunk tc of the solve (t = 32 tc .. 32 tc + 31), slot 8g + jj is
+// therefore bound to t = 32 tc + 4g + jj (jj < 4, column block 2 tc) and
+// t = 32 tc + 16 + 4g + jj - 4 (jj >= 4, column block 2 tc + 1); the inverse
+// factor is stored with the same slot order, so the product is exact in any
+// order and no lane exchange is needed.
+#include "arpc_common.h"
+#include "arpc_mfma.h"
+
+namespace arpc {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr int FW = 4;            // wavefronts per workgroup
+constexpr int FNB = 2;           // 16-row tiles per wavefront
+constexpr int FROWS = FW * FNB * 16;  // rows per workgroup tile
+constexpr int FKC = 32;          // contraction chunk
+constexpr int FCROW = 80;        // LDS bytes per staged column and plane (64 + 16 padding)
+constexpr int FGROW = 64;        // global bytes per operand column and plane
+constexpr int EROW = FNB * 16 + 1;    // padded row count of the store window
+
+struct FusedArgs {
+  const __bf16* Fb;         // panel-blocked BF16 planes of F
+  int64_t nkc;              // chunks per panel of Fb
+  int64_t N;
+  const unsigned char* Bm1; // F(S_r,:)^T in chunks
+  const unsigned char* Bm2; // permuted inverse factor in chunks
+  const double* X;          // N x d
+  int d;
+  const double* Xp;         // s_r x d accepted points
+  KFast kf;
+  float* Fu;                // F, column-major, ld N
+  __bf16* Fbw;              // Fb (written)
+  double* P;                // FP64 row norms of G
+  const RoundState* st;
+  int ntiles;
+};
+
+// Slot of contraction index t (0..31) inside a t-chunk of the solve.
+__host__ __device__ inline int solve_slot(int t) {
+  return 8 * ((t & 15) >> 2) + (t & 3) + ((t & 16) ? 4 : 0);
+}
+
+__device__ inline void split_hi_lo(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <int PASSES, int NCBT, int DX, int FD>
+__global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_round(FusedArgs a) {
+  constexpr int SPL = PASSES == 3 ? 2 : 1;
+  constexpr int CP = NCBT * 16;                 // padded column count
+  constexpr int NT = (NCBT + 1) / 2;            // t-chunks of the solve
+  constexpr int NPASS = 1;                      // solve passes (see below)
+  constexpr int STAGE = SPL * CP * FCROW;       // LDS bytes per ring stage
+  constexpr int PIECES = SPL * CP * (FGROW / 16);
+  constexpr int PER_T = (PIECES + 64 * FW - 1) / (64 * FW);
+  constexpr int PLANE_E = PH * FKC;             // elements per plane of a blocked chunk
+  constexpr int CHUNK_E = SPL * PLANE_E;
+  constexpr int RING = (2 * STAGE > FW * 64 * EROW * 4) ? 2 * STAGE : FW * 64 * EROW * 4;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[RING + CP * DX * 4];
+  float* xps = (float*)(lds + RING);
+
+  const RoundState* st = a.st;
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  if (s == 0) return;
+  const int64_t kr = st->k_r;
+  const int64_t nk = (kr + FKC - 1) / FKC;      // contraction chunks of the update GEMM
+  const int64_t N = a.N;
+  const int d = a.d;
+  const int tid0 = threadIdx.x, w = tid0 >> 6;
+
+  // accepted points in FP32, zero-padded to DX coordinates and CP columns
+  for (int q = tid0; q < CP * DX; q += 64 * FW) {
+    const int c = q / DX, t = q % DX;
+    xps[q] = (c < s && t < d) ? (float)a.Xp[(int64_t)c * d + t] : 0.f;
+  }
+
+  // ---- small-operand ring: stream position q < nk is chunk q of Bm1, then
+  // the NT chunks of the inverse factor
+  u4 sbuf[PER_T];
+  int tid = tid0;
+  auto fetch = [&](int64_t q) {
+    const unsigned char* src = (q < nk) ? a.Bm1 + (size_t)q * SPL * CP * FGROW
+                                        : a.Bm2 + (size_t)((q - nk) % NT) * SPL * CP * FGROW;
+#pragma unroll
+    for (int r = 0; r < PER_T; ++r) {
+      const int o = tid + r * 64 * FW;
+      if (o < PIECES) sbuf[r] = *(const u4*)(src + (size_t)o * 16);
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < PER_T; ++r) {
+      const int o = tid + r * 64 * FW;
+      const int pc = o >> 2, qq = o & 3;       // (plane, column) and 16-byte piece
+      if (o < PIECES) *(u4*)(lds + buf * STAGE + pc * FCROW + qq * 16) = sbuf[r];
+    }
+  };
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    // Lane-dependent values are re-derived in every tile: hoisted out of the
+    // loop they would stay live across it and spill.
+    tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, l16 = lane & 15, g = lane >> 4;
+    const int64_t row_w = (int64_t)tile * FROWS + w * (FNB * 16);
+    // this lane's rows (tiles nb = 0, 1): row_w + 16 nb + l16
+    float xr[FNB][DX];
+#pragma unroll
+    for (int nb = 0; nb < FNB; ++nb) {
+      int64_t r = row_w + nb * 16 + l16;
+      if (r >= N) r = N - 1;
+#pragma unroll
+      for (int t = 0; t < DX; ++t) xr[nb][t] = (t < d) ? (float)a.X[r * d + t] : 0.f;
+    }
+
+    f4 acc[FNB][NCBT];
+#pragma unroll
+    for (int nb = 0; nb < FNB; ++nb)
+#pragma unroll
+      for (int cb = 0; cb < NCBT; ++cb) acc[nb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // F slices: rows row_w + l16 and row_w + 16 + l16 share a 256-row panel
+    const int64_t r0 = row_w + l16;
+    const __bf16* rb = a.Fb + (size_t)(r0 / PH) * a.nkc * CHUNK_E + (size_t)(r0 % PH) * FKC + 8 * g;
+    bf8 fr[FD][FNB][SPL];
+    auto loadF = [&](bf8 (&f)[FNB][SPL], int64_t ch) {
+#pragma unroll
+      for (int nb = 0; nb < FNB; ++nb)
+#pragma unroll
+        for (int pl = 0; pl < SPL; ++pl)
+          f[nb][pl] = *(const bf8*)(rb + (size_t)ch * CHUNK_E + pl * PLANE_E + nb * 16 * FKC);
+    };
+
+    fetch(0);
+#pragma unroll
+    for (int u = 0; u < FD - 1; ++u)
+      if (u < nk) loadF(fr[u], u);
+    commit(0);
+    __syncthreads();
+
+    // ---- 1. update GEMM
+    for (int64_t ch0 = 0; ch0 < nk; ch0 += FD) {
+#pragma unroll
+      for (int u = 0; u < FD; ++u) {
+        const int64_t ch = ch0 + u;
+        if (ch < nk) {
+          // the small-operand fetch goes first: the wait before its commit
+          // (in-order load counter) then leaves the F loads in flight
+          fetch(ch + 1);
+          if (ch + FD - 1 < nk) loadF(fr[(u + FD - 1) % FD], ch + FD - 1);
+          const unsigned char* L = lds + (ch & 1) * STAGE + l16 * FCROW + g * 16;
+          // operand reads one column block ahead of the products (all of them
+          // hoisted at once would hold NCBT operand slices in registers)
+          bf8 ahn = *(const bf8*)L, aln;
+          if constexpr (PASSES == 3) aln = *(const bf8*)(L + CP * FCROW);
+#pragma unroll
+          for (int cb = 0; cb < NCBT; ++cb) {
+            const bf8 ah = ahn;
+            bf8 al;
+            if constexpr (PASSES == 3) al = aln;
+            if (cb + 1 < NCBT) {
+              ahn = *(const bf8*)(L + (cb + 1) * 16 * FCROW);
+              if constexpr (PASSES == 3) aln = *(const bf8*)(L + CP * FCROW + (cb + 1) * 16 * FCROW);
+            }
+#pragma unroll
+            for (int nb = 0; nb < FNB; ++nb) {
+              acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr[u][nb][0], acc[nb][cb], 0, 0, 0);
+              if constexpr (PASSES == 3) {
+                acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr[u][nb][1], acc[nb][cb], 0, 0, 0);
+                acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr[u][nb][0], acc[nb][cb], 0, 0, 0);
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          commit((ch + 1) & 1);
+          __syncthreads();
+        }
+      }
+    }
+
+    // ---- kernel columns and solve.  (A pass per 16-row tile would halve the
+    // live solve state but streams the inverse factor twice; with this
+    // compiler it spilled more, so both tiles are solved in one pass.)
+    f4 gacc[FNB][NCBT];
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+      constexpr int NPB = FNB / NPASS;                // row tiles per pass
+      const int nb0 = pass * NPB;
+      // kernel columns: C = kappa(x_row, x_c) - acc, zero for c >= s, as the
+      // BF16 operand slices of the solve (slot order above)
+      bf8 ch_[NPB][NT][SPL];
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) {
+        f8 cv[NPB];
+#pragma unroll
+        for (int half = 0; half < 2; ++half)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int cb = 2 * tc + half;
+            if (cb < NCBT) {
+              const int c = cb * 16 + 4 * g + j;
+              float xp[DX];
+#pragma unroll
+              for (int t = 0; t < DX; ++t) xp[t] = xps[c * DX + t];
+#pragma unroll
+              for (int ib = 0; ib < NPB; ++ib) {
+                float r2 = 0.f;
+#pragma unroll
+                for (int t = 0; t < DX; ++t) {
+                  const float e = xr[nb0 + ib][t] - xp[t];
+                  r2 = fmaf(e, e, r2);
+                }
+                // evaluated for every column (the padding coordinates are
+                // zero) and then selected: no lane mask per element
+                const float kv = kappa_fast(r2, a.kf) - acc[nb0 + ib][cb][j];
+                cv[ib][4 * half + j] = (c < s) ? kv : 0.f;
+              }
+            } else {
+#pragma unroll
+              for (int ib = 0; ib < NPB; ++ib) cv[ib][4 * half + j] = 0.f;
+            }
+          }
+#pragma unroll
+        for (int ib = 0; ib < NPB; ++ib) {
+          ch_[ib][tc][0] = __builtin_convertvector(cv[ib], bf8);
+          if constexpr (SPL == 2)
+            ch_[ib][tc][1] = __builtin_convertvector(cv[ib] - __builtin_convertvector(ch_[ib][tc][0], f8), bf8);
+        }
+      }
+      // Materialise the operand slices here: sunk into the solve loop, their
+      // computation would keep the update-GEMM accumulators alive beside the
+      // solve accumulators.
+#pragma unroll
+      for (int ib = 0; ib < NPB; ++ib)
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+          for (int pl = 0; pl < SPL; ++pl) asm volatile("" : "+v"(ch_[ib][tc][pl]));
+
+      // ---- 2. solve: G^T = Linv C^T over the lower-triangular blocks
+#pragma unroll
+      for (int ib = 0; ib < NPB; ++ib)
+#pragma unroll
+        for (int mt = 0; mt < NCBT; ++mt) gacc[nb0 + ib][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) {
+        const int64_t q = nk + pass * NT + tc;
+        const bool more = tc + 1 < NT || pass + 1 < NPASS;
+        if (more) fetch(q + 1);
+        const unsigned char* L = lds + (q & 1) * STAGE;
+#pragma unroll
+        for (int mt = 0; mt < NCBT; ++mt) {
+          if (32 * tc <= 16 * mt + 15) {
+            const bf8 ah = *(const bf8*)(L + (mt * 16 + l16) * FCROW + g * 16);
+            bf8 al;
+            if constexpr (PASSES == 3) al = *(const bf8*)(L + CP * FCROW + (mt * 16 + l16) * FCROW + g * 16);
+#pragma unroll
+            for (int ib = 0; ib < NPB; ++ib) {
+              f4& gq = gacc[nb0 + ib][mt];
+              gq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ch_[ib][tc][0], gq, 0, 0, 0);
+              if constexpr (PASSES == 3) {
+                gq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ch_[ib][tc][1], gq, 0, 0, 0);
+                gq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ch_[ib][tc][0], gq, 0, 0, 0);
+              }
+            }
+          }
+        }
+        if (more) commit((q + 1) & 1);
+        __syncthreads();
+      }
+    }
+
+    // ---- 3. row norms, then the stores through a per-wavefront LDS window
+    // of 64 columns (the ring is free after the last barrier of the solve).
+    // Lane (g, l16) holds G(row_w + 16 nb + l16, i) for i = 16 mt + 4 g + j.
+#pragma unroll
+    for (int nb = 0; nb < FNB; ++nb) {
+      double g2 = 0.0;
+#pragma unroll
+      for (int mt = 0; mt < NCBT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = gacc[nb][mt][j];
+          g2 += (mt * 16 + 4 * g + j < s) ? (double)v * (double)v : 0.0;
+        }
+      g2 += __shfl_xor(g2, 16, 64);
+      g2 += __shfl_xor(g2, 32, 64);
+      const int64_t row = row_w + nb * 16 + l16;
+      if (row < N && g == 0) a.P[row] = g2;
+    }
+    float* E = (float*)lds + w * (64 * EROW);   // E[col][row], 64 columns x 32 rows
+    const int nrows = (N - row_w) < (FNB * 16) ? (int)(N - row_w) : FNB * 16;
+#pragma unroll
+    for (int w0 = 0; w0 < CP; w0 += 64) {
+#pragma unroll
+      for (int mt = w0 / 16; mt < w0 / 16 + 4 && mt < NCBT; ++mt)
+#pragma unroll
+        for (int nb = 0; nb < FNB; ++nb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) E[(mt * 16 - w0 + 4 * g + j) * EROW + nb * 16 + l16] = gacc[nb][mt][j];
+      int wv = s - w0;
+      if (wv > 64) wv = 64;
+      // F, column-major: two columns per store, 32 consecutive rows each
+      for (int cc = lane >> 5; cc < wv; cc += 2) {
+        const int rl = lane & 31;
+        if (rl < nrows) a.Fu[(kr + w0 + cc) * N + row_w + rl] = E[cc * EROW + rl];
+      }
+      // blocked BF16 copy: one row per store, 64 consecutive columns
+      if (lane < wv)
+        for (int rl = 0; rl < nrows; ++rl) {
+          const int64_t row = row_w + rl;
+          const int64_t col = kr + w0 + lane;
+          __bf16* p = a.Fbw + (((row / PH) * a.nkc + col / FKC) * SPL) * (int64_t)PLANE_E + (row % PH) * FKC + col % FKC;
+          __bf16 hi, lo;
+          split_hi_lo(E[lane * EROW + rl], hi, lo);
+          p[0] = hi;
+          if constexpr (SPL == 2) p[PLANE_E] = lo;
+        }
+    }
+    // zeros after the last column up to the end of its chunk
+    {
+      const int64_t zbeg = kr + s, zend = (kr + s + FKC - 1) / FKC * FKC;
+      const int nz = (int)(zend - zbeg);
+      for (int q = lane; q < nz * nrows; q += 64) {
+        const int64_t row = row_w + q / nz, col = zbeg + q % nz;
+        __bf16* p = a.Fbw + (((row / PH) * a.nkc + col / FKC) * SPL) * (int64_t)PLANE_E + (row % PH) * FKC + col % FKC;
+        p[0] = (__bf16)0.f;
+        if constexpr (SPL == 2) p[PLANE_E] = (__bf16)0.f;
+      }
+    }
+    __syncthreads();   // the window area is the ring of the next tile
+  }
+}
+
+// Bm1 chunk j, column c: the blocked slice of F at row S_r(c) (zero for c >= s).
+template <int SPL>
+__global__ __launch_bounds__(256) void k_fused_bm1(const __bf16* __restrict__ Fb, int64_t nkc,
+                                                   const int64_t* __restrict__ props,
+                                                   const int32_t* __restrict__ acc, int CP,
+                                                   unsigned char* __restrict__ Bm1, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int64_t nk = (st->k_r + FKC - 1) / FKC;
+  const int64_t per_chunk = (int64_t)SPL * CP * 4;  // 16-byte pieces
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nk * per_chunk; o += (int64_t)gridDim.x * 256) {
+    const int64_t j = o / per_chunk;
+    const int rem = (int)(o % per_chunk);
+    const int plane = rem / (CP * 4), c = (rem / 4) % CP, q = rem & 3;
+    u4 v = u4{0, 0, 0, 0};
+    if (c < s) {
+      const int64_t row = props[acc[c]];
+      v = *(const u4*)(Fb + (((row / PH) * nkc + j) * SPL + plane) * (int64_t)(PH * FKC) + (row % PH) * FKC + 8 * q);
+    }
+    *(u4*)(Bm1 + (size_t)o * 16) = v;
+  }
+}
+
+// Inverse of the s x s lower factor L (column-major, ld b), one workgroup per
+// column t: forward substitution, then Linv(i, t) stored at chunk t / 32, slot
+// solve_slot(t % 32), column i (zero outside i, t < s and below the diagonal).
+template <int SPL>
+__global__ __launch_bounds__(64) void k_fused_linv(const double* __restrict__ L, int b, int CP,
+                                                   unsigned char* __restrict__ Bm2, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  __shared__ double x[BMAX];
+  if (c < s) {
+    for (int i = lane; i < s; i += 64) x[i] = 0.0;
+    __syncthreads();
+    if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
+    __syncthreads();
+    for (int i = c + 1; i < s; ++i) {
+      double p = 0.0;
+      for (int t = c + lane; t < i; t += 64) p += L[(int64_t)t * b + i] * x[t];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+      if (lane == 0) x[i] = -p / L[(int64_t)i * b + i];
+      __syncthreads();
+    }
+  }
+  const int tc = c / FKC, slot = solve_slot(c % FKC);
+  for (int i = lane; i < CP; i += 64) {
+    const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
+    __bf16 hi, lo;
+    split_hi_lo((float)v, hi, lo);
+    unsigned char* base = Bm2 + (size_t)tc * SPL * CP * FGROW + (size_t)i * FGROW + slot * 2;
+    *(__bf16*)base = hi;
+    if (SPL == 2) *(__bf16*)(base + (size_t)CP * FGROW) = lo;
+  }
+}
+
+// Column-block counts with a compiled instance.
+constexpr int kNcbt[] = {2, 4, 8, 13, 16};
+
+int ncbt_for(int b) {
+  const int need = (b + 15) / 16;
+  for (int v : kNcbt)
+    if (v >= need) return v;
+  return -1;
+}
+
+template <int PASSES, int NCBT, int DX>
+void launch_fused_t(hipStream_t s, const FusedRound& r, const RoundState* st) {
+  // F chunks in flight: the three-product mode spends three times the matrix
+  // time per chunk, so one chunk ahead hides as much latency
+  constexpr int FD = PASSES == 3 ? 2 : 4;
+  FusedArgs a{(const __bf16*)r.Fb, r.nkc, r.N, r.Bm1, r.Bm2, r.X, r.d, r.Xp, kfast_of(r.kp), (float*)r.F,
+              (__bf16*)r.Fb, r.P, st, (int)((r.N + FROWS - 1) / FROWS)};
+  int grid = r.grid;
+  if (grid > a.ntiles) grid = a.ntiles;
+  hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, FD>), dim3(grid), dim3(64 * FW), 0, s, a);
+}
+
+template <int PASSES, int NCBT>
+void launch_fused_d(hipStream_t s, const FusedRound& r, const RoundState* st) {
+  if (r.d <= 8) launch_fused_t<PASSES, NCBT, 8>(s, r, st);
+  else launch_fused_t<PASSES, NCBT, 16>(s, r, st);
+}
+
+template <int PASSES>
+void launch_fused_p(hipStream_t s, const FusedRound& r, const RoundState* st) {
+  switch (r.ncbt) {
+    case 2: launch_fused_d<PASSES, 2>(s, r, st); break;
+    case 4: launch_fused_d<PASSES, 4>(s, r, st); break;
+    case 8: launch_fused_d<PASSES, 8>(s, r, st); break;
+    case 13: launch_fused_d<PASSES, 13>(s, r, st); break;
+    default: launch_fused_d<PASSES, 16>(s, r, st); break;
+  }
+}
+
+}  // namespace
+
+int fused_ncbt(int prec, int b) {
+  if (prec != 2 && prec != 3) return -1;
+  return ncbt_for(b);
+}
+
+size_t fused_operand_bytes(int prec, int64_t kmax, int b) {
+  const int ncbt = fused_ncbt(prec, b);
+  if (ncbt < 0) return 0;
+  const int spl = prec == 2 ? 2 : 1;
+  const int64_t cp = 16 * ncbt;
+  const int64_t chunks = (kmax + FKC - 1) / FKC;
+  const int64_t nt = (ncbt + 1) / 2;
+  const int64_t m = chunks > nt ? chunks : nt;
+  return (size_t)m * spl * cp * FGROW;
+}
+
+void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
+                       const double* L, const RoundState* st) {
+  const int cp = 16 * r.ncbt;
+  const int nt = (r.ncbt + 1) / 2;
+  if (prec == 2) {
+    hipLaunchKernelGGL(k_fused_bm1<2>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
+                       r.Bm1, st);
+    hipLaunchKernelGGL(k_fused_linv<2>, dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
+  } else {
+    hipLaunchKernelGGL(k_fused_bm1<1>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
+                       r.Bm1, st);
+    hipLaunchKernelGGL(k_fused_linv<1>, dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
+  }
+}
+
+void launch_fused_round(hipStream_t s, int prec, const FusedRound& r, const RoundState* st) {
+  if (prec == 2) launch_fused_p<3>(s, r, st);
+  else launch_fused_p<1>(s, r, st);
+}
+
+}  // namespace arpc

@@ -88,11 +88,9 @@ enum { MODE_COLGEMM = 0, MODE_TRSM = 1 };
 // scratch C).  Rows are grouped in panels of PH = 256; inside a panel the
 // contraction index runs in chunks of KC; a chunk holds SPLANES planes, and in
 // a plane each row stores its KC values contiguously.  One row panel of the
-// whole factor is a single contiguous region.  In the 16x16x4 products the
+// whole factor is a single contiguous region (PH rows per panel).  In the 16x16x4 products the
 // four values a lane supplies over four successive steps are adjacent indices
 // (lane group g supplies 4g .. 4g+3); the staged Bm is read the same way.
-constexpr int PH = 256;
-
 template <class Pol>
 __host__ __device__ inline size_t blk_offset(int64_t row, int64_t k, int64_t nkc, int plane) {
   return (((size_t)((row / PH) * nkc + k / Pol::KC) * Pol::SPLANES + plane) * PH + (size_t)(row % PH)) * Pol::KC +

@@ -229,7 +229,57 @@ def test_vector_unit_gemm_cross_check(monkeypatch):
     assert_parity(F, piv, out, oracle_run(X, prob))
 
 
-@pytest.mark.parametrize("prec", [W.FP32, W.BF16X3])
+# (b, d): one case per compiled column-block count of the one-kernel round
+# product (2, 4, 8, 13, 16 blocks of 16 columns) and both coordinate widths.
+FUSED_CASES = [(20, 3), (50, 8), (120, 12), (200, 8), (250, 16)]
+# Relative Frobenius error of the first columns against the FP64 factor of the
+# same pivots: three-product BF16 carries about 2^-17 relative error per
+# product (FP32-class); one BF16 product about 2^-9 per operand.
+FUSED_TOL = {W.BF16X3: 2e-4, W.BF16: 5e-2}
+
+
+@pytest.mark.parametrize("prec", [W.BF16X3, W.BF16])
+@pytest.mark.parametrize("b,d", FUSED_CASES)
+def test_fused_round_factor_consistent_with_its_pivots(prec, b, d):
+    """The BF16 modes run the update GEMM, the solve and the stores as one
+    kernel: its factor equals the FP64 factor of the pivots it chose, on
+    sampled rows, over row counts that leave a ragged last tile and panel."""
+    rng = np.random.default_rng(1000 + b)
+    N = 6151
+    X = rng.uniform(0.0, 1.0, size=(N, d))
+    # Laplace kernel: a slowly decaying spectrum, so the rank stays far above k
+    prob = W.Problem(N=N, d=d, k=min(3 * b, 600), b=b, kernel=W.LAPLACE_L2, sigma=0.5,
+                     seed=11, prec=prec)
+    F, piv, out = gpu_factor(X, prob)
+    assert out["stats"]["fused"] == 1
+    k_out = out["stats"]["k_out"]
+    assert k_out == prob.k and len(set(piv[:k_out].tolist())) == k_out
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
+    rows = np.concatenate([np.random.default_rng(0).choice(N, 150, replace=False), np.arange(N - 40, N)])
+    ncols = min(k_out, 2 * b)
+    ref = factor_from_pivots(acc, piv[:ncols], rows=rows)
+    err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
+    print(f"fused prec={prec} b={b} d={d} cols={ncols} relF={err:.3e}")
+    assert err < FUSED_TOL[prec], err
+    # the residual trace from the factor stays a valid bound
+    trA = out["stats"]["trace_A"]
+    assert np.sum(F ** 2) <= trA * (1 + 1e-3)
+
+
+def test_fused_and_two_kernel_paths_agree_on_exact_matrix(monkeypatch):
+    """On the exact cluster matrix both BF16 round products recover the same
+    rank and pivots (a round-off independent answer)."""
+    X, labels = W.clusters([40] * 30, d=6, spacing=50.0, seed=5)
+    prob = W.Problem(N=X.shape[0], d=6, k=30, b=16, kernel=W.GAUSSIAN, sigma=0.5, seed=3, prec=W.BF16)
+    F1, piv1, out1 = gpu_factor(X, prob)
+    monkeypatch.setenv("ARPC_FUSED", "0")
+    F2, piv2, out2 = gpu_factor(X, prob)
+    assert out1["stats"]["fused"] == 1 and out2["stats"]["fused"] == 0
+    assert np.array_equal(piv1, piv2)
+    assert sorted(labels[piv1[:30]].tolist()) == list(range(30))
+
+
+@pytest.mark.parametrize("prec", [W.FP32, W.BF16X3, W.BF16])
 def test_reduced_precision_trace_error(prec):
     """Reduced-precision modes keep the trace error within 1.05x of the FP64
     run, both from the factor (tr A - |F|^2) and from the pivots alone
