@@ -84,7 +84,8 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   constexpr int PLANE_E = PH * FKC;             // elements per plane of a blocked chunk
   constexpr int CHUNK_E = SPL * PLANE_E;
   constexpr int RING = (2 * STAGE > FW * 64 * EROW * 4) ? 2 * STAGE : FW * 64 * EROW * 4;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[RING + CP * DX * 4];
+  constexpr int DUMMY = RING + CP * DX * 4;      // 16-byte sink of surplus staging pieces
+  __shared__ __attribute__((aligned(16))) unsigned char lds[DUMMY + 16];
   float* xps = (float*)(lds + RING);
 
   const RoundState* st = a.st;
@@ -110,10 +111,13 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   auto fetch = [&](int64_t q) {
     const unsigned char* src = (q < nk) ? a.Bm1 + (size_t)q * SPL * CP * FGROW
                                         : a.Bm2 + (size_t)((q - nk) % NT) * SPL * CP * FGROW;
+    // every thread issues the same loads (a piece index past the stage is
+    // clamped and its value dropped at the commit), so the number of loads in
+    // flight is the same on every path and the waits stay exact
 #pragma unroll
     for (int r = 0; r < PER_T; ++r) {
       const int o = tid + r * 64 * FW;
-      if (o < PIECES) sbuf[r] = *(const u4*)(src + (size_t)o * 16);
+      sbuf[r] = *(const u4*)(src + (size_t)(o < PIECES ? o : PIECES - 1) * 16);
     }
   };
   auto commit = [&](int buf) {
@@ -121,7 +125,9 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     for (int r = 0; r < PER_T; ++r) {
       const int o = tid + r * 64 * FW;
       const int pc = o >> 2, qq = o & 3;       // (plane, column) and 16-byte piece
-      if (o < PIECES) *(u4*)(lds + buf * STAGE + pc * FCROW + qq * 16) = sbuf[r];
+      // unguarded as well: surplus pieces go to a dummy slot
+      const int dst = o < PIECES ? buf * STAGE + pc * FCROW + qq * 16 : DUMMY;
+      *(u4*)(lds + dst) = sbuf[r];
     }
   };
 
@@ -160,23 +166,26 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
           f[nb][pl] = *(const bf8*)(rb + (size_t)ch * CHUNK_E + pl * PLANE_E + nb * 16 * FKC);
     };
 
+    // ---- 1. update GEMM.  The loop body is straight-line in its loads: each
+    // iteration fetches the next small-operand chunk and loads the F chunk
+    // FD - 1 ahead (clamped to the last chunk near the end; the surplus loads
+    // are never consumed); only the products are guarded.  The
+    // load counter is in-order, so the fetch goes first: the wait before its
+    // commit leaves the F loads in flight.
+    const int64_t nkl = nk > 0 ? nk - 1 : 0;       // last valid chunk index
     fetch(0);
 #pragma unroll
-    for (int u = 0; u < FD - 1; ++u)
-      if (u < nk) loadF(fr[u], u);
+    for (int u = 0; u < FD - 1; ++u) loadF(fr[u], u < nkl ? u : nkl);
     commit(0);
     __syncthreads();
 
-    // ---- 1. update GEMM
     for (int64_t ch0 = 0; ch0 < nk; ch0 += FD) {
 #pragma unroll
       for (int u = 0; u < FD; ++u) {
         const int64_t ch = ch0 + u;
+        fetch(ch + 1 < nk ? ch + 1 : nk);
+        loadF(fr[(u + FD - 1) % FD], ch + FD - 1 < nkl ? ch + FD - 1 : nkl);
         if (ch < nk) {
-          // the small-operand fetch goes first: the wait before its commit
-          // (in-order load counter) then leaves the F loads in flight
-          fetch(ch + 1);
-          if (ch + FD - 1 < nk) loadF(fr[(u + FD - 1) % FD], ch + FD - 1);
           const unsigned char* L = lds + (ch & 1) * STAGE + l16 * FCROW + g * 16;
           // operand reads one column block ahead of the products (all of them
           // hoisted at once would hold NCBT operand slices in registers)
@@ -201,9 +210,12 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
             }
             __builtin_amdgcn_sched_barrier(0);
           }
-          commit((ch + 1) & 1);
-          __syncthreads();
         }
+        // unguarded: past the last chunk the fetch repeats the first chunk of
+        // the inverse factor (already committed), and no product reads the
+        // buffer written here
+        commit((ch + 1) & 1);
+        __syncthreads();
       }
     }
 
