@@ -13,7 +13,6 @@ namespace arpc {
 constexpr int CHUNK = 1024;
 // Largest block size whose b x b residual submatrix (lower triangle, FP64)
 // fits the 160 KiB of LDS of one gfx950 workgroup: 200*201/2*8 = 160800 bytes.
-constexpr int REJECT_LDS_BMAX = 200;
 constexpr int BMAX = 1024;
 
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_EARLY = 2, ST_NOUNIF = 3 };

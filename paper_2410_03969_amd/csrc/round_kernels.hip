@@ -5,6 +5,8 @@
 // the end-of-round bookkeeping.  Every kernel reads the device-resident
 // RoundState and returns at once when the run has stopped, so the host can
 // enqueue rounds without synchronising.
+#include <type_traits>
+
 #include "arpc_common.h"
 #include "arpc_launch.h"
 #include "arpc_mfma.h"
@@ -241,20 +243,12 @@ __global__ __launch_bounds__(256) void k_gather_H(const double* __restrict__ X, 
 // ------------------------------------------------- RejectionSampleSubmatrix
 // Alg. 1 on the b x b residual submatrix, in one workgroup, right-looking and
 // in place: accepted column i is scaled by 1/sqrt(h_ii) and the trailing
-// lower triangle receives the rank-one Schur update.  Storage: the lower
-// triangle packed by columns in LDS (b <= REJECT_LDS_BMAX) or the full
-// column-major matrix in global memory.
+// lower triangle receives the rank-one Schur update.  Storage: register blocks
+// (b <= 248, below) or the full column-major matrix in global memory.
 // Rules beyond the printed test u_i * V < h_ii: a proposal equal to one
 // already accepted in this round is rejected, and at most k - k_r proposals are
 // accepted.  Outputs: accepted local indices, the dense lower Cholesky factor
 // L of H(T,T) (column-major, ld b), the new pivots, u = 0 at the new pivots.
-struct PackedLDS {
-  double* p;
-  int b;
-  __device__ inline double& at(int j, int i) const {  // j >= i
-    return p[(int64_t)i * b - ((int64_t)i * (i - 1)) / 2 + (j - i)];
-  }
-};
 struct FullGlobal {
   double* p;
   int b;
@@ -318,22 +312,146 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
   if (tid == 0) st->s_r = nacc;
 }
 
-__global__ __launch_bounds__(1024) void k_reject_lds(const double* __restrict__ H, int b,
-                                                     const int64_t* __restrict__ props, Unif un,
-                                                     RoundState* st, double* __restrict__ Lout,
-                                                     int32_t* __restrict__ acc_out,
-                                                     int64_t* __restrict__ pivots, double* __restrict__ u,
-                                                     int64_t kmax) {
+// Register-blocked form for b <= 248.  The lower triangle is cut into 8 x 8
+// blocks; each of the 512 threads owns at most one block (column-major
+// triangular order) and keeps it in registers.  Before step i the owners of
+// column i publish it (as updated by the earlier steps) in a double-buffered
+// LDS column; every thread then evaluates the acceptance test of proposal i
+// identically, and an accepted column, scaled by 1/sqrt(h_ii), updates the
+// owned trailing blocks.  One barrier per proposal.  The scaled accepted
+// columns are kept in H (no longer needed once in registers) and compacted
+// into L(T,T) at the end.
+constexpr int RB = 8;                 // block edge
+constexpr int REJECT_REG_THREADS = 512;
+constexpr int REJECT_REG_BMAX = 248;  // 31 * 32 / 2 = 496 blocks <= 512 threads
+
+__global__ __launch_bounds__(REJECT_REG_THREADS) void k_reject_reg(double* __restrict__ H, int b,
+                                                                   const int64_t* __restrict__ props, Unif un,
+                                                                   RoundState* st, double* __restrict__ Lout,
+                                                                   int32_t* __restrict__ acc_out,
+                                                                   int64_t* __restrict__ pivots,
+                                                                   double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
-  __shared__ double Hp[REJECT_LDS_BMAX * (REJECT_LDS_BMAX + 1) / 2];
-  __shared__ unsigned char tk[REJECT_LDS_BMAX];
-  __shared__ short accl[REJECT_LDS_BMAX];
-  __shared__ int dec[2];
-  PackedLDS S{Hp, b};
-  for (int i = 0; i < b; ++i)
-    for (int j = i + threadIdx.x; j < b; j += blockDim.x) S.at(j, i) = H[(int64_t)i * b + j];
+  __shared__ double col[2][REJECT_REG_BMAX + RB];
+  __shared__ double ul[REJECT_REG_BMAX], Vs[REJECT_REG_BMAX];
+  __shared__ short prv[REJECT_REG_BMAX], accl[REJECT_REG_BMAX];
+  __shared__ unsigned char tk[REJECT_REG_BMAX];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t kr = st->k_r, round = st->round;
+  const int cap = (int)((kmax - kr) < b ? (kmax - kr) : b);
+  const int nbb = (b + RB - 1) / RB;
+  const int nblk = nbb * (nbb + 1) / 2;
+
+  // owned block (bj, bl), bj >= bl, or none
+  int bj = -1, bl = -1;
+  if (tid < nblk) {
+    int r = (int)((sqrt(8.0 * tid + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > tid) --r;
+    while ((r + 1) * (r + 2) / 2 <= tid) ++r;
+    bj = r;
+    bl = tid - r * (r + 1) / 2;
+  }
+  double v[RB][RB];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < RB; ++cc) {
+      const int j = RB * bj + rr, l = RB * bl + cc;
+      v[rr][cc] = (bj >= 0 && j < b && l <= j) ? H[(int64_t)l * b + j] : 0.0;
+    }
+  if (tid < b) {
+    ul[tid] = H[(int64_t)tid * b + tid];
+    Vs[tid] = stream_uniform(un, 2 * (int64_t)b * round + b + tid);
+    const int64_t me = props[tid];
+    int p = -1;
+    for (int q = tid - 1; q >= 0; --q)
+      if (props[q] == me) { p = q; break; }
+    prv[tid] = (short)p;
+    tk[tid] = 0;
+  }
+  // rows past b of the column buffers stay zero (read by edge blocks)
+  for (int q = tid; q < 2 * (REJECT_REG_BMAX + RB); q += nthr) (&col[0][0])[q] = 0.0;
   __syncthreads();
-  reject_body(S, b, props, un, st, Lout, acc_out, pivots, u, kmax, tk, dec, accl);
+
+  // publish column RB * I + CC (its current values) into buffer CC & 1; the
+  // column inside the block is a compile-time index (a runtime index into v
+  // would move it to scratch memory)
+  auto publish = [&](int I, auto ccv) {
+    constexpr int CC = decltype(ccv)::value;
+    const int c = RB * I + CC;
+    if (bl == I) {
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int j = RB * bj + rr;
+        if (j >= c && j < b) col[CC & 1][j] = v[rr][CC];
+      }
+    }
+  };
+  publish(0, std::integral_constant<int, 0>{});
+  __syncthreads();
+
+  // step i = RB I + II: proposal i
+  int nacc = 0;
+  auto step = [&](int I, auto iiv) -> bool {
+    constexpr int II = decltype(iiv)::value;
+    const int i = RB * I + II;
+    if (i >= b || nacc >= cap) return false;
+    const double* ci = col[II & 1];
+    const double h = ci[i];
+    const int p = prv[i];
+    const bool dup = p >= 0 && tk[p];
+    const bool a = !dup && (ul[i] * Vs[i] < h);
+    if (a) {
+      const double rsq = 1.0 / sqrt(h);
+      if (tid >= i && tid < b) H[(int64_t)nacc * b + tid] = ci[tid] * rsq;
+      if (bl >= I) {                         // the block has columns after i
+        double sj[RB], sl[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+          sj[t] = ci[RB * bj + t] * rsq;
+          sl[t] = ci[RB * bl + t] * rsq;
+        }
+        // the whole block is updated: entries in columns <= i are no longer
+        // read (column i was published before this step), and the column
+        // buffer rows they pick up are finite
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < RB; ++cc) v[rr][cc] = fma(-sj[rr], sl[cc], v[rr][cc]);
+      }
+    }
+    if (tid == 0) {
+      tk[i] = (a || dup) ? 1 : 0;
+      if (a) accl[nacc] = (short)i;
+    }
+    nacc += a ? 1 : 0;
+    if (II < RB - 1) publish(I, std::integral_constant<int, (II + 1) % RB>{});
+    else publish(I + 1, std::integral_constant<int, 0>{});
+    __syncthreads();
+    return true;
+  };
+  for (int I = 0; I < nbb; ++I) {
+    if (!step(I, std::integral_constant<int, 0>{})) break;
+    if (!step(I, std::integral_constant<int, 1>{})) break;
+    if (!step(I, std::integral_constant<int, 2>{})) break;
+    if (!step(I, std::integral_constant<int, 3>{})) break;
+    if (!step(I, std::integral_constant<int, 4>{})) break;
+    if (!step(I, std::integral_constant<int, 5>{})) break;
+    if (!step(I, std::integral_constant<int, 6>{})) break;
+    if (!step(I, std::integral_constant<int, 7>{})) break;
+  }
+  // L = L(T,T), dense column-major: L(a, c) = scaled column c at row accl[a]
+  for (int q = tid; q < nacc * nacc; q += nthr) {
+    const int a = q % nacc, c = q / nacc;
+    Lout[(int64_t)c * b + a] = (a >= c) ? H[(int64_t)c * b + accl[a]] : 0.0;
+  }
+  for (int a = tid; a < nacc; a += nthr) {
+    const int64_t pv = props[accl[a]];
+    acc_out[a] = accl[a];
+    pivots[kr + a] = pv;
+    u[pv] = 0.0;
+  }
+  if (tid == 0) st->s_r = nacc;
 }
 
 __global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, int b,
@@ -491,8 +609,9 @@ template void launch_gather<float>(hipStream_t, const float*, int64_t, const dou
 
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
                    double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
-  if (b <= REJECT_LDS_BMAX)
-    hipLaunchKernelGGL(k_reject_lds, dim3(1), dim3(1024), 0, s, H, b, props, un, st, L, acc, pivots, u, kmax);
+  if (b <= REJECT_REG_BMAX)
+    hipLaunchKernelGGL(k_reject_reg, dim3(1), dim3(REJECT_REG_THREADS), 0, s, H, b, props, un, st, L, acc, pivots,
+                       u, kmax);
   else
     hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, L, acc, pivots, u,
                        kmax);
