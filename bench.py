@@ -8,9 +8,10 @@ resident in HBM before the timed region; F, pivots and workspace are
 allocated once.
 
 Prints one JSON line: pivots/s over the timed steps, the roofline of the
-dominant kernel (the update GEMM) from HIP-event timings taken inside the
-timed region, and the CPU oracle timed on a bounded sample of the same
-workload on this host.
+dominant kernel (the one-kernel round product of the BF16 modes, else the
+update GEMM) from HIP-event timings taken inside the timed region, the
+trace error against an FP64 run of the same problem, and the CPU oracle
+timed on a bounded sample of the same workload on this host.
 """
 from __future__ import annotations
 
@@ -41,7 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="bf16", choices=sorted(PREC_BY_NAME))
     ap.add_argument("--workload", default="mixture", choices=["mixture", "laplace", "small", "sparse_hd"])
-    ap.add_argument("--cpu-rounds", type=int, default=2,
+    ap.add_argument("--cpu-rounds", type=int, default=3,
                     help="rounds of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-compare-fp64", action="store_true",
                     help="skip the FP64 factorization that the trace-error ratio of a "
@@ -52,25 +53,69 @@ def parse():
     return ap.parse_args()
 
 
-def gemm_roofline(stats, prec):
-    """Roofline of the update GEMM from the HIP-event kernel times: the
-    algorithmic flops (2 N k_r s_r per round, counted once even where the
-    arithmetic runs as three BF16 products) against the matrix-core peak of the
-    mode, and the algorithmic HBM bytes (F read once, C written, X read) against
-    8 TB/s.  The binding roof (larger fraction) is reported first."""
+KERNEL_SOURCES = {  # dominant kernel -> source file whose hash keys its counter summary
+    "k_fused_round": "paper_2410_03969_amd/csrc/fused_kernels.hip",
+    "k_panel": "paper_2410_03969_amd/csrc/mfma_kernels.hip",
+}
+
+
+def source_hash(rel: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, dtype: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-kernel
+    factors recorded there), or None when no summary matches this workload or
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{dtype}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-record:"):
+                for kv in line.split(":", 1)[1].split():
+                    k, _, v = kv.partition("=")
+                    fields[k] = v
+    if fields.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    try:
+        return float(fields["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def gemm_roofline(stats, prec, workload):
+    """Roofline of the dominant kernel from the HIP-event kernel times: the
+    one-kernel round product (BF16 modes) or the update-GEMM kernel.  The
+    algorithmic bytes (blocked F read once, points read, G written to F and
+    its blocked copy, row norms; the two-kernel GEMM writes C instead) against
+    8 TB/s, and the algorithmic flops (2 N k_r s_r for the GEMM, plus N s_r^2
+    for the solve when fused; counted once although the three-product mode
+    issues three BF16 products) against the matrix-core peak of the mode.
+    The binding roof (larger fraction) is reported first."""
     ms = stats["ms_kernel"]["colgemm"]
     n = stats["launches"]["colgemm"]
     if ms <= 0 or n == 0:
         return None, None
+    fused = bool(stats.get("fused"))
+    kernel = "k_fused_round" if fused else "k_panel"
     sec = ms * 1e-3
-    tflops = stats["flops_colgemm"] / sec / 1e12
+    flops = stats["flops_colgemm"] + (stats["flops_trsm"] if fused else 0.0)
+    tflops = flops / sec / 1e12
     gbs = stats["bytes_colgemm"] / sec / 1e9
     peak = {W.FP64: PEAKS["fp64_tflops"], W.FP32: PEAKS["fp32_tflops"]}.get(prec, PEAKS["bf16_tflops"])
-    common = {"kernel": "colgemm", "avg_launch_ms": round(ms / n, 4), "launches": n}
+    traffic = measured_traffic(kernel, workload, W.PREC_NAMES[prec])
+    common = {"kernel": kernel, "avg_launch_ms": round(ms / n, 4), "launches": n,
+              "algorithmic_bytes_per_launch": round(stats["bytes_colgemm"] / n),
+              "algorithmic_flops_per_launch": round(flops / n)}
     mf = {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
-          "frac": round(tflops / peak, 4), "traffic": None, **common}
+          "frac": round(tflops / peak, 4), "traffic": traffic, **common}
     hb = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-          "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": None, **common}
+          "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": traffic, **common}
     return (mf, hb) if mf["frac"] >= hb["frac"] else (hb, mf)
 
 
@@ -154,11 +199,12 @@ def main():
     trace_err = (last["trace_A"] - normF2) / last["trace_A"]
     # roofline over all timed steps
     agg = dict(last)
+    agg["fused"] = last.get("fused", 0)
     agg["ms_kernel"] = {c: sum(r["ms_kernel"][c] for r in runs) for c in B.KERNEL_CLASSES}
     agg["launches"] = {c: sum(r["launches"][c] for r in runs) for c in B.KERNEL_CLASSES}
     for key in ("flops_colgemm", "bytes_colgemm", "flops_trsm", "bytes_trsm"):
         agg[key] = sum(r[key] for r in runs)
-    roof, roof_alt = gemm_roofline(agg, prec)
+    roof, roof_alt = gemm_roofline(agg, prec, args.workload)
 
     out = {
         "metric": "pivots/s", "value": round(k_out / elapsed, 2), "unit": "pivots/s",
