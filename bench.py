@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--no-compare-fp64", action="store_true",
                     help="skip the FP64 factorization that the trace-error ratio of a "
                          "reduced-precision mode is stated against")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving stream instead (prints its own JSON line)")
+    ap.add_argument("--serving-jobs", type=int, default=512)
+    ap.add_argument("--serving-prec", default="bf16x3", choices=sorted(PREC_BY_NAME))
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the timed region, copy a device buffer of this many MiB "
                          "once (a reference kernel for hardware byte counters)")
@@ -143,11 +149,82 @@ def cpu_baseline(X, prob, rounds):
                       f"{dt:.1f} s; later rounds cost more per pivot)"}
 
 
+def run_serving(args):
+    """Serving stream: jobs shaped as in workloads.serving_stream (N log-uniform
+    on [1e4, 2e5], d in {3, 8, 32}, k uniform on [200, 1500], b = k/10).  A
+    closed loop with a bounded number of outstanding jobs measures the
+    saturation throughput X_sat; then an open loop submits the same jobs at
+    Poisson arrival times with rate 0.7 X_sat and reports the p50/p99 latency
+    (submission to completion, timed by the library), the aggregate pivots/s
+    and the mean number of resident jobs."""
+    import torch
+    from paper_2410_03969_amd import binding as B
+    B.lib()
+    prec = PREC_BY_NAME[args.serving_prec]
+    jobs = W.serving_stream(n_jobs=args.serving_jobs, rate=1.0, prec=prec)
+    dev = torch.device("cuda:0")
+    Xs = [torch.from_numpy(j.X).to(dev) for j in jobs]
+    torch.cuda.synchronize()
+    budget = int(args.serving_budget_gb * (1 << 30))
+
+    def run(arrivals, max_outstanding):
+        srv = B.Server(budget, max_slots=args.serving_slots)
+        lat, pivots, resident = [], 0, []
+        pending = {}
+        i = 0
+        t0 = time.perf_counter()
+        try:
+            while i < len(jobs) or pending:
+                now = time.perf_counter() - t0
+                while (i < len(jobs) and len(pending) < max_outstanding
+                       and (arrivals is None or arrivals[i] <= now)):
+                    pending[srv.submit(Xs[i], jobs[i].problem)] = i
+                    i += 1
+                for h in list(pending):
+                    r = srv.poll(h)
+                    if r is not None:
+                        del pending[h]
+                        if r["status"] < 0:
+                            raise RuntimeError(B.arpc_status_str(r["status"]))
+                        lat.append(r["stats"]["ms_total"])
+                        pivots += r["stats"]["k_out"]
+                resident.append(srv.info()["active"])
+                time.sleep(0.0002)
+            span = time.perf_counter() - t0
+            info = srv.info()
+        finally:
+            srv.close()
+        return np.array(lat), pivots, span, float(np.mean(resident)), info
+
+    lat_c, piv_c, span_c, res_c, _ = run(None, args.serving_slots * 4)
+    x_sat = len(jobs) / span_c
+    lam = 0.7 * x_sat
+    arrivals = np.array([j.arrival for j in jobs]) / lam
+    lat, piv, span, res, info = run(arrivals, len(jobs))
+    out = {
+        "metric": "serving latency", "unit": "ms", "n_gpus": 1, "dtype": W.PREC_NAMES[prec],
+        "data": "synthetic", "higher_is_better": False,
+        "config": {"workload": f"serving stream: {len(jobs)} jobs, N log-uniform [1e4, 2e5], "
+                               f"d in {{3, 8, 32}}, k uniform [200, 1500], b = k/10, Gaussian sigma = sqrt(d)",
+                   "slots": args.serving_slots, "budget_gb": args.serving_budget_gb},
+        "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "arrival_rate_jobs_per_s": round(lam, 3), "saturation_jobs_per_s": round(x_sat, 3),
+        "pivots_per_s": round(piv / span, 1), "mean_resident_jobs": round(res, 3),
+        "mean_pivots_per_job": round(piv / len(jobs), 1),
+        "peak_active": info["peak_active"], "peak_bytes": info["peak_bytes"],
+        "closed_loop": {"pivots_per_s": round(piv_c / span_c, 1), "mean_resident_jobs": round(res_c, 3),
+                        "p50_ms": round(float(np.percentile(lat_c, 50)), 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.serving:
+        return run_serving(args)
     import torch
 
     from paper_2410_03969_amd import binding as B

@@ -146,6 +146,76 @@ arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, d
  * (process-wide switch; off by default). */
 void arpc_set_profiling(int on);
 
+/* ------------------------------------------------------------------ serving
+ * A context serves a stream of factorization jobs (each one arpc_factor's
+ * operation: Alg. 2 with Alg. 1) on one device with continuous batching:
+ *  - a job is admitted, in submission order, as soon as a slot is free and
+ *    its workspace (arpc_workspace_size of its problem, about N*k elements of
+ *    the blocked factor copy plus O(N + b*k) more) fits in what is left of the
+ *    context's HBM budget;
+ *  - every admitted job runs on a stream of its own slot, one batch of rounds
+ *    after another, so the rounds of different jobs overlap on the device;
+ *  - a finished job frees its slot and memory at once and the next job is
+ *    admitted.
+ * A job runs exactly the kernels and launch shapes of arpc_factor on its own
+ * data, so its result does not depend on the other jobs.
+ * The context owns one device allocation of the budget (made by arpc_create),
+ * its streams and a scheduler thread; the caller owns every job's X, F and
+ * pivots and must keep them alive and untouched until the job completes.
+ * Calls on one context may come from several threads. */
+typedef struct arpc_ctx_s* arpc_ctx;
+typedef uint64_t arpc_job;
+
+typedef struct arpc_serving_stats {
+  int64_t submitted;     /* jobs submitted so far */
+  int64_t completed;     /* jobs finished (any status) */
+  int64_t cancelled;     /* jobs that ended with ARPC_ECANCELED */
+  int64_t active;        /* jobs holding a slot now */
+  int64_t queued;        /* jobs waiting for admission */
+  int64_t peak_active;   /* most jobs that held slots at the same time */
+  int64_t bytes_in_use;  /* budget bytes held by active jobs now */
+  int64_t peak_bytes;    /* most budget bytes held at the same time */
+  int64_t budget_bytes;  /* the context's budget */
+  int64_t slots;         /* the context's slot count */
+} arpc_serving_stats;
+
+/* Create a serving context on HIP device `device` with a budget of
+ * hbm_budget_bytes of device memory for job workspaces (allocated here, once)
+ * and at most max_slots concurrently active jobs (1..64).  Errors:
+ * ARPC_EINVAL (bad arguments), ARPC_EDEVICE (no such device, or the budget
+ * could not be allocated). */
+arpc_status arpc_create(int device, size_t hbm_budget_bytes, int max_slots, arpc_ctx* out);
+
+/* Cancel queued jobs, let active jobs finish their current batch of rounds
+ * and end as cancelled, stop the scheduler and free the context's memory.
+ * Job handles of the context become invalid. */
+arpc_status arpc_destroy(arpc_ctx ctx);
+
+/* Queue a job.  Arguments as for arpc_factor (the workspace comes from the
+ * context).  Returns ARPC_EINVAL for an invalid problem or pointers and
+ * ARPC_ENOMEM when the job's workspace exceeds the whole budget. */
+arpc_status arpc_submit(arpc_ctx ctx, const arpc_problem* problem, const double* X, void* F, int64_t* pivots,
+                        arpc_job* job);
+
+/* Non-blocking completion check.  *done = 1 when the job has finished; then
+ * *stats (may be NULL) holds its statistics, with ms_total = milliseconds
+ * from submission to completion, and the return value is the job's own
+ * status (as arpc_factor would return).  The handle stays valid until
+ * arpc_wait or a poll that reports completion returns. */
+arpc_status arpc_poll(arpc_ctx ctx, arpc_job job, int* done, arpc_stats* stats);
+
+/* Block until the job finishes; returns its status and fills *stats (may be
+ * NULL).  ARPC_EINVAL for an unknown handle. */
+arpc_status arpc_wait(arpc_ctx ctx, arpc_job job, arpc_stats* stats);
+
+/* Cancel a job: a queued job ends at once, an active one after its current
+ * batch of rounds (its F and pivots are then incomplete).  Its status becomes
+ * ARPC_ECANCELED unless it had already finished. */
+arpc_status arpc_cancel(arpc_ctx ctx, arpc_job job);
+
+/* Snapshot of the context's counters. */
+arpc_status arpc_serving_info(arpc_ctx ctx, arpc_serving_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,9 @@ KERNEL_CLASSES = ["init", "propose", "gather", "reject", "prep", "colgemm", "trs
 NUM_KC = len(KERNEL_CLASSES)
 
 EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_factor",
-           "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling"]
+           "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling",
+           "arpc_create", "arpc_destroy", "arpc_submit", "arpc_poll", "arpc_wait", "arpc_cancel",
+           "arpc_serving_info"]
 
 
 class ArpcProblem(C.Structure):
@@ -42,6 +44,16 @@ class ArpcStats(C.Structure):
         d["ms_kernel"] = dict(zip(KERNEL_CLASSES, list(self.ms_kernel)))
         d["launches"] = dict(zip(KERNEL_CLASSES, list(self.launches)))
         return d
+
+
+class ArpcServingStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("active", C.c_int64), ("queued", C.c_int64), ("peak_active", C.c_int64),
+                ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64), ("budget_bytes", C.c_int64),
+                ("slots", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -71,6 +83,21 @@ def lib():
         L.arpc_stream_uniforms_host.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_void_p]
         L.arpc_set_profiling.restype = None
         L.arpc_set_profiling.argtypes = [C.c_int]
+        L.arpc_create.restype = C.c_int
+        L.arpc_create.argtypes = [C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]
+        L.arpc_destroy.restype = C.c_int
+        L.arpc_destroy.argtypes = [C.c_void_p]
+        L.arpc_submit.restype = C.c_int
+        L.arpc_submit.argtypes = [C.c_void_p, C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(C.c_uint64)]
+        L.arpc_poll.restype = C.c_int
+        L.arpc_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(ArpcStats)]
+        L.arpc_wait.restype = C.c_int
+        L.arpc_wait.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(ArpcStats)]
+        L.arpc_cancel.restype = C.c_int
+        L.arpc_cancel.argtypes = [C.c_void_p, C.c_uint64]
+        L.arpc_serving_info.restype = C.c_int
+        L.arpc_serving_info.argtypes = [C.c_void_p, C.POINTER(ArpcServingStats)]
         _lib = L
     return _lib
 
@@ -161,3 +188,104 @@ def factor(X, problem, U=None, device: str = "cuda", stream=None, workspace=None
     if status < 0:
         raise RuntimeError(f"arpc_factor failed: {arpc_status_str(status)}")
     return {"F": Ft.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}
+
+
+# ------------------------------------------------------------------- serving
+def arpc_create(device: int, budget_bytes: int, max_slots: int):
+    ctx = C.c_void_p()
+    st = lib().arpc_create(int(device), C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(ctx))
+    return st, ctx
+
+
+def arpc_destroy(ctx) -> int:
+    return lib().arpc_destroy(ctx)
+
+
+def arpc_submit(ctx, problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: int):
+    job = C.c_uint64(0)
+    st = lib().arpc_submit(ctx, C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(F_ptr), C.c_void_p(piv_ptr),
+                           C.byref(job))
+    return st, job.value
+
+
+def arpc_poll(ctx, job: int):
+    done = C.c_int(0)
+    stats = ArpcStats()
+    st = lib().arpc_poll(ctx, C.c_uint64(job), C.byref(done), C.byref(stats))
+    return st, bool(done.value), stats
+
+
+def arpc_wait(ctx, job: int):
+    stats = ArpcStats()
+    st = lib().arpc_wait(ctx, C.c_uint64(job), C.byref(stats))
+    return st, stats
+
+
+def arpc_cancel(ctx, job: int) -> int:
+    return lib().arpc_cancel(ctx, C.c_uint64(job))
+
+
+def arpc_serving_info(ctx) -> dict:
+    out = ArpcServingStats()
+    st = lib().arpc_serving_info(ctx, C.byref(out))
+    if st != ARPC_OK:
+        raise ValueError(arpc_status_str(st))
+    return out.as_dict()
+
+
+class Server:
+    """A serving context plus the device buffers of its jobs (allocation and
+    argument marshalling only; the scheduling runs in libarpc.so)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 8, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        st, self.ctx = arpc_create(device, budget_bytes, max_slots)
+        if st != ARPC_OK:
+            raise RuntimeError(f"arpc_create failed: {arpc_status_str(st)}")
+        self.device = torch.device("cuda", device)
+        self.bufs = {}
+
+    def submit(self, X, problem) -> int:
+        """Queue a job on points X (numpy or device tensor); returns the handle."""
+        import torch
+        pr = make_problem(problem)
+        if isinstance(X, np.ndarray):
+            Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(self.device)
+        else:
+            Xd = X.contiguous()
+        fdt = torch.float64 if problem.prec == 0 else torch.float32
+        Ft = torch.empty((problem.k, problem.N), dtype=fdt, device=self.device)
+        piv = torch.empty(problem.k, dtype=torch.int64, device=self.device)
+        # inputs resident before the scheduler's streams read them (torch's own
+        # stream only: a device-wide sync would also wait for running jobs)
+        torch.cuda.current_stream(self.device).synchronize()
+        st, job = arpc_submit(self.ctx, pr, Xd.data_ptr(), Ft.data_ptr(), piv.data_ptr())
+        if st != ARPC_OK:
+            raise RuntimeError(f"arpc_submit failed: {arpc_status_str(st)}")
+        self.bufs[job] = (Xd, Ft, piv)
+        return job
+
+    def wait(self, job: int) -> dict:
+        st, stats = arpc_wait(self.ctx, job)
+        Xd, Ft, piv = self.bufs.pop(job)
+        return {"F": Ft.t(), "pivots": piv, "status": st, "stats": stats.as_dict()}
+
+    def poll(self, job: int):
+        st, done, stats = arpc_poll(self.ctx, job)
+        if not done:
+            return None
+        Xd, Ft, piv = self.bufs.pop(job)
+        return {"F": Ft.t(), "pivots": piv, "status": st, "stats": stats.as_dict()}
+
+    def cancel(self, job: int) -> int:
+        return arpc_cancel(self.ctx, job)
+
+    def info(self) -> dict:
+        return arpc_serving_info(self.ctx)
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            arpc_destroy(self.ctx)
+            self.ctx = None

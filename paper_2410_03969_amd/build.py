@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libarpc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["round_kernels.hip", "gemm_kernels.hip", "mfma_kernels.hip", "fused_kernels.hip", "api.cpp"]
+SOURCES = ["round_kernels.hip", "gemm_kernels.hip", "mfma_kernels.hip", "fused_kernels.hip", "api.cpp",
+           "serving.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -39,10 +40,10 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(5, len(srcs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -18,10 +18,11 @@
 #include "arpc_common.h"
 #include "arpc_launch.h"
 #include "arpc_mfma.h"
+#include "arpc_host.h"
 
 using namespace arpc;
 
-namespace {
+namespace arpc {
 
 int g_profiling = 0;
 
@@ -53,13 +54,7 @@ bool fused_disabled() {
   return e && strcmp(e, "0") == 0;
 }
 
-struct Layout {
-  size_t st, u, csum, cpre, props, acc, hist, Fs, H, L, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, P, trace, total;
-  int part_cols;
-  bool valu;  // vector-unit GEMM kernels instead of the matrix-core ones
-  int ncbt;   // > 0: one-kernel round product with this column-block count
-  int grid;   // persistent workgroups of that kernel (set per call)
-};
+
 
 inline int64_t nchunks_of(int64_t N) { return (N + CHUNK - 1) / CHUNK; }
 
@@ -128,53 +123,7 @@ KParams kparams_of(const arpc_problem& p) {
   return kp;
 }
 
-// Per-kernel-class timing with HIP events on the launch stream.
-struct Profiler {
-  hipStream_t s;
-  bool on;
-  std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
-  size_t used = 0;
-  double ms[ARPC_NUM_KC] = {0};
-  int64_t n[ARPC_NUM_KC] = {0};
-  Profiler(hipStream_t st, bool enable) : s(st), on(enable) {}
-  ~Profiler() {
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-  hipEvent_t next() {
-    if (used == pool.size()) {
-      hipEvent_t e;
-      (void)hipEventCreate(&e);
-      pool.push_back(e);
-    }
-    return pool[used++];
-  }
-  void begin(int cls) {
-    if (!on) return;
-    marks.push_back({cls, used});
-    (void)hipEventRecord(next(), s);
-  }
-  void end() {
-    if (!on) return;
-    (void)hipEventRecord(next(), s);
-  }
-  // called after a stream synchronisation; ARPC_TRACE=1 also prints every
-  // launch's time to stderr
-  void collect() {
-    if (!on) return;
-    static const bool trace = getenv("ARPC_TRACE") != nullptr;
-    for (auto& m : marks) {
-      float t = 0.f;
-      if (hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]) == hipSuccess) {
-        ms[m.first] += t;
-        n[m.first] += 1;
-        if (trace) fprintf(stderr, "arpc-trace class=%d launch=%lld ms=%.4f\n", m.first, (long long)n[m.first], t);
-      }
-    }
-    marks.clear();
-    used = 0;
-  }
-};
+
 
 template <typename T>
 void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, const Unif& un, char* ws,
@@ -253,117 +202,203 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
     if ((x) != hipSuccess) return ARPC_EDEVICE; \
   } while (0)
 
+// One factorization as a host-side state machine, shared by arpc_factor and
+// the serving scheduler: begin() enqueues the initial pass, enqueue_batch() a
+// batch of rounds followed by an asynchronous copy of the round state into
+// *hstate, running() inspects that copy once the stream has reached it, and
+// finish() enqueues the final reductions, waits for them and fills the stats.
 template <typename T>
-arpc_status run(const arpc_problem& p, const double* X, T* F, int64_t* pivots, char* ws, const Layout& l,
-                hipStream_t s, const Unif& un, arpc_stats* stats) {
-  const auto t0 = std::chrono::steady_clock::now();
-  const KParams kp = kparams_of(p);
-  const int64_t N = p.N, nch = nchunks_of(N);
-  RoundState* st = (RoundState*)(ws + l.st);
-  Profiler prof(s, g_profiling != 0);
-
-  HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
-  prof.begin(ARPC_KC_INIT);
-  launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, N, (int)p.d, kp, st, nch);
-  prof.end();
-  HIPCHK(hipGetLastError());
-
-  RoundState h{};
+struct Job final : JobBase {
+  arpc_problem p;
+  const double* X;
+  T* F;
+  int64_t* pivots;
+  char* ws;
+  Layout l;
+  hipStream_t s;
+  Unif un;
+  KParams kp;
+  RoundState* hstate;
+  Profiler* prof;
   int64_t known_k = 0, enqueued = 0;
-  for (;;) {
+  hipGraphExec_t round_graph = nullptr;
+
+  Job(const arpc_problem& p_, const double* X_, T* F_, int64_t* piv_, char* ws_, const Layout& l_,
+      hipStream_t s_, const Unif& un_, RoundState* h_, Profiler* prof_)
+      : p(p_), X(X_), F(F_), pivots(piv_), ws(ws_), l(l_), s(s_), un(un_), kp(kparams_of(p_)), hstate(h_),
+        prof(prof_) {}
+  ~Job() override {
+    if (round_graph) (void)hipGraphExecDestroy(round_graph);
+  }
+
+  arpc_status begin() override {
+    RoundState* st = (RoundState*)(ws + l.st);
+    const int64_t nch = nchunks_of(p.N);
+    HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
+    prof->begin(ARPC_KC_INIT);
+    launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, p.N, (int)p.d, kp, st, nch);
+    prof->end();
+    HIPCHK(hipGetLastError());
+    return ARPC_OK;
+  }
+
+  // Record one round's kernels as a graph (they read the round state from
+  // device memory, so the same graph serves every round of this job).
+  arpc_status capture_round() override {
+    Profiler off(s, false);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_round<T>(s, p, kp, un, ws, l, X, F, pivots, off);
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || !g) return ARPC_EDEVICE;
+    const hipError_t ei = hipGraphInstantiate(&round_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      round_graph = nullptr;
+      return ARPC_EDEVICE;
+    }
+    return ARPC_OK;
+  }
+
+  arpc_status enqueue_batch() override {
     // the fewest rounds that could still be needed (every round accepts <= b)
     int64_t batch = (p.k - known_k + p.b - 1) / p.b;
     if (batch < 1) batch = 1;
     if (p.max_rounds > 0 && enqueued + batch > p.max_rounds) batch = p.max_rounds - enqueued;
     if (batch < 1) batch = 1;
-    for (int64_t r = 0; r < batch; ++r) enqueue_round<T>(s, p, kp, un, ws, l, X, F, pivots, prof);
+    for (int64_t r = 0; r < batch; ++r) {
+      if (round_graph) HIPCHK(hipGraphLaunch(round_graph, s));
+      else enqueue_round<T>(s, p, kp, un, ws, l, X, F, pivots, *prof);
+    }
     enqueued += batch;
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&h, st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hstate, ws + l.st, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+    return ARPC_OK;
+  }
+
+  bool running() override {
+    if (hstate->status != ST_RUNNING) return false;
+    known_k = hstate->k_r;
+    return true;
+  }
+
+  arpc_status finish(arpc_stats* stats, double ms_total) override {
+    const RoundState h = *hstate;
+    if (h.nonfinite) return ARPC_ENUMERIC;
+    const int64_t N = p.N, nch = nchunks_of(N);
+    // final residual trace and round history
+    double* tr = (double*)(ws + l.trace);
+    launch_trace(s, (double*)(ws + l.csum), nch, tr);
+    double trace_resid = 0.0;
+    HIPCHK(hipMemcpyAsync(&trace_resid, tr, sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> hist((size_t)h.round + 1, 0);
+    if (h.round > 0)
+      HIPCHK(hipMemcpyAsync(hist.data(), ws + l.hist, sizeof(int32_t) * h.round, hipMemcpyDeviceToHost, s));
+    const int64_t k_out = h.k_r;
+    if (k_out < p.k) {
+      HIPCHK(hipMemsetAsync(F + k_out * N, 0, sizeof(T) * (size_t)(p.k - k_out) * N, s));
+      HIPCHK(hipMemsetAsync(pivots + k_out, 0xff, sizeof(int64_t) * (size_t)(p.k - k_out), s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+
+    arpc_status ret = (k_out == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE))
+                          ? ARPC_OK
+                          : ARPC_EARLY_STOP;
+    if (h.status == ST_NOUNIF) ret = ARPC_EINVAL;
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->k_out = k_out;
+      stats->rounds = h.round;
+      stats->proposals = h.proposals;
+      stats->status = (ret == ARPC_EINVAL) ? ARPC_EINVAL : ret;
+      stats->trace_A = h.trace_A;
+      stats->trace_resid = trace_resid;
+      // algorithmic traffic per round and row: the blocked copy of F read over
+      // k_r columns, the points, G stored twice (F and its blocked copy), the
+      // row norm; the two-kernel path also writes and reads C
+      double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0;
+      const double es = (double)sizeof(T);
+      const double eb = p.prec == ARPC_FP64 ? 8.0 : (p.prec == ARPC_BF16 ? 2.0 : 4.0);
+      const bool fused = l.ncbt > 0;
+      for (int64_t r = 0; r < h.round; ++r) {
+        const double sr = hist[r];
+        fg += 2.0 * (double)N * kr * sr;
+        ft += (double)N * sr * sr;
+        if (sr > 0) {
+          if (fused) {
+            bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * (es + eb) + 8.0);
+          } else {
+            bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
+            bt += (double)N * (sr * (eb + es + eb) + 8.0);
+          }
+        }
+        kr += sr;
+      }
+      stats->fused = fused ? 1 : 0;
+      stats->flops_colgemm = fg;
+      stats->flops_trsm = ft;
+      stats->bytes_colgemm = bg;
+      stats->bytes_trsm = bt;
+      for (int c = 0; c < ARPC_NUM_KC; ++c) {
+        stats->ms_kernel[c] = prof->ms[c];
+        stats->launches[c] = prof->n[c];
+      }
+      stats->ms_total = ms_total;
+    }
+    return ret;
+  }
+};
+
+
+std::unique_ptr<JobBase> make_job(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws,
+                                  const Layout& l, hipStream_t s, const Unif& un, RoundState* hstate,
+                                  Profiler* prof) {
+  if (p.prec == ARPC_FP64)
+    return std::unique_ptr<JobBase>(new Job<double>(p, X, (double*)F, pivots, ws, l, s, un, hstate, prof));
+  return std::unique_ptr<JobBase>(new Job<float>(p, X, (float*)F, pivots, ws, l, s, un, hstate, prof));
+}
+
+arpc_status check_factor_args(const arpc_problem* p, const double* X, const void* F, const int64_t* pivots) {
+  arpc_status v = validate(p);
+  if (v != ARPC_OK) return v;
+  if (!X || !F || !pivots) return ARPC_EINVAL;
+  if (((uintptr_t)X & 7) || ((uintptr_t)F & 7) || ((uintptr_t)pivots & 7)) return ARPC_EINVAL;
+  if (use_valu_gemm() && p->prec > ARPC_FP32) return ARPC_EINVAL;  // vector kernels: FP64/FP32 only
+  return ARPC_OK;
+}
+
+}  // namespace arpc
+
+namespace {
+
+arpc_status run_sync(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws, const Layout& l,
+                     hipStream_t s, const Unif& un, arpc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Profiler prof(s, g_profiling != 0);
+  RoundState h{};
+  auto job = make_job(p, X, F, pivots, ws, l, s, un, &h, &prof);
+  arpc_status e = job->begin();
+  if (e != ARPC_OK) return e;
+  for (;;) {
+    e = job->enqueue_batch();
+    if (e != ARPC_OK) return e;
     HIPCHK(hipStreamSynchronize(s));
     prof.collect();
-    if (h.status != ST_RUNNING) break;
-    known_k = h.k_r;
+    if (!job->running()) break;
   }
-  if (h.nonfinite) return ARPC_ENUMERIC;
-
-  // final residual trace and round history
-  double* tr = (double*)(ws + l.trace);
-  launch_trace(s, (double*)(ws + l.csum), nch, tr);
-  double trace_resid = 0.0;
-  HIPCHK(hipMemcpyAsync(&trace_resid, tr, sizeof(double), hipMemcpyDeviceToHost, s));
-  std::vector<int32_t> hist((size_t)h.round + 1, 0);
-  if (h.round > 0)
-    HIPCHK(hipMemcpyAsync(hist.data(), ws + l.hist, sizeof(int32_t) * h.round, hipMemcpyDeviceToHost, s));
-  const int64_t k_out = h.k_r;
-  if (k_out < p.k) {
-    HIPCHK(hipMemsetAsync(F + k_out * N, 0, sizeof(T) * (size_t)(p.k - k_out) * N, s));
-    HIPCHK(hipMemsetAsync(pivots + k_out, 0xff, sizeof(int64_t) * (size_t)(p.k - k_out), s));
-  }
-  HIPCHK(hipStreamSynchronize(s));
-
-  arpc_status ret = (k_out == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE))
-                        ? ARPC_OK
-                        : ARPC_EARLY_STOP;
-  if (h.status == ST_NOUNIF) ret = ARPC_EINVAL;
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->k_out = k_out;
-    stats->rounds = h.round;
-    stats->proposals = h.proposals;
-    stats->status = (ret == ARPC_EINVAL) ? ARPC_EINVAL : ret;
-    stats->trace_A = h.trace_A;
-    stats->trace_resid = trace_resid;
-    // algorithmic traffic per round and row: the blocked copy of F read over
-    // k_r columns, the points, G stored twice (F and its blocked copy), the
-    // row norm; the two-kernel path also writes and reads C
-    double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0;
-    const double es = (double)sizeof(T);
-    const double eb = p.prec == ARPC_FP64 ? 8.0 : (p.prec == ARPC_BF16 ? 2.0 : 4.0);
-    const bool fused = l.ncbt > 0;
-    for (int64_t r = 0; r < h.round; ++r) {
-      const double sr = hist[r];
-      fg += 2.0 * (double)N * kr * sr;
-      ft += (double)N * sr * sr;
-      if (sr > 0) {
-        if (fused) {
-          bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * (es + eb) + 8.0);
-        } else {
-          bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
-          bt += (double)N * (sr * (eb + es + eb) + 8.0);
-        }
-      }
-      kr += sr;
-    }
-    stats->fused = fused ? 1 : 0;
-    stats->flops_colgemm = fg;
-    stats->flops_trsm = ft;
-    stats->bytes_colgemm = bg;
-    stats->bytes_trsm = bt;
-    for (int c = 0; c < ARPC_NUM_KC; ++c) {
-      stats->ms_kernel[c] = prof.ms[c];
-      stats->launches[c] = prof.n[c];
-    }
-    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-  return ret;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return job->finish(stats, ms);
 }
 
 arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t* pivots, void* ws,
                         size_t ws_bytes, void* stream, const Unif& un, arpc_stats* stats) {
-  arpc_status v = validate(p);
+  arpc_status v = check_factor_args(p, X, F, pivots);
   if (v != ARPC_OK) return v;
-  if (!X || !F || !pivots || !ws) return ARPC_EINVAL;
-  if (((uintptr_t)X & 7) || ((uintptr_t)F & 7) || ((uintptr_t)pivots & 7) || ((uintptr_t)ws & 255))
-    return ARPC_EINVAL;
+  if (!ws || ((uintptr_t)ws & 255)) return ARPC_EINVAL;
   Layout l = layout_of(*p);
   if (ws_bytes < l.total) return ARPC_EINVAL;
   if (l.ncbt > 0) l.grid = fused_grid();
-  hipStream_t s = (hipStream_t)stream;
-  if (p->prec == ARPC_FP64)
-    return run<double>(*p, X, (double*)F, pivots, (char*)ws, l, s, un, stats);
-  if (use_valu_gemm() && p->prec > ARPC_FP32) return ARPC_EINVAL;  // vector kernels: FP64/FP32 only
-  return run<float>(*p, X, (float*)F, pivots, (char*)ws, l, s, un, stats);
+  return run_sync(*p, X, F, pivots, (char*)ws, l, (hipStream_t)stream, un, stats);
 }
 
 }  // namespace

@@ -1,0 +1,91 @@
+// Host-side driver types shared by the factorization entry points and the
+// serving scheduler (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+#include <vector>
+
+#include "../../include/arpc.h"
+#include "arpc_common.h"
+
+namespace arpc {
+
+// Offsets of the buffers carved from one factorization's workspace.
+struct Layout {
+  size_t st, u, csum, cpre, props, acc, hist, Fs, H, L, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, P, trace, total;
+  int part_cols;
+  bool valu;  // vector-unit GEMM kernels instead of the matrix-core ones
+  int ncbt;   // > 0: one-kernel round product with this column-block count
+  int grid;   // persistent workgroups of that kernel (set per call)
+};
+
+// Per-kernel-class timing with HIP events on the launch stream.
+struct Profiler {
+  hipStream_t s;
+  bool on;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
+  size_t used = 0;
+  double ms[ARPC_NUM_KC] = {0};
+  int64_t n[ARPC_NUM_KC] = {0};
+  Profiler(hipStream_t st, bool enable) : s(st), on(enable) {}
+  ~Profiler() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int cls) {
+    if (!on) return;
+    marks.push_back({cls, used});
+    (void)hipEventRecord(next(), s);
+  }
+  void end() {
+    if (!on) return;
+    (void)hipEventRecord(next(), s);
+  }
+  // called after a stream synchronisation; ARPC_TRACE=1 also prints every
+  // launch's time to stderr
+  void collect() {
+    if (!on) return;
+    static const bool trace = getenv("ARPC_TRACE") != nullptr;
+    for (auto& m : marks) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]) == hipSuccess) {
+        ms[m.first] += t;
+        n[m.first] += 1;
+        if (trace) fprintf(stderr, "arpc-trace class=%d launch=%lld ms=%.4f\n", m.first, (long long)n[m.first], t);
+      }
+    }
+    marks.clear();
+    used = 0;
+  }
+};
+
+// One factorization driven by the host (see Job in api.cpp).
+struct JobBase {
+  virtual ~JobBase() {}
+  virtual arpc_status begin() = 0;
+  virtual arpc_status capture_round() = 0;
+  virtual arpc_status enqueue_batch() = 0;
+  virtual bool running() = 0;
+  virtual arpc_status finish(arpc_stats* stats, double ms_total) = 0;
+};
+
+Layout layout_of(const arpc_problem& p);
+int fused_grid();
+arpc_status check_factor_args(const arpc_problem* p, const double* X, const void* F, const int64_t* pivots);
+std::unique_ptr<JobBase> make_job(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws,
+                                  const Layout& l, hipStream_t s, const Unif& un, RoundState* hstate,
+                                  Profiler* prof);
+
+}  // namespace arpc

@@ -42,7 +42,8 @@ def test_struct_layout_matches_header(tmp_path):
     import ctypes
     import subprocess
     fields = {"arpc_problem": [f for f, _ in B.ArpcProblem._fields_],
-              "arpc_stats": [f for f, _ in B.ArpcStats._fields_]}
+              "arpc_stats": [f for f, _ in B.ArpcStats._fields_],
+              "arpc_serving_stats": [f for f, _ in B.ArpcServingStats._fields_]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "arpc.h"', 'int main(void){']
     for st, fs in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({st}));')
@@ -55,7 +56,7 @@ def test_struct_layout_matches_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = []
-    for cls in (B.ArpcProblem, B.ArpcStats):
+    for cls in (B.ArpcProblem, B.ArpcStats, B.ArpcServingStats):
         want.append(ctypes.sizeof(cls))
         want += [getattr(cls, f).offset for f, _ in cls._fields_]
     assert got == want
@@ -96,3 +97,26 @@ def test_factor_rejects_null_pointers_without_gpu_work():
     assert st == B.ARPC_EINVAL
     st, _ = B.arpc_factor(_prob(), 8, 8, 8, 100, 1 << 40, 0)   # misaligned workspace
     assert st == B.ARPC_EINVAL
+
+
+def test_serving_calls_validate_without_gpu():
+    """Serving entry points reject bad arguments before touching a device; on a
+    machine without a GPU, creating a context reports a device error."""
+    lib = B.lib()
+    import ctypes as C
+    assert lib.arpc_create(0, 1 << 20, 0, C.byref(C.c_void_p())) == B.ARPC_EINVAL
+    assert lib.arpc_create(0, 1 << 20, 65, C.byref(C.c_void_p())) == B.ARPC_EINVAL
+    assert lib.arpc_create(0, 16, 4, C.byref(C.c_void_p())) == B.ARPC_EINVAL
+    assert lib.arpc_destroy(None) == B.ARPC_EINVAL
+    assert lib.arpc_submit(None, C.byref(_prob()), None, None, None, C.byref(C.c_uint64())) == B.ARPC_EINVAL
+    assert lib.arpc_wait(None, 1, None) == B.ARPC_EINVAL
+    assert lib.arpc_cancel(None, 1) == B.ARPC_EINVAL
+    assert lib.arpc_serving_info(None, None) == B.ARPC_EINVAL
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        st, ctx = B.arpc_create(0, 1 << 20, 4)
+        assert st == B.ARPC_EDEVICE and not ctx.value

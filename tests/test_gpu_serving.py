@@ -1,0 +1,145 @@
+"""GPU serving tests (continuous batching through the C ABI).
+
+Each job's result must be the same alone (arpc_factor) and in the mix
+(submitted with other jobs to a serving context whose budget forces queueing
+and whose slots let rounds of different jobs overlap): the kernels, launch
+shapes and data of a job do not depend on the other jobs, so the comparison is
+bit for bit.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2410_03969_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs():
+    """Twelve jobs shaped like the serving stream (points uniform on [0,1]^d,
+    Gaussian kernel with bandwidth sqrt(d), b = k/10), small enough for a test,
+    over every precision mode and both round-product paths."""
+    rng = np.random.default_rng(4)
+    precs = [W.BF16X3, W.BF16, W.FP64, W.FP32]
+    out = []
+    for j in range(12):
+        N = int(round(10 ** rng.uniform(3.3, 4.3)))
+        d = int(rng.choice([3, 8, 32]))
+        k = int(rng.integers(40, 300))
+        b = max(1, k // 10)
+        X = np.random.default_rng(1000 + j).random((N, d))
+        prob = W.Problem(N=N, d=d, k=k, b=b, kernel=W.GAUSSIAN, sigma=float(np.sqrt(d)), seed=j,
+                         prec=precs[j % len(precs)])
+        out.append((X, prob))
+    return out
+
+
+def _alone(X, prob):
+    from paper_2410_03969_amd import binding
+    out = binding.factor(X, prob)
+    return out["F"].cpu().numpy().copy(), out["pivots"].cpu().numpy().copy(), out["status"]
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("graphs", ["1", "0"])
+def test_results_same_alone_and_in_the_mix(monkeypatch, graphs):
+    from paper_2410_03969_amd import binding
+    monkeypatch.setenv("ARPC_SERVE_GRAPHS", graphs)
+    jobs = _jobs()
+    alone = []
+    for X, prob in jobs:
+        _log(f"[serving alone] N={prob.N} d={prob.d} k={prob.k} b={prob.b} prec={prob.prec}")
+        alone.append(_alone(X, prob))
+    ws = [binding.arpc_workspace_size(binding.make_problem(p)) for _, p in jobs]
+    budget = int(2.5 * max(ws))   # a few jobs at a time: the rest wait for memory
+    _log(f"[serving mix] budget={budget} slots=4 graphs={graphs}")
+    srv = binding.Server(budget, max_slots=4)
+    try:
+        handles = [srv.submit(X, prob) for X, prob in jobs]
+        results = [srv.wait(h) for h in handles]
+        info = srv.info()
+    finally:
+        srv.close()
+    for (F0, p0, s0), r, (X, prob) in zip(alone, results, jobs):
+        assert r["status"] == s0
+        assert np.array_equal(r["pivots"].cpu().numpy(), p0), f"pivots differ for job {prob}"
+        assert np.array_equal(r["F"].cpu().numpy(), F0), f"F differs for job {prob}"
+        assert r["stats"]["ms_total"] > 0
+    assert info["completed"] == len(jobs) and info["active"] == 0 and info["queued"] == 0
+    assert info["peak_bytes"] <= budget
+    assert info["peak_active"] >= 2, info     # jobs did overlap
+
+
+def test_admission_respects_budget():
+    from paper_2410_03969_amd import binding
+    X = np.random.default_rng(0).random((20000, 8))
+    prob = W.Problem(N=20000, d=8, k=200, b=20, kernel=W.GAUSSIAN, sigma=1.0, seed=1, prec=W.BF16X3)
+    ws = binding.arpc_workspace_size(binding.make_problem(prob))
+    budget = 2 * ws + ws // 2                 # two jobs fit, three do not
+    _log(f"[serving budget] ws={ws} budget={budget}")
+    srv = binding.Server(budget, max_slots=8)
+    try:
+        hs = [srv.submit(X, prob.with_(seed=s)) for s in range(6)]
+        res = [srv.wait(h) for h in hs]
+        info = srv.info()
+    finally:
+        srv.close()
+    assert all(r["status"] == 0 for r in res)
+    assert info["peak_bytes"] <= budget
+    assert info["peak_active"] <= 2
+    # the same job alone gives the same pivots
+    _, p0, _ = _alone(X, prob.with_(seed=3))
+    assert np.array_equal(res[3]["pivots"].cpu().numpy(), p0)
+
+
+def test_cancel_errors_and_destroy():
+    from paper_2410_03969_amd import binding
+    rng = np.random.default_rng(2)
+    X = rng.random((50000, 3))
+    big = W.Problem(N=50000, d=3, k=1500, b=15, kernel=W.GAUSSIAN, sigma=0.05, seed=0, prec=W.BF16)
+    small = W.Problem(N=5000, d=3, k=50, b=5, kernel=W.GAUSSIAN, sigma=0.5, seed=1, prec=W.BF16)
+    ws_big = binding.arpc_workspace_size(binding.make_problem(big))
+    _log(f"[serving cancel] ws_big={ws_big}")
+    srv = binding.Server(ws_big + (1 << 20), max_slots=1)
+    try:
+        # too large for the whole budget
+        import torch
+        Xd = torch.from_numpy(X).cuda()
+        F = torch.empty((4000, 50000), dtype=torch.float32, device="cuda")
+        piv = torch.empty(4000, dtype=torch.int64, device="cuda")
+        st, _ = binding.arpc_submit(srv.ctx, binding.make_problem(big.with_(k=4000, b=40)), Xd.data_ptr(),
+                                    F.data_ptr(), piv.data_ptr())
+        assert st == binding.ARPC_ENOMEM
+        st, _ = binding.arpc_submit(srv.ctx, binding.make_problem(big.with_(b=0)), Xd.data_ptr(),
+                                    F.data_ptr(), piv.data_ptr())
+        assert st == binding.ARPC_EINVAL
+        # one slot: the second job waits in the queue and is cancelled there
+        h1 = srv.submit(X, big)
+        h2 = srv.submit(X[:5000], small)
+        assert srv.cancel(h2) == 0
+        r2 = srv.wait(h2)
+        assert r2["status"] == binding.ARPC_ECANCELED
+        # the active job is cancelled between batches of rounds (or has finished)
+        assert srv.cancel(h1) == 0
+        r1 = srv.wait(h1)
+        assert r1["status"] in (binding.ARPC_ECANCELED, binding.ARPC_OK)
+        # the context still serves
+        h3 = srv.submit(X[:5000], small)
+        r3 = srv.wait(h3)
+        assert r3["status"] == 0
+        _, p0, _ = _alone(X[:5000], small)
+        assert np.array_equal(r3["pivots"].cpu().numpy(), p0)
+        info = srv.info()
+        assert info["cancelled"] >= 1
+        # destroy with work still queued and active
+        srv.submit(X, big)
+        srv.submit(X[:5000], small)
+        time.sleep(0.01)
+    finally:
+        srv.close()
