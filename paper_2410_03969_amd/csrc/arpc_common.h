@@ -144,6 +144,53 @@ __device__ __attribute__((always_inline)) inline float kappa_fast(float r2, cons
   return poly * __builtin_amdgcn_exp2f(-k.q * t);
 }
 
+__device__ inline double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Column c of the inverse of the s x s lower-triangular L (column-major, ld
+// b), s <= 256, in one wavefront by column-oriented forward substitution: lane
+// l keeps rows l, l + 64, l + 128, l + 192 of the right-hand side e_c, which
+// becomes column c of L^{-1}.  Column t of L is read coalesced and does not
+// depend on the solution, so it is loaded a step ahead; the dependency chain
+// is one readlane and a few FMAs per step.  Rows outside [c, s) are zero.
+__device__ inline void linv_column(const double* __restrict__ L, int b, int s, int c, int lane, double (&r)[4]) {
+  double invd[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = lane + 64 * m;
+    r[m] = (i == c && c < s) ? 1.0 : 0.0;
+    invd[m] = (i < s) ? 1.0 / L[(int64_t)i * b + i] : 0.0;
+  }
+  if (c >= s) return;
+  double cur[4], nxt[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = lane + 64 * m;
+    cur[m] = (i > c && i < s) ? L[(int64_t)c * b + i] : 0.0;
+  }
+  for (int t = c; t < s; ++t) {
+    // column t + 1 of L, ahead of the chain
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = lane + 64 * m;
+      nxt[m] = (t + 1 < s && i > t + 1 && i < s) ? L[(int64_t)(t + 1) * b + i] : 0.0;
+    }
+    const int mt = t >> 6, lt = t & 63;
+    const double own = mt == 0 ? r[0] : mt == 1 ? r[1] : mt == 2 ? r[2] : r[3];
+    const double ownd = mt == 0 ? invd[0] : mt == 1 ? invd[1] : mt == 2 ? invd[2] : invd[3];
+    const double xt = readlane_f64(own, lt) * readlane_f64(ownd, lt);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (m == mt && lane == lt) r[m] = xt;
+      r[m] = fma(-cur[m], xt, r[m]);     // cur is zero outside rows t+1 .. s-1
+      cur[m] = nxt[m];
+    }
+  }
+}
+
 // Squared distance by direct differences (a point paired with itself gives 0).
 __device__ __attribute__((always_inline)) inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
   double s = 0.0;

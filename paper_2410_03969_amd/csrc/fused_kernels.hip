@@ -37,13 +37,22 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-constexpr int FW = 4;            // wavefronts per workgroup
 constexpr int FNB = 2;           // 16-row tiles per wavefront
-constexpr int FROWS = FW * FNB * 16;  // rows per workgroup tile
 constexpr int FKC = 32;          // contraction chunk
 constexpr int FCROW = 80;        // LDS bytes per staged column and plane (64 + 16 padding)
 constexpr int FGROW = 64;        // global bytes per operand column and plane
-constexpr int EROW = FNB * 16 + 1;    // padded row count of the store window
+constexpr int EROW = 36;         // padded row count of the store window (16-byte rows)
+
+// Lower-triangular blocks of the permuted inverse factor: block (mt, tc)
+// holds rows i = 16 mt .. 16 mt + 15 and the t-chunk tc, and is nonzero only
+// if 32 tc <= 16 mt + 15.  Resident form: the blocks of row block mt follow
+// those of mt - 1, each 16 rows of FCROW bytes.
+__host__ __device__ constexpr int tri_row_blocks(int mt) { return (16 * mt + 15) / 32 + 1; }
+__host__ __device__ constexpr int tri_base(int mt) {
+  int b = 0;
+  for (int m = 0; m < mt; ++m) b += tri_row_blocks(m);
+  return b;
+}
 
 struct FusedArgs {
   const __bf16* Fb;         // panel-blocked BF16 planes of F
@@ -72,7 +81,12 @@ __device__ inline void split_hi_lo(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <int PASSES, int NCBT, int DX, int FD>
+// FW wavefronts per workgroup.  RES: the whole lower triangle of the inverse
+// factor stays in LDS for the launch (one 8-wavefront workgroup per CU), so the
+// solve needs no staging; otherwise its chunks stream through the ring (two
+// 4-wavefront workgroups per CU, for the three-product mode whose two planes
+// do not fit).
+template <int PASSES, int NCBT, int DX, int FD, int FW, bool RES>
 __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_round(FusedArgs a) {
   constexpr int SPL = PASSES == 3 ? 2 : 1;
   constexpr int CP = NCBT * 16;                 // padded column count
@@ -83,10 +97,21 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   constexpr int PER_T = (PIECES + 64 * FW - 1) / (64 * FW);
   constexpr int PLANE_E = PH * FKC;             // elements per plane of a blocked chunk
   constexpr int CHUNK_E = SPL * PLANE_E;
-  constexpr int RING = (2 * STAGE > FW * 64 * EROW * 4) ? 2 * STAGE : FW * 64 * EROW * 4;
-  constexpr int DUMMY = RING + CP * DX * 4;      // 16-byte sink of surplus staging pieces
+  constexpr int FROWS = FW * FNB * 16;           // rows per workgroup tile
+  constexpr int WC = RES ? 32 : 64;             // columns per store window
+  constexpr int RING = (2 * STAGE > FW * WC * EROW * 4) ? 2 * STAGE : FW * WC * EROW * 4;
+  constexpr int TRI = RES ? tri_base(NCBT) * 16 * FCROW : 0;   // resident inverse factor
+  constexpr int XPS = RING + TRI;
+  constexpr int YN = XPS + CP * DX * 4;         // squared norms of the accepted points
+  constexpr int DUMMY = YN + CP * 4;            // 16-byte sink of surplus staging pieces
   __shared__ __attribute__((aligned(16))) unsigned char lds[DUMMY + 16];
-  float* xps = (float*)(lds + RING);
+  float* xps = (float*)(lds + XPS);
+  float* yn = (float*)(lds + YN);
+  // Distances: the three-product mode differences the coordinates directly;
+  // the one-product mode, whose C is rounded to BF16 anyway, uses
+  // |x|^2 + |y|^2 - 2 x.y (half the arithmetic; its FP32 cancellation error,
+  // about |x|^2 * 2^-23, is far below the BF16 rounding of C).
+  constexpr bool EXPAND = PASSES == 1;
 
   const RoundState* st = a.st;
   if (st->status != ST_RUNNING) return;
@@ -103,14 +128,34 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     const int c = q / DX, t = q % DX;
     xps[q] = (c < s && t < d) ? (float)a.Xp[(int64_t)c * d + t] : 0.f;
   }
+  if constexpr (EXPAND) {
+    for (int c = tid0; c < CP; c += 64 * FW) {
+      float n2 = 0.f;
+      for (int t = 0; t < d && c < s; ++t) {
+        const float y = (float)a.Xp[(int64_t)c * d + t];
+        n2 = fmaf(y, y, n2);
+      }
+      yn[c] = n2;
+    }
+  }
+
+  if constexpr (RES) {
+    // the inverse factor's triangle, once per launch (ordered before its first
+    // use by the first barrier of the tile loop)
+    for (int q = tid0; q < TRI / 16; q += 64 * FW)
+      *(u4*)(lds + RING + q * 16) = *(const u4*)(a.Bm2 + (size_t)q * 16);
+  }
 
   // ---- small-operand ring: stream position q < nk is chunk q of Bm1, then
-  // the NT chunks of the inverse factor
+  // (streaming form) the NT chunks of the inverse factor
+  const int64_t nkl = nk > 0 ? nk - 1 : 0;       // last valid chunk index
   u4 sbuf[PER_T];
   int tid = tid0;
   auto fetch = [&](int64_t q) {
-    const unsigned char* src = (q < nk) ? a.Bm1 + (size_t)q * SPL * CP * FGROW
-                                        : a.Bm2 + (size_t)((q - nk) % NT) * SPL * CP * FGROW;
+    const unsigned char* src;
+    if constexpr (RES) src = a.Bm1 + (size_t)(q < nkl ? q : nkl) * SPL * CP * FGROW;
+    else src = (q < nk) ? a.Bm1 + (size_t)q * SPL * CP * FGROW
+                        : a.Bm2 + (size_t)((q - nk) % NT) * SPL * CP * FGROW;
     // every thread issues the same loads (a piece index past the stage is
     // clamped and its value dropped at the commit), so the number of loads in
     // flight is the same on every path and the waits stay exact
@@ -172,7 +217,6 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // are never consumed); only the products are guarded.  The
     // load counter is in-order, so the fetch goes first: the wait before its
     // commit leaves the F loads in flight.
-    const int64_t nkl = nk > 0 ? nk - 1 : 0;       // last valid chunk index
     fetch(0);
 #pragma unroll
     for (int u = 0; u < FD - 1; ++u) loadF(fr[u], u < nkl ? u : nkl);
@@ -219,6 +263,14 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       }
     }
 
+    float xn[FNB];
+#pragma unroll
+    for (int nb = 0; nb < FNB; ++nb) {
+      float n2 = 0.f;
+#pragma unroll
+      for (int t = 0; t < DX; ++t) n2 = fmaf(xr[nb][t], xr[nb][t], n2);
+      xn[nb] = n2;
+    }
     // ---- kernel columns and solve.  (A pass per 16-row tile would halve the
     // live solve state but streams the inverse factor twice; with this
     // compiler it spilled more, so both tiles are solved in one pass.)
@@ -243,13 +295,21 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
               float xp[DX];
 #pragma unroll
               for (int t = 0; t < DX; ++t) xp[t] = xps[c * DX + t];
+              const float ync = EXPAND ? yn[c] : 0.f;
 #pragma unroll
               for (int ib = 0; ib < NPB; ++ib) {
                 float r2 = 0.f;
+                if constexpr (EXPAND) {
+                  float dot = 0.f;
 #pragma unroll
-                for (int t = 0; t < DX; ++t) {
-                  const float e = xr[nb0 + ib][t] - xp[t];
-                  r2 = fmaf(e, e, r2);
+                  for (int t = 0; t < DX; ++t) dot = fmaf(xr[nb0 + ib][t], xp[t], dot);
+                  r2 = fmaxf(fmaf(-2.f, dot, xn[nb0 + ib] + ync), 0.f);
+                } else {
+#pragma unroll
+                  for (int t = 0; t < DX; ++t) {
+                    const float e = xr[nb0 + ib][t] - xp[t];
+                    r2 = fmaf(e, e, r2);
+                  }
                 }
                 // evaluated for every column (the padding coordinates are
                 // zero) and then selected: no lane mask per element
@@ -286,15 +346,19 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
       for (int tc = 0; tc < NT; ++tc) {
         const int64_t q = nk + pass * NT + tc;
-        const bool more = tc + 1 < NT || pass + 1 < NPASS;
+        const bool more = !RES && (tc + 1 < NT || pass + 1 < NPASS);
         if (more) fetch(q + 1);
         const unsigned char* L = lds + (q & 1) * STAGE;
 #pragma unroll
         for (int mt = 0; mt < NCBT; ++mt) {
           if (32 * tc <= 16 * mt + 15) {
-            const bf8 ah = *(const bf8*)(L + (mt * 16 + l16) * FCROW + g * 16);
-            bf8 al;
-            if constexpr (PASSES == 3) al = *(const bf8*)(L + CP * FCROW + (mt * 16 + l16) * FCROW + g * 16);
+            bf8 ah, al;
+            if constexpr (RES) {
+              ah = *(const bf8*)(lds + RING + (tri_base(mt) + tc) * 16 * FCROW + l16 * FCROW + g * 16);
+            } else {
+              ah = *(const bf8*)(L + (mt * 16 + l16) * FCROW + g * 16);
+              if constexpr (PASSES == 3) al = *(const bf8*)(L + CP * FCROW + (mt * 16 + l16) * FCROW + g * 16);
+            }
 #pragma unroll
             for (int ib = 0; ib < NPB; ++ib) {
               f4& gq = gacc[nb0 + ib][mt];
@@ -306,13 +370,14 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
             }
           }
         }
-        if (more) commit((q + 1) & 1);
-        __syncthreads();
+        if constexpr (!RES) {
+          if (more) commit((q + 1) & 1);
+          __syncthreads();
+        }
       }
     }
 
-    // ---- 3. row norms, then the stores through a per-wavefront LDS window
-    // of 64 columns (the ring is free after the last barrier of the solve).
+    // ---- 3. row norms, then the stores through a per-wavefront LDS window.
     // Lane (g, l16) holds G(row_w + 16 nb + l16, i) for i = 16 mt + 4 g + j.
 #pragma unroll
     for (int nb = 0; nb < FNB; ++nb) {
@@ -329,42 +394,59 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       const int64_t row = row_w + nb * 16 + l16;
       if (row < N && g == 0) a.P[row] = g2;
     }
-    float* E = (float*)lds + w * (64 * EROW);   // E[col][row], 64 columns x 32 rows
+    // E[col][row]: WC columns x 32 rows of this wavefront (the ring area: no
+    // wavefront reads the ring after the last barrier of the contraction)
+    float* E = (float*)lds + w * (WC * EROW);
     const int nrows = (N - row_w) < (FNB * 16) ? (int)(N - row_w) : FNB * 16;
+    const bool vec_cols = (N & 3) == 0;          // 16-byte aligned columns of F
+    // row row_w of the blocked copy (a wavefront's 32 rows lie in one panel)
+    __bf16* brow = a.Fbw + (row_w / PH) * a.nkc * (int64_t)CHUNK_E + (row_w % PH) * FKC;
 #pragma unroll
-    for (int w0 = 0; w0 < CP; w0 += 64) {
+    for (int w0 = 0; w0 < CP; w0 += WC) {
 #pragma unroll
-      for (int mt = w0 / 16; mt < w0 / 16 + 4 && mt < NCBT; ++mt)
+      for (int mt = w0 / 16; mt < w0 / 16 + WC / 16 && mt < NCBT; ++mt)
 #pragma unroll
         for (int nb = 0; nb < FNB; ++nb)
 #pragma unroll
           for (int j = 0; j < 4; ++j) E[(mt * 16 - w0 + 4 * g + j) * EROW + nb * 16 + l16] = gacc[nb][mt][j];
       int wv = s - w0;
-      if (wv > 64) wv = 64;
-      // F, column-major: two columns per store, 32 consecutive rows each
-      for (int cc = lane >> 5; cc < wv; cc += 2) {
-        const int rl = lane & 31;
-        if (rl < nrows) a.Fu[(kr + w0 + cc) * N + row_w + rl] = E[cc * EROW + rl];
-      }
-      // blocked BF16 copy: one row per store, 64 consecutive columns
-      if (lane < wv)
-        for (int rl = 0; rl < nrows; ++rl) {
-          const int64_t row = row_w + rl;
-          const int64_t col = kr + w0 + lane;
-          __bf16* p = a.Fbw + (((row / PH) * a.nkc + col / FKC) * SPL) * (int64_t)PLANE_E + (row % PH) * FKC + col % FKC;
-          __bf16 hi, lo;
-          split_hi_lo(E[lane * EROW + rl], hi, lo);
-          p[0] = hi;
-          if constexpr (SPL == 2) p[PLANE_E] = lo;
+      if (wv > WC) wv = WC;
+      // F, column-major: 4 consecutive rows per lane (16-byte stores), or one
+      // row per lane when the columns are not 16-byte aligned
+      if (vec_cols && nrows == FNB * 16) {
+        for (int cc = lane >> 3; cc < wv; cc += 8) {
+          const int r4 = 4 * (lane & 7);
+          *(f4*)(a.Fu + (kr + w0 + cc) * N + row_w + r4) = *(const f4*)(E + cc * EROW + r4);
         }
+      } else {
+        for (int cc = lane >> 5; cc < wv; cc += 2) {
+          const int rl = lane & 31;
+          if (rl < nrows) a.Fu[(kr + w0 + cc) * N + row_w + rl] = E[cc * EROW + rl];
+        }
+      }
+      // blocked BF16 copy: 64 / WC rows per store, WC consecutive columns each
+      {
+        constexpr int RPS = 64 / WC;               // rows per store instruction
+        const int cl = lane % WC, rsub = lane / WC;
+        const int64_t col = kr + w0 + cl;
+        __bf16* p = brow + (col / FKC) * (int64_t)CHUNK_E + col % FKC + rsub * FKC;
+        if (cl < wv)
+          for (int rl = rsub; rl < nrows; rl += RPS, p += RPS * FKC) {
+            __bf16 hi, lo;
+            split_hi_lo(E[cl * EROW + rl], hi, lo);
+            p[0] = hi;
+            if constexpr (SPL == 2) p[PLANE_E] = lo;
+          }
+      }
     }
     // zeros after the last column up to the end of its chunk
     {
       const int64_t zbeg = kr + s, zend = (kr + s + FKC - 1) / FKC * FKC;
       const int nz = (int)(zend - zbeg);
       for (int q = lane; q < nz * nrows; q += 64) {
-        const int64_t row = row_w + q / nz, col = zbeg + q % nz;
-        __bf16* p = a.Fbw + (((row / PH) * a.nkc + col / FKC) * SPL) * (int64_t)PLANE_E + (row % PH) * FKC + col % FKC;
+        const int rl = q / nz;
+        const int64_t col = zbeg + q % nz;
+        __bf16* p = brow + (col / FKC) * (int64_t)CHUNK_E + col % FKC + rl * FKC;
         p[0] = (__bf16)0.f;
         if constexpr (SPL == 2) p[PLANE_E] = (__bf16)0.f;
       }
@@ -399,36 +481,36 @@ __global__ __launch_bounds__(256) void k_fused_bm1(const __bf16* __restrict__ Fb
 // Inverse of the s x s lower factor L (column-major, ld b), one workgroup per
 // column t: forward substitution, then Linv(i, t) stored at chunk t / 32, slot
 // solve_slot(t % 32), column i (zero outside i, t < s and below the diagonal).
-template <int SPL>
+template <int SPL, bool RES>
 __global__ __launch_bounds__(64) void k_fused_linv(const double* __restrict__ L, int b, int CP,
                                                    unsigned char* __restrict__ Bm2, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
-  __shared__ double x[BMAX];
-  if (c < s) {
-    for (int i = lane; i < s; i += 64) x[i] = 0.0;
-    __syncthreads();
-    if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
-    __syncthreads();
-    for (int i = c + 1; i < s; ++i) {
-      double p = 0.0;
-      for (int t = c + lane; t < i; t += 64) p += L[(int64_t)t * b + i] * x[t];
+  __shared__ double x[256];
+  double r[4];
+  linv_column(L, b, s, c, lane, r);
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      if (lane == 0) x[i] = -p / L[(int64_t)i * b + i];
-      __syncthreads();
-    }
-  }
+  for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
+  __syncthreads();
   const int tc = c / FKC, slot = solve_slot(c % FKC);
-  for (int i = lane; i < CP; i += 64) {
-    const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
-    __bf16 hi, lo;
-    split_hi_lo((float)v, hi, lo);
-    unsigned char* base = Bm2 + (size_t)tc * SPL * CP * FGROW + (size_t)i * FGROW + slot * 2;
-    *(__bf16*)base = hi;
-    if (SPL == 2) *(__bf16*)(base + (size_t)CP * FGROW) = lo;
+  if constexpr (RES) {
+    // rows 32 tc .. CP - 1 of the blocks (i / 16, tc) of the resident triangle
+    for (int i = FKC * tc + lane; i < CP; i += 64) {
+      const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
+      unsigned char* base = Bm2 + (size_t)(tri_base(i / 16) + tc) * 16 * FCROW + (size_t)(i % 16) * FCROW + slot * 2;
+      *(__bf16*)base = (__bf16)(float)v;
+    }
+  } else {
+    for (int i = lane; i < CP; i += 64) {
+      const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
+      __bf16 hi, lo;
+      split_hi_lo((float)v, hi, lo);
+      unsigned char* base = Bm2 + (size_t)tc * SPL * CP * FGROW + (size_t)i * FGROW + slot * 2;
+      *(__bf16*)base = hi;
+      if (SPL == 2) *(__bf16*)(base + (size_t)CP * FGROW) = lo;
+    }
   }
 }
 
@@ -442,16 +524,28 @@ int ncbt_for(int b) {
   return -1;
 }
 
-template <int PASSES, int NCBT, int DX>
-void launch_fused_t(hipStream_t s, const FusedRound& r, const RoundState* st) {
+// One-plane BF16: resident inverse factor, one 8-wavefront workgroup per CU.
+// Three-product BF16: streamed inverse factor, two 4-wavefront workgroups per CU.
+template <int PASSES>
+struct FusedShape {
+  static constexpr bool RES = PASSES == 1;
+  static constexpr int FW = RES ? 8 : 4;
+  static constexpr int PER_CU = RES ? 1 : 2;
   // F chunks in flight: the three-product mode spends three times the matrix
   // time per chunk, so one chunk ahead hides as much latency
-  constexpr int FD = PASSES == 3 ? 2 : 4;
+  static constexpr int FD = PASSES == 3 ? 2 : 4;
+};
+
+template <int PASSES, int NCBT, int DX>
+void launch_fused_t(hipStream_t s, const FusedRound& r, const RoundState* st) {
+  using SH = FusedShape<PASSES>;
+  constexpr int FROWS = SH::FW * FNB * 16;
   FusedArgs a{(const __bf16*)r.Fb, r.nkc, r.N, r.Bm1, r.Bm2, r.X, r.d, r.Xp, kfast_of(r.kp), (float*)r.F,
               (__bf16*)r.Fb, r.P, st, (int)((r.N + FROWS - 1) / FROWS)};
-  int grid = r.grid;
+  int grid = r.grid / 2 * SH::PER_CU;   // r.grid is two per CU
   if (grid > a.ntiles) grid = a.ntiles;
-  hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, FD>), dim3(grid), dim3(64 * FW), 0, s, a);
+  hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES>), dim3(grid), dim3(64 * SH::FW), 0,
+                     s, a);
 }
 
 template <int PASSES, int NCBT>
@@ -486,7 +580,9 @@ size_t fused_operand_bytes(int prec, int64_t kmax, int b) {
   const int64_t chunks = (kmax + FKC - 1) / FKC;
   const int64_t nt = (ncbt + 1) / 2;
   const int64_t m = chunks > nt ? chunks : nt;
-  return (size_t)m * spl * cp * FGROW;
+  const size_t streamed = (size_t)m * spl * cp * FGROW;
+  const size_t resident = (size_t)tri_base(ncbt) * 16 * FCROW;   // one-plane mode
+  return streamed > resident ? streamed : resident;
 }
 
 void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
@@ -496,11 +592,11 @@ void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64
   if (prec == 2) {
     hipLaunchKernelGGL(k_fused_bm1<2>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
                        r.Bm1, st);
-    hipLaunchKernelGGL(k_fused_linv<2>, dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
+    hipLaunchKernelGGL((k_fused_linv<2, false>), dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
   } else {
     hipLaunchKernelGGL(k_fused_bm1<1>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
                        r.Bm1, st);
-    hipLaunchKernelGGL(k_fused_linv<1>, dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
+    hipLaunchKernelGGL((k_fused_linv<1, true>), dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
   }
 }
 

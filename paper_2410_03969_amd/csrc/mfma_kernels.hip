@@ -476,7 +476,13 @@ __global__ __launch_bounds__(64) void k_trinv_bm(const double* __restrict__ L, i
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   __shared__ double x[BMAX];
-  if (c < s) {
+  if (s <= 256) {
+    double r[4];
+    linv_column(L, b, s, c, lane, r);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
+    __syncthreads();
+  } else if (c < s) {
     for (int i = lane; i < s; i += 64) x[i] = 0.0;
     __syncthreads();
     if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
