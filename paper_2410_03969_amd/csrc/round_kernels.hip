@@ -314,13 +314,19 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
 
 // Register-blocked form for b <= 248.  The lower triangle is cut into 8 x 8
 // blocks; each of the 512 threads owns at most one block (column-major
-// triangular order) and keeps it in registers.  Before step i the owners of
-// column i publish it (as updated by the earlier steps) in a double-buffered
-// LDS column; every thread then evaluates the acceptance test of proposal i
-// identically, and an accepted column, scaled by 1/sqrt(h_ii), updates the
-// owned trailing blocks.  One barrier per proposal.  The scaled accepted
-// columns are kept in H (no longer needed once in registers) and compacted
-// into L(T,T) at the end.
+// triangular order) and keeps it in registers.  The proposals are taken 8 at
+// a time (block column I):
+//  A. the owner of the diagonal block (I, I) runs the tests of Alg. 1 on its
+//     8 proposals in registers (an accepted column is scaled by 1/sqrt(h) and
+//     applied to the rest of the block) and publishes the decisions and the
+//     block's scaled columns;
+//  B. the owners of the blocks below it scale their rows of the accepted
+//     columns and apply them to the rest of their rows, and publish them;
+//  C. the owners of trailing blocks apply the accepted columns.
+// Every matrix entry receives the same operations in the same order as in the
+// one-column-at-a-time right-looking form; two barriers per 8 proposals.  The
+// scaled accepted columns are kept in H (no longer needed once in registers)
+// and compacted into L(T,T) at the end.
 constexpr int RB = 8;                 // block edge
 constexpr int REJECT_REG_THREADS = 512;
 constexpr int REJECT_REG_BMAX = 248;  // 31 * 32 / 2 = 496 blocks <= 512 threads
@@ -332,7 +338,10 @@ __global__ __launch_bounds__(REJECT_REG_THREADS) void k_reject_reg(double* __res
                                                                    int64_t* __restrict__ pivots,
                                                                    double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
-  __shared__ double col[2][REJECT_REG_BMAX + RB];
+  __shared__ double PL[2][RB][REJECT_REG_BMAX + RB];  // scaled accepted columns, by in-block index
+  __shared__ double Lb[2][RB][RB];                      // their rows inside the diagonal block
+  __shared__ double Rs[2][RB];                          // 1/sqrt(h) of the accepted proposals
+  __shared__ int bmask[2];                              // accepted proposals of the block
   __shared__ double ul[REJECT_REG_BMAX], Vs[REJECT_REG_BMAX];
   __shared__ short prv[REJECT_REG_BMAX], accl[REJECT_REG_BMAX];
   __shared__ unsigned char tk[REJECT_REG_BMAX];
@@ -369,77 +378,97 @@ __global__ __launch_bounds__(REJECT_REG_THREADS) void k_reject_reg(double* __res
     prv[tid] = (short)p;
     tk[tid] = 0;
   }
-  // rows past b of the column buffers stay zero (read by edge blocks)
-  for (int q = tid; q < 2 * (REJECT_REG_BMAX + RB); q += nthr) (&col[0][0])[q] = 0.0;
   __syncthreads();
 
-  // publish column RB * I + CC (its current values) into buffer CC & 1; the
-  // column inside the block is a compile-time index (a runtime index into v
-  // would move it to scratch memory)
-  auto publish = [&](int I, auto ccv) {
-    constexpr int CC = decltype(ccv)::value;
-    const int c = RB * I + CC;
-    if (bl == I) {
-#pragma unroll
-      for (int rr = 0; rr < RB; ++rr) {
-        const int j = RB * bj + rr;
-        if (j >= c && j < b) col[CC & 1][j] = v[rr][CC];
-      }
-    }
-  };
-  publish(0, std::integral_constant<int, 0>{});
-  __syncthreads();
-
-  // step i = RB I + II: proposal i
   int nacc = 0;
-  auto step = [&](int I, auto iiv) -> bool {
-    constexpr int II = decltype(iiv)::value;
-    const int i = RB * I + II;
-    if (i >= b || nacc >= cap) return false;
-    const double* ci = col[II & 1];
-    const double h = ci[i];
-    const int p = prv[i];
-    const bool dup = p >= 0 && tk[p];
-    const bool a = !dup && (ul[i] * Vs[i] < h);
-    if (a) {
-      const double rsq = 1.0 / sqrt(h);
-      if (tid >= i && tid < b) H[(int64_t)nacc * b + tid] = ci[tid] * rsq;
-      if (bl >= I) {                         // the block has columns after i
-        double sj[RB], sl[RB];
+  for (int I = 0; I < nbb && nacc < cap; ++I) {
+    const int buf = I & 1;
+    // A: the eight tests, on the diagonal block
+    if (bj == I && bl == I) {
+      int mask = 0, cnt = 0;
 #pragma unroll
-        for (int t = 0; t < RB; ++t) {
-          sj[t] = ci[RB * bj + t] * rsq;
-          sl[t] = ci[RB * bl + t] * rsq;
+      for (int ii = 0; ii < RB; ++ii) {
+        const int i = RB * I + ii;
+        if (i < b && nacc + cnt < cap) {
+          const double h = v[ii][ii];
+          const int p = prv[i];
+          const bool dup = p >= 0 && tk[p];
+          const bool a = !dup && (ul[i] * Vs[i] < h);
+          tk[i] = (a || dup) ? 1 : 0;
+          if (a) {
+            const double rsq = 1.0 / sqrt(h);
+            double col[RB];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) col[rr] = (rr >= ii) ? v[rr][ii] * rsq : 0.0;
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              Lb[buf][ii][rr] = col[rr];
+              if (rr >= ii && RB * I + rr < b) H[(int64_t)(nacc + cnt) * b + RB * I + rr] = col[rr];
+            }
+            Rs[buf][ii] = rsq;
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+              for (int cc = 0; cc < RB; ++cc)
+                if (cc > ii && rr >= cc) v[rr][cc] = fma(-col[rr], col[cc], v[rr][cc]);
+            accl[nacc + cnt] = (short)i;
+            mask |= 1 << ii;
+            ++cnt;
+          }
         }
-        // the whole block is updated: entries in columns <= i are no longer
-        // read (column i was published before this step), and the column
-        // buffer rows they pick up are finite
+      }
+      bmask[buf] = mask;
+    }
+    __syncthreads();
+    const int mask = bmask[buf];
+    if (mask == 0) continue;
+    // B: the rows below the diagonal block
+    if (bl == I && bj > I) {
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
+      for (int ii = 0; ii < RB; ++ii) {
+        if ((mask >> ii) & 1) {
+          const double rsq = Rs[buf][ii];
+          const int rank = __popc(mask & ((1 << ii) - 1));
+          double pl[RB];
 #pragma unroll
-          for (int cc = 0; cc < RB; ++cc) v[rr][cc] = fma(-sj[rr], sl[cc], v[rr][cc]);
+          for (int rr = 0; rr < RB; ++rr) {
+            pl[rr] = v[rr][ii] * rsq;
+            const int j = RB * bj + rr;
+            PL[buf][ii][j] = pl[rr];
+            if (j < b) H[(int64_t)(nacc + rank) * b + j] = pl[rr];
+          }
+#pragma unroll
+          for (int cc = ii + 1; cc < RB; ++cc) {
+            const double lb = Lb[buf][ii][cc];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) v[rr][cc] = fma(-pl[rr], lb, v[rr][cc]);
+          }
+        }
       }
     }
-    if (tid == 0) {
-      tk[i] = (a || dup) ? 1 : 0;
-      if (a) accl[nacc] = (short)i;
-    }
-    nacc += a ? 1 : 0;
-    if (II < RB - 1) publish(I, std::integral_constant<int, (II + 1) % RB>{});
-    else publish(I + 1, std::integral_constant<int, 0>{});
     __syncthreads();
-    return true;
-  };
-  for (int I = 0; I < nbb; ++I) {
-    if (!step(I, std::integral_constant<int, 0>{})) break;
-    if (!step(I, std::integral_constant<int, 1>{})) break;
-    if (!step(I, std::integral_constant<int, 2>{})) break;
-    if (!step(I, std::integral_constant<int, 3>{})) break;
-    if (!step(I, std::integral_constant<int, 4>{})) break;
-    if (!step(I, std::integral_constant<int, 5>{})) break;
-    if (!step(I, std::integral_constant<int, 6>{})) break;
-    if (!step(I, std::integral_constant<int, 7>{})) break;
+    // C: trailing blocks (entries above the diagonal of a diagonal block and
+    // in padding rows are never read, so whole blocks are updated)
+    if (bl > I) {
+#pragma unroll
+      for (int ii = 0; ii < RB; ++ii) {
+        if ((mask >> ii) & 1) {
+          double sj[RB], sl[RB];
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            sj[t] = PL[buf][ii][RB * bj + t];
+            sl[t] = PL[buf][ii][RB * bl + t];
+          }
+#pragma unroll
+          for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+            for (int cc = 0; cc < RB; ++cc) v[rr][cc] = fma(-sj[rr], sl[cc], v[rr][cc]);
+        }
+      }
+    }
+    nacc += __popc(mask);
   }
+  __syncthreads();
   // L = L(T,T), dense column-major: L(a, c) = scaled column c at row accl[a]
   for (int q = tid; q < nacc * nacc; q += nthr) {
     const int a = q % nacc, c = q / nacc;
