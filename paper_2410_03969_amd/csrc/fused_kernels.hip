@@ -7,15 +7,15 @@
 //   2. G^T = Linv C^T on the matrix cores, the accumulators of step 1 serving
 //      directly as the operand (see the slot permutation below);
 //   3. G into F(:, k_r : k_r + s_r) (column-major FP32), into the panel-blocked
-//      BF16 copy of F that the next rounds contract over, and the FP64 row
-//      norms of G for the residual-diagonal update.
+//      BF16 copy of F that the next rounds contract over, and the row norms
+//      of G for the residual-diagonal update.
 //
-// Workgroups are persistent (two per CU) and walk the row tiles; each F
-// element is read from HBM once per round.  Wavefront w owns 32 rows of the
-// tile and all columns; its F slices are loaded straight from HBM into
-// registers FD chunks ahead.  The small operands (Bm1 chunks, then the chunks
-// of the permuted inverse factor) stream through a two-stage LDS ring shared
-// by the four wavefronts.
+// Workgroups are persistent and walk the row tiles; each F element is read
+// from HBM once per round.  Wavefront w owns 32 rows of the tile and all
+// columns; its F slices are loaded straight from HBM into registers FD chunks
+// ahead.  The small operands (Bm1 chunks, and in the three-product mode the
+// chunks of the permuted inverse factor) stream through a two-stage LDS ring
+// shared by the workgroup's wavefronts.
 //
 // Slot permutation.  A 16x16x32 BF16 product takes, in lane (g, n), operand
 // values for contraction slots 8g .. 8g+7 of column n.  The accumulator of
@@ -25,6 +25,8 @@
 // t = 32 tc + 16 + 4g + jj - 4 (jj >= 4, column block 2 tc + 1); the inverse
 // factor is stored with the same slot order, so the product is exact in any
 // order and no lane exchange is needed.
+#include <type_traits>
+
 #include "arpc_common.h"
 #include "arpc_mfma.h"
 
@@ -66,7 +68,7 @@ struct FusedArgs {
   KFast kf;
   float* Fu;                // F, column-major, ld N
   __bf16* Fbw;              // Fb (written)
-  double* P;                // FP64 row norms of G
+  double* P;                // row norms of G
   const RoundState* st;
   int ntiles;
 };
@@ -86,7 +88,7 @@ __device__ inline void split_hi_lo(float x, __bf16& hi, __bf16& lo) {
 // solve needs no staging; otherwise its chunks stream through the ring (two
 // 4-wavefront workgroups per CU, for the three-product mode whose two planes
 // do not fit).
-template <int PASSES, int NCBT, int DX, int FD, int FW, bool RES>
+template <int PASSES, int NCBT, int DX, int FD, int FW, bool RES, bool UR>
 __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_round(FusedArgs a) {
   constexpr int SPL = PASSES == 3 ? 2 : 1;
   constexpr int CP = NCBT * 16;                 // padded column count
@@ -109,8 +111,9 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   float* yn = (float*)(lds + YN);
   // Distances: the three-product mode differences the coordinates directly;
   // the one-product mode, whose C is rounded to BF16 anyway, uses
-  // |x|^2 + |y|^2 - 2 x.y (half the arithmetic; its FP32 cancellation error,
-  // about |x|^2 * 2^-23, is far below the BF16 rounding of C).
+  // |x|^2 + |y|^2 - 2 x.y with the product on the matrix cores (its FP32
+  // cancellation error, about |x|^2 * 2^-23, is far below the BF16 rounding
+  // of C).
   constexpr bool EXPAND = PASSES == 1;
 
   const RoundState* st = a.st;
@@ -123,10 +126,22 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const int d = a.d;
   const int tid0 = threadIdx.x, w = tid0 >> 6;
 
-  // accepted points in FP32, zero-padded to DX coordinates and CP columns
+  // The kernel's scale folds into the points.  Every kernel here is
+  // phi(sqrt(cr) r) with phi(t) = (1 + p1 t + p2 t^2) 2^(-q t) (use_r) or
+  // phi(r^2) = 2^(-cr r^2) (Gaussian), so one scaled squared distance
+  // e = cr |x - y|^2 is all a column needs.
+  const KFast kf = a.kf;
+  const float cr = UR ? kf.scale * kf.scale : kf.q * kf.scale;
+  // accepted points in FP32, zero-padded to DX coordinates and CP columns.
+  // Expanded form: r^2 = |x|^2 + |y|^2 - 2 x.y, the product on the matrix
+  // cores, so the points are stored coordinate-major and scaled by -2, with
+  // |y|^2 beside them; the scale cr multiplies r^2 after the cancellation
+  // (exact for points on an integer grid, as in the unscaled form).  Direct
+  // form: the points scaled by sqrt(cr), column-major.
+  const float sxp = EXPAND ? -2.f : sqrtf(cr);
   for (int q = tid0; q < CP * DX; q += 64 * FW) {
-    const int c = q / DX, t = q % DX;
-    xps[q] = (c < s && t < d) ? (float)a.Xp[(int64_t)c * d + t] : 0.f;
+    const int c = EXPAND ? q % CP : q / DX, t = EXPAND ? q / CP : q % DX;
+    xps[q] = (c < s && t < d) ? sxp * (float)a.Xp[(int64_t)c * d + t] : 0.f;
   }
   if constexpr (EXPAND) {
     for (int c = tid0; c < CP; c += 64 * FW) {
@@ -183,14 +198,20 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, l16 = lane & 15, g = lane >> 4;
     const int64_t row_w = (int64_t)tile * FROWS + w * (FNB * 16);
-    // this lane's rows (tiles nb = 0, 1): row_w + 16 nb + l16
-    float xr[FNB][DX];
+    // this lane's rows (tiles nb = 0, 1): row_w + 16 nb + l16.  Expanded
+    // form: coordinates 4 ks + g only, the B operand of the distance product
+    // (lane (g, n) holds B(k = g, n)); direct form: all coordinates, scaled.
+    constexpr int XR = EXPAND ? DX / 4 : DX;
+    float xr[FNB][XR];
 #pragma unroll
     for (int nb = 0; nb < FNB; ++nb) {
       int64_t r = row_w + nb * 16 + l16;
       if (r >= N) r = N - 1;
 #pragma unroll
-      for (int t = 0; t < DX; ++t) xr[nb][t] = (t < d) ? (float)a.X[r * d + t] : 0.f;
+      for (int t = 0; t < XR; ++t) {
+        const int tt = EXPAND ? 4 * t + g : t;
+        xr[nb][t] = (tt < d) ? (EXPAND ? 1.f : sxp) * (float)a.X[r * d + tt] : 0.f;
+      }
     }
 
     f4 acc[FNB][NCBT];
@@ -263,13 +284,20 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       }
     }
 
-    float xn[FNB];
+    // |x|^2 of this lane's rows (expanded form): the partial sums of the
+    // four lanes that hold a row's coordinates, added in the same order in
+    // each of them
+    float xa[FNB];
+    if constexpr (EXPAND) {
 #pragma unroll
-    for (int nb = 0; nb < FNB; ++nb) {
-      float n2 = 0.f;
+      for (int nb = 0; nb < FNB; ++nb) {
+        float n2 = 0.f;
 #pragma unroll
-      for (int t = 0; t < DX; ++t) n2 = fmaf(xr[nb][t], xr[nb][t], n2);
-      xn[nb] = n2;
+        for (int t = 0; t < XR; ++t) n2 = fmaf(xr[nb][t], xr[nb][t], n2);
+        n2 += __shfl_xor(n2, 16, 64);
+        n2 += __shfl_xor(n2, 32, 64);
+        xa[nb] = n2;
+      }
     }
     // ---- kernel columns and solve.  (A pass per 16-row tile would halve the
     // live solve state but streams the inverse factor twice; with this
@@ -279,48 +307,82 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     for (int pass = 0; pass < NPASS; ++pass) {
       constexpr int NPB = FNB / NPASS;                // row tiles per pass
       const int nb0 = pass * NPB;
-      // kernel columns: C = kappa(x_row, x_c) - acc, zero for c >= s, as the
-      // BF16 operand slices of the solve (slot order above)
+      // kernel columns: C = kappa(x_row, x_c) - acc as the BF16 operand slices
+      // of the solve (slot order above).  Columns c >= s hold finite values
+      // (zero points, zero update) that meet only zero inverse-factor
+      // entries, so they are not masked.
       bf8 ch_[NPB][NT][SPL];
+      // phi of four scaled squared distances
+      auto phi4 = [&](f4 e) __attribute__((always_inline)) {
+        f4 k;
+        if constexpr (UR) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float t = __builtin_amdgcn_sqrtf(fmaxf(e[j], 0.f));
+            k[j] = fmaf(fmaf(kf.p2, t, kf.p1), t, 1.f) * __builtin_amdgcn_exp2f(-kf.q * t);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) k[j] = __builtin_amdgcn_exp2f(-fmaxf(e[j], 0.f));
+        }
+        return k;
+      };
 #pragma unroll
       for (int tc = 0; tc < NT; ++tc) {
         f8 cv[NPB];
 #pragma unroll
-        for (int half = 0; half < 2; ++half)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int cb = 2 * tc + half;
-            if (cb < NCBT) {
-              const int c = cb * 16 + 4 * g + j;
-              float xp[DX];
-#pragma unroll
-              for (int t = 0; t < DX; ++t) xp[t] = xps[c * DX + t];
-              const float ync = EXPAND ? yn[c] : 0.f;
+        for (int half = 0; half < 2; ++half) {
+          const int cb = 2 * tc + half;
+          if (cb < NCBT) {
+            if constexpr (EXPAND) {
+              // r^2 = |x|^2 + |y|^2 - 2 x.y: lane (g, n) of a 16x16x4 FP32
+              // product holds (column 16 cb + 4 g + j, row n), the layout of
+              // the update accumulators
+              const f4 y4 = *(const f4*)(yn + cb * 16 + 4 * g);
 #pragma unroll
               for (int ib = 0; ib < NPB; ++ib) {
-                float r2 = 0.f;
-                if constexpr (EXPAND) {
-                  float dot = 0.f;
+                f4 e4 = y4 + xa[nb0 + ib];
 #pragma unroll
-                  for (int t = 0; t < DX; ++t) dot = fmaf(xr[nb0 + ib][t], xp[t], dot);
-                  r2 = fmaxf(fmaf(-2.f, dot, xn[nb0 + ib] + ync), 0.f);
-                } else {
+                for (int ks = 0; ks < XR; ++ks)
+                  e4 = __builtin_amdgcn_mfma_f32_16x16x4f32(xps[(4 * ks + g) * CP + cb * 16 + l16], xr[nb0 + ib][ks],
+                                                           e4, 0, 0, 0);
+                const f4 k4 = phi4(cr * e4) - acc[nb0 + ib][cb];
 #pragma unroll
-                  for (int t = 0; t < DX; ++t) {
-                    const float e = xr[nb0 + ib][t] - xp[t];
-                    r2 = fmaf(e, e, r2);
-                  }
-                }
-                // evaluated for every column (the padding coordinates are
-                // zero) and then selected: no lane mask per element
-                const float kv = kappa_fast(r2, a.kf) - acc[nb0 + ib][cb][j];
-                cv[ib][4 * half + j] = (c < s) ? kv : 0.f;
+                for (int j = 0; j < 4; ++j) cv[ib][4 * half + j] = k4[j];
               }
             } else {
+              f4 e4[NPB];
 #pragma unroll
-              for (int ib = 0; ib < NPB; ++ib) cv[ib][4 * half + j] = 0.f;
+              for (int j = 0; j < 4; ++j) {
+                const int c = cb * 16 + 4 * g + j;
+                float xp[DX];
+#pragma unroll
+                for (int t = 0; t < DX; ++t) xp[t] = xps[c * DX + t];
+#pragma unroll
+                for (int ib = 0; ib < NPB; ++ib) {
+                  float e = 0.f;
+#pragma unroll
+                  for (int t = 0; t < DX; ++t) {
+                    const float df = xr[nb0 + ib][t] - xp[t];
+                    e = fmaf(df, df, e);
+                  }
+                  e4[ib][j] = e;
+                }
+              }
+#pragma unroll
+              for (int ib = 0; ib < NPB; ++ib) {
+                const f4 k4 = phi4(e4[ib]) - acc[nb0 + ib][cb];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cv[ib][4 * half + j] = k4[j];
+              }
             }
+          } else {
+#pragma unroll
+            for (int ib = 0; ib < NPB; ++ib)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) cv[ib][4 * half + j] = 0.f;
           }
+        }
 #pragma unroll
         for (int ib = 0; ib < NPB; ++ib) {
           ch_[ib][tc][0] = __builtin_convertvector(cv[ib], bf8);
@@ -377,30 +439,94 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       }
     }
 
-    // ---- 3. row norms, then the stores through a per-wavefront LDS window.
-    // Lane (g, l16) holds G(row_w + 16 nb + l16, i) for i = 16 mt + 4 g + j.
+    // ---- 3. row norms, the blocked copy, then F through a per-wavefront LDS
+    // window.  Lane (g, l16) holds G(row_w + 16 nb + l16, i) for
+    // i = 16 mt + 4 g + j; G(:, i) is exactly zero for s <= i < CP (zero rows
+    // of the inverse factor).  Norms: FP32 sums over a lane's 4 NCBT entries
+    // (relative error a few 2^-24, far below the BF16 rounding of G), then
+    // over the four lanes of a row.
 #pragma unroll
     for (int nb = 0; nb < FNB; ++nb) {
-      double g2 = 0.0;
+      float g2 = 0.f;
 #pragma unroll
       for (int mt = 0; mt < NCBT; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float v = gacc[nb][mt][j];
-          g2 += (mt * 16 + 4 * g + j < s) ? (double)v * (double)v : 0.0;
-        }
+        for (int j = 0; j < 4; ++j) g2 = fmaf(gacc[nb][mt][j], gacc[nb][mt][j], g2);
       g2 += __shfl_xor(g2, 16, 64);
       g2 += __shfl_xor(g2, 32, 64);
       const int64_t row = row_w + nb * 16 + l16;
-      if (row < N && g == 0) a.P[row] = g2;
+      if (row < N && g == 0) a.P[row] = (double)g2;
+    }
+    // Blocked BF16 copy, 8-byte stores straight from the accumulators.  Its
+    // columns kr - m .. are cut into groups of four (m = kr mod 4, so a group
+    // never crosses a 32-column chunk): lane (g, l16) of group mt writes
+    // columns kr - m + 16 mt + 4 g .. + 3, which hold G(:, i) for
+    // i = 16 mt + 4 g - m .. + 3: its own entries j < 4 - m, and the last m
+    // entries of the lane before it (lane g - 1, or lane g = 3 of group
+    // mt - 1), fetched with one lane permutation per 32-bit word.  The
+    // groups run on past CP as zeros up to the end of the last chunk, which
+    // the next round's contraction reads whole.  The first group of a round
+    // starts m columns inside the previous round's: that lane writes only its
+    // own 4 - m values.
+    {
+      const int m = (int)(kr & 3);
+      const int64_t zend = (kr + s + FKC - 1) / FKC * FKC;
+      const int sh = 16 * m;
+      const int src = (lane + 48) & 63;                  // lane g - 1 (mod 4), same l16
+#pragma unroll
+      for (int nb = 0; nb < FNB; ++nb) {
+        const int64_t row = row_w + nb * 16 + l16;
+        __bf16* prow = a.Fbw + (row / PH) * a.nkc * (int64_t)CHUNK_E + (row % PH) * FKC;
+        uint64_t tprev[SPL];
+#pragma unroll
+        for (int pl = 0; pl < SPL; ++pl) tprev[pl] = 0;
+#pragma unroll
+        for (int mt = 0; mt < NCBT + 3; ++mt) {
+          if (kr - m + 16 * mt >= zend) break;          // uniform
+          const int64_t a0 = kr - m + 16 * mt + 4 * g;
+          __bf16* p = prow + (a0 / FKC) * (int64_t)CHUNK_E + a0 % FKC;
+          const bool ok = row < N && a0 < zend;
+          const bool first = mt == 0 && g == 0 && m != 0;
+#pragma unroll
+          for (int pl = 0; pl < SPL; ++pl) {
+            uint64_t v = 0;
+            if (mt < NCBT) {
+              const f4 gv = gacc[nb][mt < NCBT ? mt : 0];
+              __bf16 h[4];   // plane 0: BF16 of G; plane 1: BF16 of the remainder
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                h[j] = (__bf16)gv[j];
+                if (pl == 1) h[j] = (__bf16)(gv[j] - (float)h[j]);
+              }
+              v = (uint64_t)__builtin_bit_cast(unsigned short, h[0]) |
+                  ((uint64_t)__builtin_bit_cast(unsigned short, h[1]) << 16) |
+                  ((uint64_t)__builtin_bit_cast(unsigned short, h[2]) << 32) |
+                  ((uint64_t)__builtin_bit_cast(unsigned short, h[3]) << 48);
+            }
+            const unsigned lo32 = __shfl((unsigned)v, src, 64), hi32 = __shfl((unsigned)(v >> 32), src, 64);
+            const uint64_t t = (uint64_t)lo32 | ((uint64_t)hi32 << 32);
+            const uint64_t pv = g == 0 ? tprev[pl] : t;
+            tprev[pl] = t;
+            const uint64_t out = m ? (v << sh) | (pv >> (64 - sh)) : v;
+            __bf16* pp = p + pl * PLANE_E;
+            if (ok) {
+              if (first) {
+#pragma unroll
+                for (int jj = 1; jj < 4; ++jj)
+                  if (jj >= m) pp[jj] = __builtin_bit_cast(__bf16, (unsigned short)(out >> (16 * jj)));
+              } else {
+                *(uint64_t*)pp = out;
+              }
+            }
+          }
+        }
+      }
     }
     // E[col][row]: WC columns x 32 rows of this wavefront (the ring area: no
     // wavefront reads the ring after the last barrier of the contraction)
     float* E = (float*)lds + w * (WC * EROW);
     const int nrows = (N - row_w) < (FNB * 16) ? (int)(N - row_w) : FNB * 16;
     const bool vec_cols = (N & 3) == 0;          // 16-byte aligned columns of F
-    // row row_w of the blocked copy (a wavefront's 32 rows lie in one panel)
-    __bf16* brow = a.Fbw + (row_w / PH) * a.nkc * (int64_t)CHUNK_E + (row_w % PH) * FKC;
 #pragma unroll
     for (int w0 = 0; w0 < CP; w0 += WC) {
 #pragma unroll
@@ -423,32 +549,6 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
           const int rl = lane & 31;
           if (rl < nrows) a.Fu[(kr + w0 + cc) * N + row_w + rl] = E[cc * EROW + rl];
         }
-      }
-      // blocked BF16 copy: 64 / WC rows per store, WC consecutive columns each
-      {
-        constexpr int RPS = 64 / WC;               // rows per store instruction
-        const int cl = lane % WC, rsub = lane / WC;
-        const int64_t col = kr + w0 + cl;
-        __bf16* p = brow + (col / FKC) * (int64_t)CHUNK_E + col % FKC + rsub * FKC;
-        if (cl < wv)
-          for (int rl = rsub; rl < nrows; rl += RPS, p += RPS * FKC) {
-            __bf16 hi, lo;
-            split_hi_lo(E[cl * EROW + rl], hi, lo);
-            p[0] = hi;
-            if constexpr (SPL == 2) p[PLANE_E] = lo;
-          }
-      }
-    }
-    // zeros after the last column up to the end of its chunk
-    {
-      const int64_t zbeg = kr + s, zend = (kr + s + FKC - 1) / FKC * FKC;
-      const int nz = (int)(zend - zbeg);
-      for (int q = lane; q < nz * nrows; q += 64) {
-        const int rl = q / nz;
-        const int64_t col = zbeg + q % nz;
-        __bf16* p = brow + (col / FKC) * (int64_t)CHUNK_E + col % FKC + rl * FKC;
-        p[0] = (__bf16)0.f;
-        if constexpr (SPL == 2) p[PLANE_E] = (__bf16)0.f;
       }
     }
     __syncthreads();   // the window area is the ring of the next tile
@@ -544,8 +644,12 @@ void launch_fused_t(hipStream_t s, const FusedRound& r, const RoundState* st) {
               (__bf16*)r.Fb, r.P, st, (int)((r.N + FROWS - 1) / FROWS)};
   int grid = r.grid / 2 * SH::PER_CU;   // r.grid is two per CU
   if (grid > a.ntiles) grid = a.ntiles;
-  hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES>), dim3(grid), dim3(64 * SH::FW), 0,
-                     s, a);
+  if (a.kf.use_r)
+    hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES, true>), dim3(grid),
+                       dim3(64 * SH::FW), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES, false>), dim3(grid),
+                       dim3(64 * SH::FW), 0, s, a);
 }
 
 template <int PASSES, int NCBT>
