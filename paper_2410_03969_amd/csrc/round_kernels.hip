@@ -243,8 +243,9 @@ __global__ __launch_bounds__(256) void k_gather_H(const double* __restrict__ X, 
 // ------------------------------------------------- RejectionSampleSubmatrix
 // Alg. 1 on the b x b residual submatrix, in one workgroup, right-looking and
 // in place: accepted column i is scaled by 1/sqrt(h_ii) and the trailing
-// lower triangle receives the rank-one Schur update.  Storage: register blocks
-// (b <= 248, below) or the full column-major matrix in global memory.
+// lower triangle receives the rank-one Schur update.  Storage: matrix-core
+// tiles in registers (b <= 256, below) or the full column-major matrix in
+// global memory.
 // Rules beyond the printed test u_i * V < h_ii: a proposal equal to one
 // already accepted in this round is rejected, and at most k - k_r proposals are
 // accepted.  Outputs: accepted local indices, the dense lower Cholesky factor
@@ -312,169 +313,216 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
   if (tid == 0) st->s_r = nacc;
 }
 
-// Register-blocked form for b <= 248.  The lower triangle is cut into 8 x 8
-// blocks; each of the 512 threads owns at most one block (column-major
-// triangular order) and keeps it in registers.  The proposals are taken 8 at
-// a time (block column I):
-//  A. the owner of the diagonal block (I, I) runs the tests of Alg. 1 on its
-//     8 proposals in registers (an accepted column is scaled by 1/sqrt(h) and
-//     applied to the rest of the block) and publishes the decisions and the
-//     block's scaled columns;
-//  B. the owners of the blocks below it scale their rows of the accepted
-//     columns and apply them to the rest of their rows, and publish them;
-//  C. the owners of trailing blocks apply the accepted columns.
-// Every matrix entry receives the same operations in the same order as in the
-// one-column-at-a-time right-looking form; two barriers per 8 proposals.  The
-// scaled accepted columns are kept in H (no longer needed once in registers)
-// and compacted into L(T,T) at the end.
-constexpr int RB = 8;                 // block edge
-constexpr int REJECT_REG_THREADS = 512;
-constexpr int REJECT_REG_BMAX = 248;  // 31 * 32 / 2 = 496 blocks <= 512 threads
+// Tiled form for b <= 256, one workgroup of eight wavefronts.  The trailing
+// submatrix is cut into 16 x 16 tiles held in FP64 matrix-core accumulators
+// (tile t = J (J + 1) / 2 + L of the lower triangle, J >= L, belongs to
+// wavefront t mod 8; entry i of lane (g, n) is row 16 J + g + 4 i, column
+// 16 L + n: the layout of the FP64 16x16x4 product's accumulator).
+// The proposals are taken 16 at a time (block column I):
+//  1. the owners of the tiles of block column I copy them to LDS;
+//  2. wavefront 0 runs the tests of Alg. 1 on the diagonal block, one row per
+//     lane: an accepted column is scaled by 1/sqrt(h) and its rank-one update
+//     applied to the rest of the block (the same operations, in the same
+//     order, as the one-column-at-a-time form);
+//  3. one thread per row below the block solves that row against the accepted
+//     columns (forward substitution, in acceptance order);
+//  4. the trailing tiles receive the rank-16 update on the matrix cores
+//     (rejected columns are zero), four 16x16x4 FP64 products per tile.
+// Three barriers per 16 proposals; the block-column buffer is double-buffered
+// so step 1 of the next block does not wait for step 4.  The scaled accepted
+// columns are kept in H (no longer read once in registers) and compacted into
+// L(T,T) at the end.
+constexpr int RT = 16;                  // tile edge
+constexpr int REJECT_T_THREADS = 512;
+constexpr int REJECT_T_BMAX = 256;
+constexpr int REJECT_T_TPW = 17;        // tiles per wavefront: 136 / 8, rounded up
+constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
 
-__global__ __launch_bounds__(REJECT_REG_THREADS) void k_reject_reg(double* __restrict__ H, int b,
+typedef double rd4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void tile_coords(int t, int& J, int& L) {
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (r * (r + 1) / 2 > t) --r;
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  J = r;
+  L = t - r * (r + 1) / 2;
+}
+
+__global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __restrict__ H, int b,
                                                                    const int64_t* __restrict__ props, Unif un,
                                                                    RoundState* st, double* __restrict__ Lout,
                                                                    int32_t* __restrict__ acc_out,
                                                                    int64_t* __restrict__ pivots,
                                                                    double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
-  __shared__ double PL[2][RB][REJECT_REG_BMAX + RB];  // scaled accepted columns, by in-block index
-  __shared__ double Lb[2][RB][RB];                      // their rows inside the diagonal block
-  __shared__ double Rs[2][RB];                          // 1/sqrt(h) of the accepted proposals
-  __shared__ int bmask[2];                              // accepted proposals of the block
-  __shared__ double ul[REJECT_REG_BMAX], Vs[REJECT_REG_BMAX];
-  __shared__ short prv[REJECT_REG_BMAX], accl[REJECT_REG_BMAX];
-  __shared__ unsigned char tk[REJECT_REG_BMAX];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  __shared__ __attribute__((aligned(16))) double Q[2][REJECT_T_BMAX][QS];  // block column I
+  __shared__ double LD[RT][RT];            // LD[ii][r]: scaled accepted column ii at row r of the block
+  __shared__ double rsq[RT];               // 1/sqrt(h) of the accepted proposals
+  __shared__ double uv[REJECT_T_BMAX];     // u_i V_i of the test
+  __shared__ int64_t pr[REJECT_T_BMAX];
+  __shared__ short prv[REJECT_T_BMAX], accl[REJECT_T_BMAX];
+  __shared__ unsigned char tk[REJECT_T_BMAX];
+  __shared__ int bmask;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // tile coordinates in scalar registers
+  const int g = lane >> 4, l16 = lane & 15;
   const int64_t kr = st->k_r, round = st->round;
   const int cap = (int)((kmax - kr) < b ? (kmax - kr) : b);
-  const int nbb = (b + RB - 1) / RB;
-  const int nblk = nbb * (nbb + 1) / 2;
+  const int nbk = (b + RT - 1) / RT;
+  const int ntile = nbk * (nbk + 1) / 2;
 
-  // owned block (bj, bl), bj >= bl, or none
-  int bj = -1, bl = -1;
-  if (tid < nblk) {
-    int r = (int)((sqrt(8.0 * tid + 1.0) - 1.0) * 0.5);
-    while (r * (r + 1) / 2 > tid) --r;
-    while ((r + 1) * (r + 2) / 2 <= tid) ++r;
-    bj = r;
-    bl = tid - r * (r + 1) / 2;
-  }
-  double v[RB][RB];
+  // this wavefront's tiles of H (the full symmetric matrix; zero padding);
+  // tJ = -1 marks no tile
+  rd4 tr[REJECT_T_TPW];
+  int tJ[REJECT_T_TPW], tL[REJECT_T_TPW];
 #pragma unroll
-  for (int rr = 0; rr < RB; ++rr)
+  for (int k = 0; k < REJECT_T_TPW; ++k) {
+    const int t = w + 8 * k;
+    tr[k] = rd4{0.0, 0.0, 0.0, 0.0};
+    tJ[k] = -1;
+    tL[k] = -1;
+    if (t < ntile) {
+      int J, L;
+      tile_coords(t, J, L);
+      tJ[k] = J;
+      tL[k] = L;
+      const int col = RT * L + l16;
 #pragma unroll
-    for (int cc = 0; cc < RB; ++cc) {
-      const int j = RB * bj + rr, l = RB * bl + cc;
-      v[rr][cc] = (bj >= 0 && j < b && l <= j) ? H[(int64_t)l * b + j] : 0.0;
+      for (int i = 0; i < 4; ++i) {
+        const int row = RT * J + g + 4 * i;
+        if (row < b && col < b) tr[k][i] = H[(int64_t)col * b + row];
+      }
     }
+  }
   if (tid < b) {
-    ul[tid] = H[(int64_t)tid * b + tid];
-    Vs[tid] = stream_uniform(un, 2 * (int64_t)b * round + b + tid);
-    const int64_t me = props[tid];
-    int p = -1;
-    for (int q = tid - 1; q >= 0; --q)
-      if (props[q] == me) { p = q; break; }
-    prv[tid] = (short)p;
+    uv[tid] = H[(int64_t)tid * b + tid] * stream_uniform(un, 2 * (int64_t)b * round + b + tid);
+    pr[tid] = props[tid];
     tk[tid] = 0;
   }
   __syncthreads();
+  // the latest earlier proposal of the same point, eight LDS reads in flight
+  if (tid < b) {
+    const int64_t me = pr[tid];
+    int p = -1;
+    for (int q0 = tid - 1; q0 >= 0 && p < 0; q0 -= 8) {
+      int64_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = (q0 - k >= 0) ? pr[q0 - k] : -1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (p < 0 && v[k] == me) p = q0 - k;
+    }
+    prv[tid] = (short)p;
+  }
 
   int nacc = 0;
-  for (int I = 0; I < nbb && nacc < cap; ++I) {
-    const int buf = I & 1;
-    // A: the eight tests, on the diagonal block
-    if (bj == I && bl == I) {
+  for (int I = 0; I < nbk && nacc < cap; ++I) {
+    double(*Qb)[QS] = Q[I & 1];
+    // 1. block column I into LDS (rows 16 I ..)
+#pragma unroll
+    for (int k = 0; k < REJECT_T_TPW; ++k)
+      if (tL[k] == I)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Qb[RT * tJ[k] + g + 4 * i][l16] = tr[k][i];
+    __syncthreads();
+    // 2. the tests, on the diagonal block: lane r (mod 16) keeps row 16 I + r
+    if (w == 0) {
+      double dr[RT];
+#pragma unroll
+      for (int c = 0; c < RT; ++c) dr[c] = Qb[RT * I + l16][c];
       int mask = 0, cnt = 0;
 #pragma unroll
-      for (int ii = 0; ii < RB; ++ii) {
-        const int i = RB * I + ii;
-        if (i < b && nacc + cnt < cap) {
-          const double h = v[ii][ii];
-          const int p = prv[i];
-          const bool dup = p >= 0 && tk[p];
-          const bool a = !dup && (ul[i] * Vs[i] < h);
-          tk[i] = (a || dup) ? 1 : 0;
-          if (a) {
-            const double rsq = 1.0 / sqrt(h);
-            double col[RB];
+      for (int ii = 0; ii < RT; ++ii) {
+        const int i = RT * I + ii;
+        if (i >= b || nacc + cnt >= cap) continue;   // uniform
+        const double h = readlane_f64(dr[ii], ii);
+        const int p = prv[i];
+        const bool dup = p >= 0 && tk[p];
+        const bool a = !dup && (uv[i] < h);
+        if (lane == 0) tk[i] = (a || dup) ? 1 : 0;
+        if (a) {
+          const double rs = 1.0 / sqrt(h);
+          const double col = (l16 >= ii) ? dr[ii] * rs : 0.0;
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) col[rr] = (rr >= ii) ? v[rr][ii] * rsq : 0.0;
-#pragma unroll
-            for (int rr = 0; rr < RB; ++rr) {
-              Lb[buf][ii][rr] = col[rr];
-              if (rr >= ii && RB * I + rr < b) H[(int64_t)(nacc + cnt) * b + RB * I + rr] = col[rr];
-            }
-            Rs[buf][ii] = rsq;
-#pragma unroll
-            for (int rr = 0; rr < RB; ++rr)
-#pragma unroll
-              for (int cc = 0; cc < RB; ++cc)
-                if (cc > ii && rr >= cc) v[rr][cc] = fma(-col[rr], col[cc], v[rr][cc]);
+          for (int cc = ii + 1; cc < RT; ++cc) dr[cc] = fma(-col, readlane_f64(col, cc), dr[cc]);
+          if (lane < RT) {
+            LD[ii][lane] = col;
+            if (lane >= ii && RT * I + lane < b) H[(int64_t)(nacc + cnt) * b + RT * I + lane] = col;
+          }
+          if (lane == 0) {
+            rsq[ii] = rs;
             accl[nacc + cnt] = (short)i;
-            mask |= 1 << ii;
-            ++cnt;
           }
+          mask |= 1 << ii;
+          ++cnt;
         }
       }
-      bmask[buf] = mask;
+      if (lane == 0) bmask = mask;
     }
     __syncthreads();
-    const int mask = bmask[buf];
+    const int mask = bmask;
     if (mask == 0) continue;
-    // B: the rows below the diagonal block
-    if (bl == I && bj > I) {
+    // 3. the rows below the block against the accepted columns
+    {
+      const int j = RT * (I + 1) + tid;
+      if (j < b) {
+        double q[RT];
 #pragma unroll
-      for (int ii = 0; ii < RB; ++ii) {
-        if ((mask >> ii) & 1) {
-          const double rsq = Rs[buf][ii];
-          const int rank = __popc(mask & ((1 << ii) - 1));
-          double pl[RB];
+        for (int c = 0; c < RT; ++c) q[c] = Qb[j][c];
+        int rank = 0;
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr) {
-            pl[rr] = v[rr][ii] * rsq;
-            const int j = RB * bj + rr;
-            PL[buf][ii][j] = pl[rr];
-            if (j < b) H[(int64_t)(nacc + rank) * b + j] = pl[rr];
-          }
+        for (int ii = 0; ii < RT; ++ii) {
+          if ((mask >> ii) & 1) {
+            const double pl = q[ii] * rsq[ii];
+            q[ii] = pl;
 #pragma unroll
-          for (int cc = ii + 1; cc < RB; ++cc) {
-            const double lb = Lb[buf][ii][cc];
-#pragma unroll
-            for (int rr = 0; rr < RB; ++rr) v[rr][cc] = fma(-pl[rr], lb, v[rr][cc]);
+            for (int cc = ii + 1; cc < RT; ++cc) q[cc] = fma(-pl, LD[ii][cc], q[cc]);
+            H[(int64_t)(nacc + rank) * b + j] = pl;
+            ++rank;
+          } else {
+            q[ii] = 0.0;
           }
         }
+#pragma unroll
+        for (int c = 0; c < RT; ++c) Qb[j][c] = q[c];
       }
     }
     __syncthreads();
-    // C: trailing blocks (entries above the diagonal of a diagonal block and
-    // in padding rows are never read, so whole blocks are updated)
-    if (bl > I) {
+    // 4. trailing tiles: T(J, L) -= P_J P_L^T, k-steps of four columns
 #pragma unroll
-      for (int ii = 0; ii < RB; ++ii) {
-        if ((mask >> ii) & 1) {
-          double sj[RB], sl[RB];
+    for (int k = 0; k < REJECT_T_TPW; ++k) {
+      if (tL[k] > I) {
 #pragma unroll
-          for (int t = 0; t < RB; ++t) {
-            sj[t] = PL[buf][ii][RB * bj + t];
-            sl[t] = PL[buf][ii][RB * bl + t];
+        for (int ks = 0; ks < 4; ++ks) {
+          if ((mask >> (4 * ks)) & 15) {
+            const double av = -Qb[RT * tJ[k] + l16][4 * ks + g];
+            const double bv = Qb[RT * tL[k] + l16][4 * ks + g];
+            tr[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, tr[k], 0, 0, 0);
           }
-#pragma unroll
-          for (int rr = 0; rr < RB; ++rr)
-#pragma unroll
-            for (int cc = 0; cc < RB; ++cc) v[rr][cc] = fma(-sj[rr], sl[cc], v[rr][cc]);
         }
       }
     }
     nacc += __popc(mask);
   }
   __syncthreads();
-  // L = L(T,T), dense column-major: L(a, c) = scaled column c at row accl[a]
-  for (int q = tid; q < nacc * nacc; q += nthr) {
-    const int a = q % nacc, c = q / nacc;
-    Lout[(int64_t)c * b + a] = (a >= c) ? H[(int64_t)c * b + accl[a]] : 0.0;
+  // L = L(T,T), dense column-major: L(a, c) = scaled column c at row accl[a];
+  // eight loads in flight per thread
+  const int nn = nacc * nacc;
+  for (int q0 = tid; q0 < nn; q0 += 8 * REJECT_T_THREADS) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int q = q0 + k * REJECT_T_THREADS;
+      const int a = q % nacc, c = q / nacc;
+      v[k] = (q < nn && a >= c) ? H[(int64_t)c * b + accl[a]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int q = q0 + k * REJECT_T_THREADS;
+      if (q < nn) Lout[(int64_t)(q / nacc) * b + q % nacc] = v[k];
+    }
   }
-  for (int a = tid; a < nacc; a += nthr) {
+  for (int a = tid; a < nacc; a += REJECT_T_THREADS) {
     const int64_t pv = props[accl[a]];
     acc_out[a] = accl[a];
     pivots[kr + a] = pv;
@@ -638,8 +686,8 @@ template void launch_gather<float>(hipStream_t, const float*, int64_t, const dou
 
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
                    double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
-  if (b <= REJECT_REG_BMAX)
-    hipLaunchKernelGGL(k_reject_reg, dim3(1), dim3(REJECT_REG_THREADS), 0, s, H, b, props, un, st, L, acc, pivots,
+  if (b <= REJECT_T_BMAX)
+    hipLaunchKernelGGL(k_reject_tiled, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, L, acc, pivots,
                        u, kmax);
   else
     hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, L, acc, pivots, u,
