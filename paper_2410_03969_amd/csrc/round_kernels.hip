@@ -313,39 +313,43 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
   if (tid == 0) st->s_r = nacc;
 }
 
-// Tiled form for b <= 256, one workgroup of eight wavefronts.  The trailing
-// submatrix is cut into 16 x 16 tiles held in FP64 matrix-core accumulators
-// (tile t = J (J + 1) / 2 + L of the lower triangle, J >= L, belongs to
-// wavefront t mod 8; entry i of lane (g, n) is row 16 J + g + 4 i, column
-// 16 L + n: the layout of the FP64 16x16x4 product's accumulator).
-// The proposals are taken 16 at a time (block column I):
-//  1. the owners of the tiles of block column I copy them to LDS;
-//  2. wavefront 0 runs the tests of Alg. 1 on the diagonal block, one row per
-//     lane: an accepted column is scaled by 1/sqrt(h) and its rank-one update
-//     applied to the rest of the block (the same operations, in the same
-//     order, as the one-column-at-a-time form);
-//  3. one thread per row below the block solves that row against the accepted
-//     columns (forward substitution, in acceptance order);
-//  4. the trailing tiles receive the rank-16 update on the matrix cores
-//     (rejected columns are zero), four 16x16x4 FP64 products per tile.
+// Tiled form for b <= 256, one workgroup of eight wavefronts.  Wavefront 0
+// runs the tests; the other seven hold the trailing submatrix as 16 x 16
+// tiles in FP64 matrix-core accumulators (tile t = J (J + 1) / 2 + L of the
+// lower triangle, J >= L, belongs to tile wavefront t mod 7; entry i of lane
+// (g, n) is row 16 J + g + 4 i, column 16 L + n: the layout of the FP64
+// 16x16x4 product's accumulator).  The proposals are taken 16 at a time
+// (block column I):
+//  1. the tile wavefronts finish the previous block's update on block column
+//     I and copy it to LDS;
+//  2. wavefront 0 runs the tests of Alg. 1 on the diagonal block while the
+//     tile wavefronts apply the previous block's update to the rest of the
+//     trailing tiles;
+//  3. the panel below the block is solved against the accepted columns as a
+//     product with the inverse of their factor (formed by wavefront 0 with
+//     the tests), four matrix-core products per tile;
+//  4. (at the next block) the trailing tiles receive the rank-16 update on
+//     the matrix cores, four products per tile (rejected columns are zero).
 // Three barriers per 16 proposals; the block-column buffer is double-buffered
-// so step 1 of the next block does not wait for step 4.  The scaled accepted
-// columns are kept in H (no longer read once in registers) and compacted into
-// L(T,T) at the end.
+// so a block's copy does not overwrite the previous panel while it is still
+// being applied.  The scaled accepted columns are kept in H (no longer read
+// once in registers) and compacted into L(T,T) at the end.
 constexpr int RT = 16;                  // tile edge
 constexpr int REJECT_T_THREADS = 512;
 constexpr int REJECT_T_BMAX = 256;
-constexpr int REJECT_T_TPW = 17;        // tiles per wavefront: 136 / 8, rounded up
+constexpr int REJECT_T_TW = 7;          // tile wavefronts
+constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
 
 typedef double rd4 __attribute__((ext_vector_type(4)));
 
-__device__ inline void tile_coords(int t, int& J, int& L) {
-  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (r * (r + 1) / 2 > t) --r;
-  while ((r + 1) * (r + 2) / 2 <= t) ++r;
-  J = r;
-  L = t - r * (r + 1) / 2;
+// (J, L) of lower-triangular tile index t, given those of t - step (L may
+// start past J: it is carried into the following rows).
+__device__ inline void tile_advance(int& J, int& L) {
+  while (L > J) {
+    L -= J + 1;
+    ++J;
+  }
 }
 
 __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __restrict__ H, int b,
@@ -355,45 +359,24 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
                                                                    int64_t* __restrict__ pivots,
                                                                    double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
-  __shared__ __attribute__((aligned(16))) double Q[2][REJECT_T_BMAX][QS];  // block column I
+  __shared__ __attribute__((aligned(16))) double Q[2][REJECT_T_BMAX][QS];  // block columns
   __shared__ double LD[RT][RT];            // LD[ii][r]: scaled accepted column ii at row r of the block
-  __shared__ double rsq[RT];               // 1/sqrt(h) of the accepted proposals
+  __shared__ double BC[RT][RT];            // BC[ii][r]: column ii of the block when its test runs;
+                                           // then X = L^{-1} of the block's accepted part, X(r, c) at BC[r][c]
+  __shared__ double rsq[RT];               // 1/sqrt(h) of the accepted proposals (0: rejected)
   __shared__ double uv[REJECT_T_BMAX];     // u_i V_i of the test
   __shared__ int64_t pr[REJECT_T_BMAX];
   __shared__ short prv[REJECT_T_BMAX], accl[REJECT_T_BMAX];
   __shared__ unsigned char tk[REJECT_T_BMAX];
   __shared__ int bmask;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // tile coordinates in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: tile coordinates stay scalar
   const int g = lane >> 4, l16 = lane & 15;
   const int64_t kr = st->k_r, round = st->round;
   const int cap = (int)((kmax - kr) < b ? (kmax - kr) : b);
   const int nbk = (b + RT - 1) / RT;
   const int ntile = nbk * (nbk + 1) / 2;
 
-  // this wavefront's tiles of H (the full symmetric matrix; zero padding);
-  // tJ = -1 marks no tile
-  rd4 tr[REJECT_T_TPW];
-  int tJ[REJECT_T_TPW], tL[REJECT_T_TPW];
-#pragma unroll
-  for (int k = 0; k < REJECT_T_TPW; ++k) {
-    const int t = w + 8 * k;
-    tr[k] = rd4{0.0, 0.0, 0.0, 0.0};
-    tJ[k] = -1;
-    tL[k] = -1;
-    if (t < ntile) {
-      int J, L;
-      tile_coords(t, J, L);
-      tJ[k] = J;
-      tL[k] = L;
-      const int col = RT * L + l16;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = RT * J + g + 4 * i;
-        if (row < b && col < b) tr[k][i] = H[(int64_t)col * b + row];
-      }
-    }
-  }
   if (tid < b) {
     uv[tid] = H[(int64_t)tid * b + tid] * stream_uniform(un, 2 * (int64_t)b * round + b + tid);
     pr[tid] = props[tid];
@@ -416,93 +399,221 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
   }
 
   int nacc = 0;
-  for (int I = 0; I < nbk && nacc < cap; ++I) {
-    double(*Qb)[QS] = Q[I & 1];
-    // 1. block column I into LDS (rows 16 I ..)
-#pragma unroll
-    for (int k = 0; k < REJECT_T_TPW; ++k)
-      if (tL[k] == I)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) Qb[RT * tJ[k] + g + 4 * i][l16] = tr[k][i];
-    __syncthreads();
-    // 2. the tests, on the diagonal block: lane r (mod 16) keeps row 16 I + r
-    if (w == 0) {
+  if (w == 0) {
+    // ---- the tests.  Lane r (mod 16) keeps row 16 I + r of the (symmetric)
+    // diagonal block.  The update after an accepted proposal ii is written as
+    // T(r, c) -= (T(r, ii) / h) T(c, ii), the same rank-one update as with the
+    // scaled column, so the chain from one test to the next holds a
+    // reciprocal but no square root; the scaled columns, 1/sqrt(h) and the
+    // outputs are formed for the whole block afterwards, one lane per column.
+    // Straight-line code: a rejected proposal has a zero multiplier.  Column
+    // ii is broadcast through LDS at the start of its step, off the chain.
+    // Lane ii also holds what the test of proposal 16 I + ii needs: u V, and
+    // whether an earlier proposal of the same point was taken (before this
+    // block: from tk; inside it: the scalar mask).
+    for (int I = 0; I < nbk && nacc < cap; ++I) {
+      double(*Qb)[QS] = Q[I & 1];
+      __syncthreads();   // (1) block column I is in LDS
       double dr[RT];
 #pragma unroll
       for (int c = 0; c < RT; ++c) dr[c] = Qb[RT * I + l16][c];
-      int mask = 0, cnt = 0;
+      const int iL = RT * I + l16;
+      double uvL = 0.0;
+      int pL = -1;
+      bool dupL = false;
+      if (iL < b) {
+        uvL = uv[iL];
+        const int p = prv[iL];
+        if (p >= RT * I) pL = p - RT * I;
+        else if (p >= 0) dupL = tk[p] != 0;
+      }
+      const unsigned dup_before = (unsigned)__ballot(dupL) & 0xffffu;
+      int mask = 0, taken = 0, cnt = 0;
+      double hL = 1.0;   // lane ii: h of proposal 16 I + ii
 #pragma unroll
       for (int ii = 0; ii < RT; ++ii) {
         const int i = RT * I + ii;
-        if (i >= b || nacc + cnt >= cap) continue;   // uniform
-        const double h = readlane_f64(dr[ii], ii);
-        const int p = prv[i];
-        const bool dup = p >= 0 && tk[p];
-        const bool a = !dup && (uv[i] < h);
-        if (lane == 0) tk[i] = (a || dup) ? 1 : 0;
-        if (a) {
-          const double rs = 1.0 / sqrt(h);
-          const double col = (l16 >= ii) ? dr[ii] * rs : 0.0;
+        // column ii is final: T(ii + 1, ii), needed by the next test, by
+        // readlane; the rest through LDS (lanes r and r + 16 k write the same
+        // value), needed no earlier than the test after next
+        BC[ii][l16] = dr[ii];
+        const double bn = readlane_f64(dr[ii], ii + 1 < RT ? ii + 1 : ii);
+        double bc[RT];
 #pragma unroll
-          for (int cc = ii + 1; cc < RT; ++cc) dr[cc] = fma(-col, readlane_f64(col, cc), dr[cc]);
-          if (lane < RT) {
-            LD[ii][lane] = col;
-            if (lane >= ii && RT * I + lane < b) H[(int64_t)(nacc + cnt) * b + RT * I + lane] = col;
-          }
-          if (lane == 0) {
-            rsq[ii] = rs;
-            accl[nacc + cnt] = (short)i;
-          }
-          mask |= 1 << ii;
-          ++cnt;
+        for (int c = ii + 2; c < RT; ++c) bc[c] = BC[ii][c];
+        // the test, evaluated on lane ii (which holds h = its diagonal entry)
+        const int dupl = (int)((dup_before >> l16) & 1u) | ((pL >= 0) & (int)((taken >> (pL & 15)) & 1));
+        const int al = (dupl ^ 1) & (uvL < dr[ii] ? 1 : 0);
+        const int bits = __builtin_amdgcn_readlane(al | (dupl << 1), ii);
+        const bool dup = (bits & 2) != 0;
+        const bool a = (bits & 1) && i < b && nacc + cnt < cap;
+        const double h = readlane_f64(dr[ii], ii);
+        taken |= (a || dup) ? (1 << ii) : 0;
+        // 1/h: hardware reciprocal and two Newton steps (exact for h = 1)
+        const double ha = a ? h : 1.0;
+        double inv = __builtin_amdgcn_rcp(ha);
+        inv = fma(inv, fma(-ha, inv, 1.0), inv);
+        inv = fma(inv, fma(-ha, inv, 1.0), inv);
+        const double t = a ? dr[ii] * inv : 0.0;
+        if (ii + 1 < RT) dr[ii + 1] = fma(-t, bn, dr[ii + 1]);
+#pragma unroll
+        for (int c = ii + 2; c < RT; ++c) dr[c] = fma(-t, bc[c], dr[c]);
+        hL = (l16 == ii) ? h : hL;
+        mask |= a ? (1 << ii) : 0;
+        cnt += a ? 1 : 0;
+      }
+      // the block's outputs: lane c forms 1/sqrt(h_c); row r keeps the
+      // unscaled entries T(r, ii) of the steps, which scale into column ii
+      const double rsL = ((mask >> l16) & 1) ? 1.0 / sqrt(hL) : 0.0;
+      if (lane < RT) {
+        rsq[lane] = rsL;
+        if (iL < b) tk[iL] = (taken >> lane) & 1;
+        if ((mask >> lane) & 1) accl[nacc + __popc(mask & ((1 << lane) - 1))] = (short)iL;
+      }
+      int rank = 0;
+#pragma unroll
+      for (int ii = 0; ii < RT; ++ii) {
+        const double col = (l16 >= ii) ? dr[ii] * rsq[ii] : 0.0;
+        if (lane < RT) LD[ii][lane] = col;
+        if ((mask >> ii) & 1) {
+          if (lane < RT && lane >= ii && iL < b) H[(int64_t)(nacc + rank) * b + iL] = col;
+          ++rank;
         }
+      }
+      // X = L^{-1} restricted to the accepted proposals (rejected rows and
+      // columns come out zero): lane c forms column c by forward
+      // substitution, into XS(r, c) (the broadcast area, free again)
+      {
+        double y[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) y[r] = (r == l16) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+          const double xk = y[k] * rsq[k];
+          y[k] = xk;
+#pragma unroll
+          for (int r = k + 1; r < RT; ++r) y[r] = fma(-LD[k][r], xk, y[r]);
+        }
+        if (lane < RT)
+#pragma unroll
+          for (int r = 0; r < RT; ++r) BC[r][lane] = y[r];
       }
       if (lane == 0) bmask = mask;
+      __syncthreads();   // (2) decisions, LD, rsq and X are in LDS
+      if (mask == 0) continue;
+      __syncthreads();   // (3) the panel is solved
+      nacc += __popc(mask);
     }
-    __syncthreads();
-    const int mask = bmask;
-    if (mask == 0) continue;
-    // 3. the rows below the block against the accepted columns
+  } else {
+    const int wt = w - 1;
+    rd4 tr[REJECT_T_TPW];
+    // coordinates of this wavefront's tiles, four bits each of J and L, four
+    // tiles per word (scalar registers)
+    unsigned pk[(REJECT_T_TPW + 3) / 4];
     {
-      const int j = RT * (I + 1) + tid;
-      if (j < b) {
-        double q[RT];
 #pragma unroll
-        for (int c = 0; c < RT; ++c) q[c] = Qb[j][c];
-        int rank = 0;
+      for (int q = 0; q < (REJECT_T_TPW + 3) / 4; ++q) pk[q] = 0;
+      int J = 0, L = wt;
 #pragma unroll
-        for (int ii = 0; ii < RT; ++ii) {
-          if ((mask >> ii) & 1) {
-            const double pl = q[ii] * rsq[ii];
-            q[ii] = pl;
-#pragma unroll
-            for (int cc = ii + 1; cc < RT; ++cc) q[cc] = fma(-pl, LD[ii][cc], q[cc]);
-            H[(int64_t)(nacc + rank) * b + j] = pl;
-            ++rank;
-          } else {
-            q[ii] = 0.0;
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < RT; ++c) Qb[j][c] = q[c];
+      for (int k = 0; k < REJECT_T_TPW; ++k) {
+        tile_advance(J, L);
+        pk[k / 4] |= (unsigned)((J & 15) | ((L & 15) << 4)) << (8 * (k % 4));
+        L += REJECT_T_TW;
       }
     }
-    __syncthreads();
-    // 4. trailing tiles: T(J, L) -= P_J P_L^T, k-steps of four columns
+    // f(k, J, L) for each tile k of this wavefront
+    auto for_tiles = [&](auto f) __attribute__((always_inline)) {
 #pragma unroll
-    for (int k = 0; k < REJECT_T_TPW; ++k) {
-      if (tL[k] > I) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          if ((mask >> (4 * ks)) & 15) {
-            const double av = -Qb[RT * tJ[k] + l16][4 * ks + g];
-            const double bv = Qb[RT * tL[k] + l16][4 * ks + g];
-            tr[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, tr[k], 0, 0, 0);
-          }
+      for (int k = 0; k < REJECT_T_TPW; ++k) {
+        if (wt + REJECT_T_TW * k < ntile) {
+          const unsigned e = pk[k / 4] >> (8 * (k % 4));
+          f(k, (int)(e & 15), (int)((e >> 4) & 15));
         }
       }
+    };
+    // this wavefront's tiles of H (zero padding), read along rows of the
+    // symmetric H so that a load instruction covers four 128-byte runs; the
+    // loads are unconditional (clamped indices) so that all stay in flight
+#pragma unroll
+    for (int k = 0; k < REJECT_T_TPW; ++k) tr[k] = rd4{0.0, 0.0, 0.0, 0.0};
+    for_tiles([&](int k, int J, int L) {
+      const int col = RT * L + l16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = RT * J + g + 4 * i;
+        tr[k][i] = H[(int64_t)(row < b ? row : b - 1) * b + (col < b ? col : b - 1)];
+      }
+    });
+    for_tiles([&](int k, int J, int L) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (RT * J + g + 4 * i >= b || RT * L + l16 >= b) tr[k][i] = 0.0;
+    });
+    // T(J, L) -= P_J P_L^T for the tiles selected by pick, four k-steps of
+    // four columns (rejected columns of P are zero), P the previous block's
+    // solved panel; a tile's eight operands are read before its products
+    auto update = [&](double(*P)[QS], auto pick) __attribute__((always_inline)) {
+      for_tiles([&](int k, int J, int L) {
+        if (pick(L)) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            av[ks] = P[RT * J + l16][4 * ks + g];
+            bv[ks] = P[RT * L + l16][4 * ks + g];
+          }
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) tr[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ks], bv[ks], tr[k], 0, 0, 0);
+        }
+      });
+    };
+    int pmask = 0;   // accepted columns of the previous block (update pending)
+    for (int I = 0; I < nbk && nacc < cap; ++I) {
+      double(*Qb)[QS] = Q[I & 1];
+      double(*Qp)[QS] = Q[(I + 1) & 1];
+      // 1. the pending update on block column I, then its copy to LDS
+      if (pmask) update(Qp, [&](int l) { return l == I; });
+      for_tiles([&](int k, int J, int L) {
+        if (L == I)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = tr[k][i];
+      });
+      __syncthreads();   // (1)
+      // 2. the rest of the pending update, beside the tests
+      if (pmask) update(Qp, [&](int l) { return l > I; });
+      __syncthreads();   // (2)
+      const int mask = bmask;
+      pmask = mask;
+      if (mask == 0) continue;
+      // 3. the panel below the block: P_J = Q_J X^T for this wavefront's
+      // tiles (J, I), J > I, four 16x16x4 products each (rejected columns of
+      // X^T are zero), into the panel rows of the buffer (for the update)
+      // and the accepted columns into H
+      for_tiles([&](int k, int J, int L) {
+        if (L == I && J > I) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            av[ks] = Qb[RT * J + l16][4 * ks + g];
+            bv[ks] = BC[l16][4 * ks + g];
+          }
+          rd4 pj = rd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) pj = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], pj, 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = pj[i];
+          if ((mask >> l16) & 1) {
+            const int64_t c = nacc + __popc(mask & ((1 << l16) - 1));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = RT * J + g + 4 * i;
+              if (row < b) H[c * b + row] = pj[i];
+            }
+          }
+        }
+      });
+      __syncthreads();   // (3)
+      nacc += __popc(mask);
     }
-    nacc += __popc(mask);
   }
   __syncthreads();
   // L = L(T,T), dense column-major: L(a, c) = scaled column c at row accl[a];
