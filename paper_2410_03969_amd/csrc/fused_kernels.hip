@@ -162,11 +162,15 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   }
 
   // ---- small-operand ring: stream position q < nk is chunk q of Bm1, then
-  // (streaming form) the NT chunks of the inverse factor
+  // (streaming form) the NT chunks of the inverse factor.  Chunks are loaded
+  // into registers D positions ahead of their commit to the two-stage LDS
+  // ring, so the load latency (an L2 round trip per chunk) overlaps D
+  // iterations of the contraction.
+  constexpr int D = RES ? FD : 1;
   const int64_t nkl = nk > 0 ? nk - 1 : 0;       // last valid chunk index
-  u4 sbuf[PER_T];
+  u4 sbq[D][PER_T];
   int tid = tid0;
-  auto fetch = [&](int64_t q) {
+  auto fetch_to = [&](u4 (&sbuf)[PER_T], int64_t q) {
     const unsigned char* src;
     if constexpr (RES) src = a.Bm1 + (size_t)(q < nkl ? q : nkl) * SPL * CP * FGROW;
     else src = (q < nk) ? a.Bm1 + (size_t)q * SPL * CP * FGROW
@@ -180,7 +184,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       sbuf[r] = *(const u4*)(src + (size_t)(o < PIECES ? o : PIECES - 1) * 16);
     }
   };
-  auto commit = [&](int buf) {
+  auto commit_from = [&](const u4 (&sbuf)[PER_T], int buf) {
 #pragma unroll
     for (int r = 0; r < PER_T; ++r) {
       const int o = tid + r * 64 * FW;
@@ -238,17 +242,20 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // are never consumed); only the products are guarded.  The
     // load counter is in-order, so the fetch goes first: the wait before its
     // commit leaves the F loads in flight.
-    fetch(0);
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch_to(sbq[u], u);
 #pragma unroll
     for (int u = 0; u < FD - 1; ++u) loadF(fr[u], u < nkl ? u : nkl);
-    commit(0);
+    commit_from(sbq[0], 0);
     __syncthreads();
 
     for (int64_t ch0 = 0; ch0 < nk; ch0 += FD) {
 #pragma unroll
       for (int u = 0; u < FD; ++u) {
         const int64_t ch = ch0 + u;
-        fetch(ch + 1 < nk ? ch + 1 : nk);
+        // slot u % D held chunk ch, committed at the end of the previous
+        // iteration; it now receives chunk ch + D
+        fetch_to(sbq[u % D], (D == 1 && ch + 1 > nk) ? nk : ch + D);
         loadF(fr[(u + FD - 1) % FD], ch + FD - 1 < nkl ? ch + FD - 1 : nkl);
         if (ch < nk) {
           const unsigned char* L = lds + (ch & 1) * STAGE + l16 * FCROW + g * 16;
@@ -279,7 +286,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         // unguarded: past the last chunk the fetch repeats the first chunk of
         // the inverse factor (already committed), and no product reads the
         // buffer written here
-        commit((ch + 1) & 1);
+        commit_from(sbq[(u + 1) % D], (ch + 1) & 1);
         __syncthreads();
       }
     }
@@ -409,7 +416,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       for (int tc = 0; tc < NT; ++tc) {
         const int64_t q = nk + pass * NT + tc;
         const bool more = !RES && (tc + 1 < NT || pass + 1 < NPASS);
-        if (more) fetch(q + 1);
+        if (more) fetch_to(sbq[0], q + 1);
         const unsigned char* L = lds + (q & 1) * STAGE;
 #pragma unroll
         for (int mt = 0; mt < NCBT; ++mt) {
@@ -433,7 +440,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
           }
         }
         if constexpr (!RES) {
-          if (more) commit((q + 1) & 1);
+          if (more) commit_from(sbq[0], (q + 1) & 1);
           __syncthreads();
         }
       }
