@@ -195,6 +195,56 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     }
   };
 
+  // Operands a tile starts with: its rows' coordinates and the first D chunks
+  // of Bm1 (early part), the first FD - 1 chunks of F (late part).  Where the
+  // registers allow (PRE), the early part for the next tile is loaded before
+  // the stores of the current one, so those loads go out ahead of the stores
+  // instead of queueing behind them.
+  constexpr bool PRE = NCBT <= 13;
+  constexpr int XR = EXPAND ? DX / 4 : DX;
+  float xr[FNB][XR];
+  bf8 fr[FD][FNB][SPL];
+  // F slices: rows row_w + l16 and row_w + 16 + l16 share a 256-row panel
+  auto fbase = [&](int64_t row_w_, int l16_, int g_) {
+    const int64_t r0 = row_w_ + l16_;
+    return a.Fb + (size_t)(r0 / PH) * a.nkc * CHUNK_E + (size_t)(r0 % PH) * FKC + 8 * g_;
+  };
+  auto loadF = [&](bf8 (&f)[FNB][SPL], const __bf16* rb, int64_t ch) {
+#pragma unroll
+    for (int nb = 0; nb < FNB; ++nb)
+#pragma unroll
+      for (int pl = 0; pl < SPL; ++pl)
+        f[nb][pl] = *(const bf8*)(rb + (size_t)ch * CHUNK_E + pl * PLANE_E + nb * 16 * FKC);
+  };
+  auto prologue_early = [&](int tile_) {
+    const int lane_ = tid & 63, l16_ = lane_ & 15, g_ = lane_ >> 4;
+    const int64_t row_w_ = (int64_t)tile_ * FROWS + w * (FNB * 16);
+    // this lane's rows (tiles nb = 0, 1): row_w + 16 nb + l16.  Expanded
+    // form: coordinates 4 ks + g only, the B operand of the distance product
+    // (lane (g, n) holds B(k = g, n)); direct form: all coordinates, scaled.
+#pragma unroll
+    for (int nb = 0; nb < FNB; ++nb) {
+      int64_t r = row_w_ + nb * 16 + l16_;
+      if (r >= N) r = N - 1;
+#pragma unroll
+      for (int t = 0; t < XR; ++t) {
+        const int tt = EXPAND ? 4 * t + g_ : t;
+        xr[nb][t] = (tt < d) ? (EXPAND ? 1.f : sxp) * (float)a.X[r * d + tt] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch_to(sbq[u], u);
+  };
+  auto prologue_late = [&](const __bf16* rb_) {
+#pragma unroll
+    for (int u = 0; u < FD - 1; ++u) loadF(fr[u], rb_, u < nkl ? u : nkl);
+  };
+  if (PRE && blockIdx.x < a.ntiles) {
+    tid = tid0;
+    asm volatile("" : "+v"(tid));
+    prologue_early(blockIdx.x);
+  }
+
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     // Lane-dependent values are re-derived in every tile: hoisted out of the
     // loop they would stay live across it and spill.
@@ -202,50 +252,21 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, l16 = lane & 15, g = lane >> 4;
     const int64_t row_w = (int64_t)tile * FROWS + w * (FNB * 16);
-    // this lane's rows (tiles nb = 0, 1): row_w + 16 nb + l16.  Expanded
-    // form: coordinates 4 ks + g only, the B operand of the distance product
-    // (lane (g, n) holds B(k = g, n)); direct form: all coordinates, scaled.
-    constexpr int XR = EXPAND ? DX / 4 : DX;
-    float xr[FNB][XR];
-#pragma unroll
-    for (int nb = 0; nb < FNB; ++nb) {
-      int64_t r = row_w + nb * 16 + l16;
-      if (r >= N) r = N - 1;
-#pragma unroll
-      for (int t = 0; t < XR; ++t) {
-        const int tt = EXPAND ? 4 * t + g : t;
-        xr[nb][t] = (tt < d) ? (EXPAND ? 1.f : sxp) * (float)a.X[r * d + tt] : 0.f;
-      }
-    }
 
     f4 acc[FNB][NCBT];
 #pragma unroll
     for (int nb = 0; nb < FNB; ++nb)
 #pragma unroll
       for (int cb = 0; cb < NCBT; ++cb) acc[nb][cb] = f4{0.f, 0.f, 0.f, 0.f};
-
-    // F slices: rows row_w + l16 and row_w + 16 + l16 share a 256-row panel
-    const int64_t r0 = row_w + l16;
-    const __bf16* rb = a.Fb + (size_t)(r0 / PH) * a.nkc * CHUNK_E + (size_t)(r0 % PH) * FKC + 8 * g;
-    bf8 fr[FD][FNB][SPL];
-    auto loadF = [&](bf8 (&f)[FNB][SPL], int64_t ch) {
-#pragma unroll
-      for (int nb = 0; nb < FNB; ++nb)
-#pragma unroll
-        for (int pl = 0; pl < SPL; ++pl)
-          f[nb][pl] = *(const bf8*)(rb + (size_t)ch * CHUNK_E + pl * PLANE_E + nb * 16 * FKC);
-    };
-
+    const __bf16* rb = fbase(row_w, l16, g);
+    if (!PRE) prologue_early(tile);
+    prologue_late(rb);
     // ---- 1. update GEMM.  The loop body is straight-line in its loads: each
     // iteration fetches the next small-operand chunk and loads the F chunk
     // FD - 1 ahead (clamped to the last chunk near the end; the surplus loads
     // are never consumed); only the products are guarded.  The
     // load counter is in-order, so the fetch goes first: the wait before its
     // commit leaves the F loads in flight.
-#pragma unroll
-    for (int u = 0; u < D; ++u) fetch_to(sbq[u], u);
-#pragma unroll
-    for (int u = 0; u < FD - 1; ++u) loadF(fr[u], u < nkl ? u : nkl);
     commit_from(sbq[0], 0);
     __syncthreads();
 
@@ -256,22 +277,28 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         // slot u % D held chunk ch, committed at the end of the previous
         // iteration; it now receives chunk ch + D
         fetch_to(sbq[u % D], (D == 1 && ch + 1 > nk) ? nk : ch + D);
-        loadF(fr[(u + FD - 1) % FD], ch + FD - 1 < nkl ? ch + FD - 1 : nkl);
+        loadF(fr[(u + FD - 1) % FD], rb, ch + FD - 1 < nkl ? ch + FD - 1 : nkl);
         if (ch < nk) {
           const unsigned char* L = lds + (ch & 1) * STAGE + l16 * FCROW + g * 16;
-          // operand reads one column block ahead of the products (all of them
-          // hoisted at once would hold NCBT operand slices in registers)
-          bf8 ahn = *(const bf8*)L, aln;
-          if constexpr (PASSES == 3) aln = *(const bf8*)(L + CP * FCROW);
+          // operand reads PD - 1 column blocks ahead of the products: enough
+          // LDS reads in flight to cover their latency, without holding all
+          // NCBT operand slices in registers
+          constexpr int PD = (PASSES == 3 || NCBT > 13) ? 2 : 4;
+          bf8 ap[PD], alp[PD];
+#pragma unroll
+          for (int j = 0; j < PD - 1 && j < NCBT; ++j) {
+            ap[j] = *(const bf8*)(L + j * 16 * FCROW);
+            if constexpr (PASSES == 3) alp[j] = *(const bf8*)(L + CP * FCROW + j * 16 * FCROW);
+          }
 #pragma unroll
           for (int cb = 0; cb < NCBT; ++cb) {
-            const bf8 ah = ahn;
-            bf8 al;
-            if constexpr (PASSES == 3) al = aln;
-            if (cb + 1 < NCBT) {
-              ahn = *(const bf8*)(L + (cb + 1) * 16 * FCROW);
-              if constexpr (PASSES == 3) aln = *(const bf8*)(L + CP * FCROW + (cb + 1) * 16 * FCROW);
+            if (cb + PD - 1 < NCBT) {
+              ap[(cb + PD - 1) % PD] = *(const bf8*)(L + (cb + PD - 1) * 16 * FCROW);
+              if constexpr (PASSES == 3) alp[(cb + PD - 1) % PD] = *(const bf8*)(L + CP * FCROW + (cb + PD - 1) * 16 * FCROW);
             }
+            const bf8 ah = ap[cb % PD];
+            bf8 al;
+            if constexpr (PASSES == 3) al = alp[cb % PD];
 #pragma unroll
             for (int nb = 0; nb < FNB; ++nb) {
               acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr[u][nb][0], acc[nb][cb], 0, 0, 0);
@@ -464,6 +491,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       const int64_t row = row_w + nb * 16 + l16;
       if (row < N && g == 0) a.P[row] = (double)g2;
     }
+    if (PRE && tile + (int)gridDim.x < a.ntiles) prologue_early(tile + gridDim.x);
     // Blocked BF16 copy, 8-byte stores straight from the accumulators.  Its
     // columns kr - m .. are cut into groups of four (m = kr mod 4, so a group
     // never crosses a 32-column chunk): lane (g, l16) of group mt writes
@@ -489,7 +517,6 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         for (int pl = 0; pl < SPL; ++pl) tprev[pl] = 0;
 #pragma unroll
         for (int mt = 0; mt < NCBT + 3; ++mt) {
-          if (kr - m + 16 * mt >= zend) break;          // uniform
           const int64_t a0 = kr - m + 16 * mt + 4 * g;
           __bf16* p = prow + (a0 / FKC) * (int64_t)CHUNK_E + a0 % FKC;
           const bool ok = row < N && a0 < zend;
