@@ -86,6 +86,7 @@ Layout layout_of(const arpc_problem& p) {
   l.acc = take(sizeof(int32_t) * p.b);
   l.hist = take(sizeof(int32_t) * (p.k + 1));
   l.Fs = take(sizeof(double) * p.b * p.k);
+  l.Hp = take(sizeof(double) * gather_splits(p.k) * p.b * p.b);
   l.H = take(sizeof(double) * p.b * p.b);
   l.L = take(sizeof(double) * p.b * p.b);
   l.Xp = take(sizeof(double) * p.b * p.d);
@@ -152,7 +153,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
                (int)((b + 15) / 16 * 16), P, Fs, k, acc, L, b, k};
   prof.begin(ARPC_KC_GATHER);
-  launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, H, st);
+  launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, (double*)(ws + l.Hp), H, st);
   prof.end();
   prof.begin(ARPC_KC_REJECT);
   launch_reject(s, H, b, props, un, st, L, acc, pivots, u, k);

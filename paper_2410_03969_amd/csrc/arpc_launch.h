@@ -9,12 +9,14 @@ void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_
                  RoundState* st, int64_t nchunks);
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
                     int64_t N, int b, Unif un, RoundState* st, int64_t* props);
+// Partitions of the contraction index in the product F(S',:) F(S',:)^T of
+// H (its partial products are summed in partition order); Hp holds
+// gather_splits(kmax) * b * b doubles.
+int gather_splits(int64_t kmax);
 template <typename T>
 void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
-                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* H,
+                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* Hp, double* H,
                    const RoundState* st);
-void launch_gather_H(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b,
-                     const double* Fs, int64_t ldf, double* H, const RoundState* st);
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
                    double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax);
 template <typename T>

@@ -208,11 +208,13 @@ __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ F, in
 }
 
 // H = A(S',S') - F(S',:) F(S',:)^T (Alg. 2 step 2), FP64, column-major b x b
-// (ld = b).  One 16 x 16 tile per workgroup; F rows staged through LDS.
-__global__ __launch_bounds__(256) void k_gather_H(const double* __restrict__ X, int d, KParams kp,
-                                                  const int64_t* __restrict__ props, int b,
-                                                  const double* __restrict__ Fs, int64_t ldf,
-                                                  double* __restrict__ H, const RoundState* st) {
+// (ld = b), in two launches.  First the product, split along the contraction
+// index into partitions of W columns: workgroup (x, y, p) forms the 16 x 16
+// tile (x, y) of partition p's partial product (F rows staged through LDS)
+// into Hp(p).  The split keeps enough workgroups busy at any k_r; each tile
+// is summed in one fixed order, so H is symmetric and reproducible.
+__global__ __launch_bounds__(256) void k_gather_Hp(int b, const double* __restrict__ Fs, int64_t ldf, int64_t W,
+                                                   double* __restrict__ Hp, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
   const int64_t kr = st->k_r;
   __shared__ double As[16][65];
@@ -220,24 +222,39 @@ __global__ __launch_bounds__(256) void k_gather_H(const double* __restrict__ X, 
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
   const int i = i0 + ty, j = j0 + tx;
+  const int64_t cbeg = (int64_t)blockIdx.z * W;
+  const int64_t cend = (cbeg + W < kr) ? cbeg + W : kr;
   double acc = 0.0;
-  for (int64_t c0 = 0; c0 < kr; c0 += 64) {
+  for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
     for (int q = threadIdx.x; q < 16 * 64; q += 256) {
       const int r = q >> 6, cc = q & 63;
       const int64_t c = c0 + cc;
-      As[r][cc] = (i0 + r < b && c < kr) ? Fs[(int64_t)(i0 + r) * ldf + c] : 0.0;
-      Bs[r][cc] = (j0 + r < b && c < kr) ? Fs[(int64_t)(j0 + r) * ldf + c] : 0.0;
+      As[r][cc] = (i0 + r < b && c < cend) ? Fs[(int64_t)(i0 + r) * ldf + c] : 0.0;
+      Bs[r][cc] = (j0 + r < b && c < cend) ? Fs[(int64_t)(j0 + r) * ldf + c] : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
     for (int cc = 0; cc < 64; ++cc) acc += As[ty][cc] * Bs[tx][cc];
     __syncthreads();
   }
-  if (i < b && j < b) {
-    const double* xi = X + props[i] * d;
-    const double* xj = X + props[j] * d;
-    H[(int64_t)j * b + i] = kappa_r2(sqdist(xi, xj, d), kp) - acc;
-  }
+  if (i < b && j < b) Hp[(int64_t)blockIdx.z * b * b + (int64_t)j * b + i] = acc;
+}
+
+// Second launch: H(i, j) = kappa(x_i, x_j) - sum over the partitions, in
+// partition order.
+__global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X, int d, KParams kp,
+                                                   const int64_t* __restrict__ props, int b, int parts,
+                                                   const double* __restrict__ Hp, double* __restrict__ H,
+                                                   const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (int64_t)b * b) return;
+  const int i = (int)(q % b), j = (int)(q / b);
+  double acc = 0.0;
+  for (int p = 0; p < parts; ++p) acc += Hp[(int64_t)p * b * b + q];
+  const double* xi = X + props[i] * d;
+  const double* xj = X + props[j] * d;
+  H[q] = kappa_r2(sqdist(xi, xj, d), kp) - acc;
 }
 
 // ------------------------------------------------- RejectionSampleSubmatrix
@@ -773,26 +790,30 @@ void launch_propose(hipStream_t s, const double* u, const double* csum, double* 
                      s, u, cpre, nchunks, N, b, un, st, props);
 }
 
+int gather_splits(int64_t kmax) {
+  const int64_t p = (kmax + 255) / 256;
+  return (int)(p < 1 ? 1 : (p > 8 ? 8 : p));
+}
+
 template <typename T>
 void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
-                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* H,
+                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* Hp, double* H,
                    const RoundState* st) {
   if (kmax > 0)
     hipLaunchKernelGGL(k_gather_rows<T>, dim3((unsigned)((kmax + 255) / 256), b), dim3(256), 0, s, F, N,
                        props, Fs, ldf, st);
-  launch_gather_H(s, X, d, kp, props, b, Fs, ldf, H, st);
-}
-
-void launch_gather_H(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b,
-                     const double* Fs, int64_t ldf, double* H, const RoundState* st) {
+  const int parts = gather_splits(kmax);
+  const int64_t W = ((kmax + parts - 1) / parts + 63) / 64 * 64;   // columns per partition
   const unsigned nb = (unsigned)((b + 15) / 16);
-  hipLaunchKernelGGL(k_gather_H, dim3(nb, nb), dim3(256), 0, s, X, d, kp, props, b, Fs, ldf, H, st);
+  hipLaunchKernelGGL(k_gather_Hp, dim3(nb, nb, parts), dim3(256), 0, s, b, Fs, ldf, W, Hp, st);
+  hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp, props,
+                     b, parts, Hp, H, st);
 }
 template void launch_gather<double>(hipStream_t, const double*, int64_t, const double*, int, KParams,
-                                    const int64_t*, int, double*, int64_t, int64_t, double*,
+                                    const int64_t*, int, double*, int64_t, int64_t, double*, double*,
                                     const RoundState*);
 template void launch_gather<float>(hipStream_t, const float*, int64_t, const double*, int, KParams,
-                                   const int64_t*, int, double*, int64_t, int64_t, double*,
+                                   const int64_t*, int, double*, int64_t, int64_t, double*, double*,
                                    const RoundState*);
 
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
