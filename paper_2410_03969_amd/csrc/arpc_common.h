@@ -154,39 +154,58 @@ __device__ inline double readlane_f64(double v, int l) {
 // b), s <= 256, in one wavefront by column-oriented forward substitution: lane
 // l keeps rows l, l + 64, l + 128, l + 192 of the right-hand side e_c, which
 // becomes column c of L^{-1}.  Column t of L is read coalesced and does not
-// depend on the solution, so it is loaded a step ahead; the dependency chain
-// is one readlane and a few FMAs per step.  Rows outside [c, s) are zero.
+// depend on the solution, so it is loaded P steps ahead (an L2 round trip
+// per step otherwise); the dependency chain is one readlane and a few FMAs
+// per step.  Rows outside [c, s) are zero.
 __device__ inline void linv_column(const double* __restrict__ L, int b, int s, int c, int lane, double (&r)[4]) {
+  constexpr int P = 8;   // columns of L in flight ahead of the chain (divides 64)
   double invd[4];
+  int ic[4];             // row index clamped into L (rows outside (t, s) are masked at use)
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int i = lane + 64 * m;
     r[m] = (i == c && c < s) ? 1.0 : 0.0;
     invd[m] = (i < s) ? 1.0 / L[(int64_t)i * b + i] : 0.0;
+    ic[m] = i < b ? i : b - 1;
   }
   if (c >= s) return;
-  double cur[4], nxt[4];
+  // Steps t run from c rounded down to a multiple of P (earlier ones are
+  // skipped); column t of L sits in buf[t % P], loaded P steps ahead with an
+  // unconditional load (column index clamped to s - 1).  The rows of step t
+  // live in register group t / 64 of lane t % 64; the four groups are walked
+  // in turn, so that group is a compile-time choice and only groups at or
+  // past it are updated.
+  const int t0 = c & ~(P - 1);
+  double buf[P][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int i = lane + 64 * m;
-    cur[m] = (i > c && i < s) ? L[(int64_t)c * b + i] : 0.0;
+  for (int u = 0; u < P; ++u) {
+    const int tc = t0 + u < s ? t0 + u : s - 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) buf[u][m] = L[(int64_t)tc * b + ic[m]];
   }
-  for (int t = c; t < s; ++t) {
-    // column t + 1 of L, ahead of the chain
+  int t = t0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int i = lane + 64 * m;
-      nxt[m] = (t + 1 < s && i > t + 1 && i < s) ? L[(int64_t)(t + 1) * b + i] : 0.0;
-    }
-    const int mt = t >> 6, lt = t & 63;
-    const double own = mt == 0 ? r[0] : mt == 1 ? r[1] : mt == 2 ? r[2] : r[3];
-    const double ownd = mt == 0 ? invd[0] : mt == 1 ? invd[1] : mt == 2 ? invd[2] : invd[3];
-    const double xt = readlane_f64(own, lt) * readlane_f64(ownd, lt);
+  for (int mt = 0; mt < 4; ++mt) {
+    const int te = s < 64 * (mt + 1) ? s : 64 * (mt + 1);
+    for (; t < te; t += P) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      if (m == mt && lane == lt) r[m] = xt;
-      r[m] = fma(-cur[m], xt, r[m]);     // cur is zero outside rows t+1 .. s-1
-      cur[m] = nxt[m];
+      for (int u = 0; u < P; ++u) {
+        const int tt = t + u;
+        if (tt >= c && tt < te) {
+          const int lt = tt & 63;
+          const double xt = readlane_f64(r[mt], lt) * readlane_f64(invd[mt], lt);
+          r[mt] = (lane == lt) ? xt : r[mt];
+#pragma unroll
+          for (int m = mt; m < 4; ++m) {
+            const int i = lane + 64 * m;
+            const double lv = (i > tt && i < s) ? buf[u][m] : 0.0;   // rows tt+1 .. s-1 of column tt
+            r[m] = fma(-lv, xt, r[m]);
+          }
+        }
+        const int tn = tt + P < s ? tt + P : s - 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) buf[u][m] = L[(int64_t)tn * b + ic[m]];
+      }
     }
   }
 }
