@@ -143,8 +143,13 @@ arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, v
 arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out);
 
 /* Per-kernel timing with HIP events, recorded into arpc_stats.ms_kernel
- * (process-wide switch; off by default). */
+ * (process-wide switch; off by default).  on != 0 times every kernel class. */
 void arpc_set_profiling(int on);
+
+/* The same switch restricted to the kernel classes whose bit (1 << ARPC_KC_*)
+ * is set in mask (0: off).  Timing one class keeps the events of the others
+ * off the stream. */
+void arpc_set_profiling_classes(unsigned mask);
 
 /* ------------------------------------------------------------------ serving
  * A context serves a stream of factorization jobs (each one arpc_factor's

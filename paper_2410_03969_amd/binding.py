@@ -21,6 +21,7 @@ NUM_KC = len(KERNEL_CLASSES)
 
 EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_factor",
            "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling",
+           "arpc_set_profiling_classes",
            "arpc_create", "arpc_destroy", "arpc_submit", "arpc_poll", "arpc_wait", "arpc_cancel",
            "arpc_serving_info"]
 
@@ -83,6 +84,8 @@ def lib():
         L.arpc_stream_uniforms_host.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_void_p]
         L.arpc_set_profiling.restype = None
         L.arpc_set_profiling.argtypes = [C.c_int]
+        L.arpc_set_profiling_classes.restype = None
+        L.arpc_set_profiling_classes.argtypes = [C.c_uint]
         L.arpc_create.restype = C.c_int
         L.arpc_create.argtypes = [C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]
         L.arpc_destroy.restype = C.c_int
@@ -153,6 +156,14 @@ def arpc_stream_uniforms_host(seed: int, start: int, n: int) -> np.ndarray:
 
 def arpc_set_profiling(on: bool) -> None:
     lib().arpc_set_profiling(1 if on else 0)
+
+
+def arpc_set_profiling_classes(classes) -> None:
+    """Time only the named kernel classes (names from KERNEL_CLASSES)."""
+    mask = 0
+    for c in classes:
+        mask |= 1 << KERNEL_CLASSES.index(c)
+    lib().arpc_set_profiling_classes(mask)
 
 
 # ------------------------------------------------------------ torch convenience

@@ -24,7 +24,7 @@ using namespace arpc;
 
 namespace arpc {
 
-int g_profiling = 0;
+unsigned g_profiling = 0;   // timed kernel classes
 
 // The update GEMM and triangular solve run on the matrix cores; setting
 // ARPC_GEMM=valu selects the register-tiled vector kernels instead (FP64 and
@@ -375,7 +375,7 @@ namespace {
 arpc_status run_sync(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws, const Layout& l,
                      hipStream_t s, const Unif& un, arpc_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
-  Profiler prof(s, g_profiling != 0);
+  Profiler prof(s, g_profiling);
   RoundState h{};
   auto job = make_job(p, X, F, pivots, ws, l, s, un, &h, &prof);
   arpc_status e = job->begin();
@@ -451,6 +451,8 @@ arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, d
   return ARPC_OK;
 }
 
-void arpc_set_profiling(int on) { g_profiling = on; }
+void arpc_set_profiling(int on) { g_profiling = on ? ~0u : 0u; }
+
+void arpc_set_profiling_classes(unsigned mask) { g_profiling = mask; }
 
 }  // extern "C"

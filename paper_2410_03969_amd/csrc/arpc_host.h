@@ -27,12 +27,14 @@ struct Layout {
 struct Profiler {
   hipStream_t s;
   bool on;
+  unsigned mask;      // timed classes (bit per ARPC_KC_*)
+  bool open = false;  // the current class is being timed
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
   size_t used = 0;
   double ms[ARPC_NUM_KC] = {0};
   int64_t n[ARPC_NUM_KC] = {0};
-  Profiler(hipStream_t st, bool enable) : s(st), on(enable) {}
+  Profiler(hipStream_t st, unsigned classes) : s(st), on(classes != 0), mask(classes) {}
   ~Profiler() {
     for (auto e : pool) (void)hipEventDestroy(e);
   }
@@ -45,13 +47,15 @@ struct Profiler {
     return pool[used++];
   }
   void begin(int cls) {
-    if (!on) return;
+    open = on && ((mask >> cls) & 1u);
+    if (!open) return;
     marks.push_back({cls, used});
     (void)hipEventRecord(next(), s);
   }
   void end() {
-    if (!on) return;
+    if (!open) return;
     (void)hipEventRecord(next(), s);
+    open = false;
   }
   // called after a stream synchronisation; ARPC_TRACE=1 also prints every
   // launch's time to stderr

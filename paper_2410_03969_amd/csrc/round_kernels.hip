@@ -571,7 +571,7 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
     // solved panel; a tile's eight operands are read before its products
     auto update = [&](double(*P)[QS], auto pick) __attribute__((always_inline)) {
       for_tiles([&](int k, int J, int L) {
-        if (pick(L)) {
+        if (__builtin_expect(pick(L), 0)) {
           double av[4], bv[4];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
       // 1. the pending update on block column I, then its copy to LDS
       if (pmask) update(Qp, [&](int l) { return l == I; });
       for_tiles([&](int k, int J, int L) {
-        if (L == I)
+        if (__builtin_expect(L == I, 0))
 #pragma unroll
           for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = tr[k][i];
       });
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
       // X^T are zero), into the panel rows of the buffer (for the update)
       // and the accepted columns into H
       for_tiles([&](int k, int J, int L) {
-        if (L == I && J > I) {
+        if (__builtin_expect(L == I && J > I, 0)) {
           double av[4], bv[4];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
