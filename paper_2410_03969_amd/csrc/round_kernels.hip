@@ -487,15 +487,19 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
         if (iL < b) tk[iL] = (taken >> lane) & 1;
         if ((mask >> lane) & 1) accl[nacc + __popc(mask & ((1 << lane) - 1))] = (short)iL;
       }
-      int rank = 0;
+      double rs[RT];
+#pragma unroll
+      for (int ii = 0; ii < RT; ++ii) rs[ii] = rsq[ii];
+      // Straight-line stores: column ii goes to H column nacc + (accepted
+      // proposals before ii).  A rejected proposal's (zero) column lands in the
+      // column of the next accepted one, whose own store comes later and covers
+      // every row the compaction reads (rows at or below that proposal).
 #pragma unroll
       for (int ii = 0; ii < RT; ++ii) {
-        const double col = (l16 >= ii) ? dr[ii] * rsq[ii] : 0.0;
+        const double col = (l16 >= ii) ? dr[ii] * rs[ii] : 0.0;
         if (lane < RT) LD[ii][lane] = col;
-        if ((mask >> ii) & 1) {
-          if (lane < RT && lane >= ii && iL < b) H[(int64_t)(nacc + rank) * b + iL] = col;
-          ++rank;
-        }
+        const int cidx = nacc + __popc(mask & ((1 << ii) - 1));
+        if (lane < RT && lane >= ii && iL < b && cidx < b) H[(int64_t)cidx * b + iL] = col;
       }
       // X = L^{-1} restricted to the accepted proposals (rejected rows and
       // columns come out zero): lane c forms column c by forward
