@@ -88,7 +88,6 @@ Layout layout_of(const arpc_problem& p) {
   l.Fs = take(sizeof(double) * p.b * p.k);
   l.Hp = take(sizeof(double) * gather_splits(p.k) * p.b * p.b);
   l.H = take(sizeof(double) * p.b * p.b);
-  l.L = take(sizeof(double) * p.b * p.b);
   l.Xp = take(sizeof(double) * p.b * p.d);
   l.Bt = take(valu ? es * p.k * p.b : 0);
   l.Bt2 = take(valu ? es * p.b * p.b : 0);
@@ -140,7 +139,6 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   int32_t* hist = (int32_t*)(ws + l.hist);
   double* Fs = (double*)(ws + l.Fs);
   double* H = (double*)(ws + l.H);
-  double* L = (double*)(ws + l.L);
   double* Xp = (double*)(ws + l.Xp);
   T* Bt = (T*)(ws + l.Bt);
   T* Bt2 = (T*)(ws + l.Bt2);
@@ -151,26 +149,26 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   launch_propose(s, u, csum, cpre, nch, N, b, un, st, props);
   prof.end();
   MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
-               (int)((b + 15) / 16 * 16), P, Fs, k, acc, L, b, k};
+               (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k};
   prof.begin(ARPC_KC_GATHER);
   launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, (double*)(ws + l.Hp), H, st);
   prof.end();
   prof.begin(ARPC_KC_REJECT);
-  launch_reject(s, H, b, props, un, st, L, acc, pivots, u, k);
+  launch_reject(s, H, b, props, un, st, acc, pivots, u, k);
   prof.end();
   if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
     FusedRound fr{F, ws + l.Fb, (k + 31) / 32, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1),
                   (unsigned char*)(ws + l.Bm2), P, b, l.ncbt, l.grid};
     prof.begin(ARPC_KC_PREP);
     launch_prep_xp(s, acc, props, X, d, Xp, st);
-    launch_fused_prep(s, p.prec, fr, props, acc, L, st);
+    launch_fused_prep(s, p.prec, fr, props, acc, H, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
     launch_fused_round(s, p.prec, fr, st);
     prof.end();
   } else if (l.valu) {  // vector-unit kernels (cross-check path)
     prof.begin(ARPC_KC_PREP);
-    launch_prep<T>(s, Fs, k, acc, props, X, d, Bt, b, Xp, L, b, Bt2, k, st);
+    launch_prep<T>(s, Fs, k, acc, props, X, d, Bt, b, Xp, H, b, Bt2, k, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
     launch_colgemm<T>(s, F, N, Bt, b, X, d, Xp, kp, C, b, st);

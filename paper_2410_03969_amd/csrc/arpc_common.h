@@ -150,25 +150,40 @@ __device__ inline double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Column c of the inverse of the s x s lower-triangular L (column-major, ld
-// b), s <= 256, in one wavefront by column-oriented forward substitution: lane
-// l keeps rows l, l + 64, l + 128, l + 192 of the right-hand side e_c, which
-// becomes column c of L^{-1}.  Column t of L is read coalesced and does not
-// depend on the solution, so it is loaded P steps ahead (an L2 round trip
-// per step otherwise); the dependency chain is one readlane and a few FMAs
-// per step.  Rows outside [c, s) are zero.
-__device__ inline void linv_column(const double* __restrict__ L, int b, int s, int c, int lane, double (&r)[4]) {
+// The accepted factor L(T,T) as RejectionSampleSubmatrix leaves it: entry
+// (a, c), a >= c, is H(acc[a], acc[c]) (the scaled column of proposal acc[c]
+// stays in column acc[c] of the b x b column-major H).  Entries above the
+// diagonal are not defined.
+struct LFactor {
+  const double* H;
+  const int32_t* acc;
+  int b;
+  __device__ double at(int a, int c) const { return H[(int64_t)acc[c] * b + acc[a]]; }
+};
+
+// Column c of the inverse of the s x s lower-triangular L, s <= 256, in one
+// wavefront by column-oriented forward substitution: lane l keeps rows l,
+// l + 64, l + 128, l + 192 of the right-hand side e_c, which becomes column c
+// of L^{-1}.  Column t of L (gathered from one column of H) does not depend
+// on the solution, so it is loaded P steps ahead (an L2 round trip per step
+// otherwise); the dependency chain is one readlane and a few FMAs per step.
+// Rows outside [c, s) are zero.
+__device__ inline void linv_column(const LFactor& L, int s, int c, int lane, double (&r)[4]) {
   constexpr int P = 8;   // columns of L in flight ahead of the chain (divides 64)
   double invd[4];
-  int ic[4];             // row index clamped into L (rows outside (t, s) are masked at use)
+  int64_t ic[4];         // H row of row i (clamped to s - 1; rows outside (t, s) are masked at use)
+  if (c >= s) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) r[m] = 0.0;
+    return;
+  }
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int i = lane + 64 * m;
-    r[m] = (i == c && c < s) ? 1.0 : 0.0;
-    invd[m] = (i < s) ? 1.0 / L[(int64_t)i * b + i] : 0.0;
-    ic[m] = i < b ? i : b - 1;
+    r[m] = (i == c) ? 1.0 : 0.0;
+    invd[m] = (i < s) ? 1.0 / L.at(i, i) : 0.0;
+    ic[m] = L.acc[i < s ? i : s - 1];
   }
-  if (c >= s) return;
   // Steps t run from c rounded down to a multiple of P (earlier ones are
   // skipped); column t of L sits in buf[t % P], loaded P steps ahead with an
   // unconditional load (column index clamped to s - 1).  The rows of step t
@@ -181,7 +196,7 @@ __device__ inline void linv_column(const double* __restrict__ L, int b, int s, i
   for (int u = 0; u < P; ++u) {
     const int tc = t0 + u < s ? t0 + u : s - 1;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) buf[u][m] = L[(int64_t)tc * b + ic[m]];
+    for (int m = 0; m < 4; ++m) buf[u][m] = L.H[(int64_t)L.acc[tc] * L.b + ic[m]];
   }
   int t = t0;
 #pragma unroll
@@ -204,7 +219,7 @@ __device__ inline void linv_column(const double* __restrict__ L, int b, int s, i
         }
         const int tn = tt + P < s ? tt + P : s - 1;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) buf[u][m] = L[(int64_t)tn * b + ic[m]];
+        for (int m = 0; m < 4; ++m) buf[u][m] = L.H[(int64_t)L.acc[tn] * L.b + ic[m]];
       }
     }
   }

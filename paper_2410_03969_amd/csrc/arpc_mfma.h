@@ -26,7 +26,7 @@ struct MfmaRound {
   const double* Fs;        // F rows at the proposals, FP64, ld ldf
   int64_t ldf;
   const int32_t* acc;      // accepted local indices
-  const double* L;         // Cholesky factor of H(T,T), column-major, ld b
+  const double* H;         // H as left by RejectionSampleSubmatrix (holds L(T,T), see LFactor)
   int b;
   int64_t kmax;
 };
@@ -55,7 +55,7 @@ struct FusedRound {
 int fused_ncbt(int prec, int b);
 size_t fused_operand_bytes(int prec, int64_t kmax, int b);
 void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
-                       const double* L, const RoundState* st);
+                       const double* H, const RoundState* st);
 void launch_fused_round(hipStream_t s, int prec, const FusedRound& r, const RoundState* st);
 
 size_t mfma_operand_bytes(int prec, int64_t kmax, int b);

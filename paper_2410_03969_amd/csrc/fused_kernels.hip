@@ -612,19 +612,20 @@ __global__ __launch_bounds__(256) void k_fused_bm1(const __bf16* __restrict__ Fb
   }
 }
 
-// Inverse of the s x s lower factor L (column-major, ld b), one workgroup per
-// column t: forward substitution, then Linv(i, t) stored at chunk t / 32, slot
+// Inverse of the s x s lower factor L (read from H through the accepted
+// indices), one workgroup per column t: forward substitution, then Linv(i, t)
+// stored at chunk t / 32, slot
 // solve_slot(t % 32), column i (zero outside i, t < s and below the diagonal).
 template <int SPL, bool RES>
-__global__ __launch_bounds__(64) void k_fused_linv(const double* __restrict__ L, int b, int CP,
-                                                   unsigned char* __restrict__ Bm2, const RoundState* st) {
+__global__ __launch_bounds__(64) void k_fused_linv(LFactor L, int CP, unsigned char* __restrict__ Bm2,
+                                                   const RoundState* st) {
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   __shared__ double x[256];
   double r[4];
-  linv_column(L, b, s, c, lane, r);
+  linv_column(L, s, c, lane, r);
 #pragma unroll
   for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
   __syncthreads();
@@ -724,17 +725,18 @@ size_t fused_operand_bytes(int prec, int64_t kmax, int b) {
 }
 
 void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
-                       const double* L, const RoundState* st) {
+                       const double* H, const RoundState* st) {
+  const LFactor L{H, acc, r.b};
   const int cp = 16 * r.ncbt;
   const int nt = (r.ncbt + 1) / 2;
   if (prec == 2) {
     hipLaunchKernelGGL(k_fused_bm1<2>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
                        r.Bm1, st);
-    hipLaunchKernelGGL((k_fused_linv<2, false>), dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
+    hipLaunchKernelGGL((k_fused_linv<2, false>), dim3(nt * FKC), dim3(64), 0, s, L, cp, r.Bm2, st);
   } else {
     hipLaunchKernelGGL(k_fused_bm1<1>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
                        r.Bm1, st);
-    hipLaunchKernelGGL((k_fused_linv<1, true>), dim3(nt * FKC), dim3(64), 0, s, L, r.b, cp, r.Bm2, st);
+    hipLaunchKernelGGL((k_fused_linv<1, true>), dim3(nt * FKC), dim3(64), 0, s, L, cp, r.Bm2, st);
   }
 }
 

@@ -464,13 +464,14 @@ __global__ __launch_bounds__(256) void k_prep_bm(const double* __restrict__ Fs, 
   }
 }
 
-// Inverse of the s x s lower factor L (column-major, ld b): workgroup c
+// Inverse of the s x s lower factor L (read from H through the accepted
+// indices): workgroup c
 // computes column c by forward substitution with wavefront dot products and
 // stores Linv(i, c) as element (k = c, column i) of the chunked operand of the
 // triangular-solve product.  Workgroups c >= s write the zero padding.
 template <class Pol, int PASSES>
-__global__ __launch_bounds__(64) void k_trinv_bm(const double* __restrict__ L, int b, int Ctot,
-                                                 unsigned char* __restrict__ Bm, const RoundState* st) {
+__global__ __launch_bounds__(64) void k_trinv_bm(LFactor L, int Ctot, unsigned char* __restrict__ Bm,
+                                                 const RoundState* st) {
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
@@ -478,21 +479,21 @@ __global__ __launch_bounds__(64) void k_trinv_bm(const double* __restrict__ L, i
   __shared__ double x[BMAX];
   if (s <= 256) {
     double r[4];
-    linv_column(L, b, s, c, lane, r);
+    linv_column(L, s, c, lane, r);
 #pragma unroll
     for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
     __syncthreads();
   } else if (c < s) {
     for (int i = lane; i < s; i += 64) x[i] = 0.0;
     __syncthreads();
-    if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
+    if (lane == 0) x[c] = 1.0 / L.at(c, c);
     __syncthreads();
     for (int i = c + 1; i < s; ++i) {
       double p = 0.0;
-      for (int t = c + lane; t < i; t += 64) p += L[(int64_t)t * b + i] * x[t];
+      for (int t = c + lane; t < i; t += 64) p += L.at(i, t) * x[t];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      if (lane == 0) x[i] = -p / L[(int64_t)i * b + i];
+      if (lane == 0) x[i] = -p / L.at(i, i);
       __syncthreads();
     }
   }
@@ -561,7 +562,8 @@ static void prep_impl(hipStream_t s, const MfmaRound& r, const RoundState* st) {
   hipLaunchKernelGGL((k_prep_bm<Pol, PASSES>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r.Fs, r.ldf,
                      r.acc, r.Ctot, r.Bm1, st);
   const int nblk = (r.b + Pol::KC - 1) / Pol::KC * Pol::KC;
-  hipLaunchKernelGGL((k_trinv_bm<Pol, PASSES>), dim3(nblk), dim3(64), 0, s, r.L, r.b, r.Ctot, r.Bm2, st);
+  hipLaunchKernelGGL((k_trinv_bm<Pol, PASSES>), dim3(nblk), dim3(64), 0, s, LFactor{r.H, r.acc, r.b}, r.Ctot, r.Bm2,
+                     st);
 }
 
 size_t mfma_operand_bytes(int prec, int64_t kmax, int b) {

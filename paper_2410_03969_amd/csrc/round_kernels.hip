@@ -265,8 +265,10 @@ __global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X,
 // global memory.
 // Rules beyond the printed test u_i * V < h_ii: a proposal equal to one
 // already accepted in this round is rejected, and at most k - k_r proposals are
-// accepted.  Outputs: accepted local indices, the dense lower Cholesky factor
-// L of H(T,T) (column-major, ld b), the new pivots, u = 0 at the new pivots.
+// accepted.  Outputs: accepted local indices, the new pivots, u = 0 at the
+// new pivots, and the lower Cholesky factor L of H(T,T) left in H: the scaled
+// column of accepted proposal i is column i of H (rows at and below i), so
+// L(a, c) = H(acc[a], acc[c]) (read through LFactor).
 struct FullGlobal {
   double* p;
   int b;
@@ -275,7 +277,7 @@ struct FullGlobal {
 
 template <class Store>
 __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, Unif un,
-                            RoundState* st, double* __restrict__ Lout, int32_t* __restrict__ acc_out,
+                            RoundState* st, int32_t* __restrict__ acc_out,
                             int64_t* __restrict__ pivots, double* __restrict__ u, int64_t kmax,
                             unsigned char* tk, int* dec, short* accl) {
   const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
@@ -316,11 +318,7 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
     ++nacc;
   }
   __syncthreads();
-  // L = L(T,T), dense column-major
-  for (int q = tid; q < nacc * nacc; q += nthr) {
-    const int a = q % nacc, c = q / nacc;  // row a, column c
-    Lout[(int64_t)c * b + a] = (a >= c) ? S.at(accl[a], accl[c]) : 0.0;
-  }
+  // L(T,T) stays in H: entry (a, c) is S.at(accl[a], accl[c]) (see LFactor)
   for (int a = tid; a < nacc; a += nthr) {
     const int64_t p = props[accl[a]];
     acc_out[a] = accl[a];
@@ -349,8 +347,8 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
 //     the matrix cores, four products per tile (rejected columns are zero).
 // Three barriers per 16 proposals; the block-column buffer is double-buffered
 // so a block's copy does not overwrite the previous panel while it is still
-// being applied.  The scaled accepted columns are kept in H (no longer read
-// once in registers) and compacted into L(T,T) at the end.
+// being applied.  The scaled column of proposal i goes to column i of H (no
+// longer read once in registers), where the solve's preparation reads it.
 constexpr int RT = 16;                  // tile edge
 constexpr int REJECT_T_THREADS = 512;
 constexpr int REJECT_T_BMAX = 256;
@@ -371,8 +369,7 @@ __device__ inline void tile_advance(int& J, int& L) {
 
 __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __restrict__ H, int b,
                                                                    const int64_t* __restrict__ props, Unif un,
-                                                                   RoundState* st, double* __restrict__ Lout,
-                                                                   int32_t* __restrict__ acc_out,
+                                                                   RoundState* st, int32_t* __restrict__ acc_out,
                                                                    int64_t* __restrict__ pivots,
                                                                    double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
@@ -490,16 +487,13 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
       double rs[RT];
 #pragma unroll
       for (int ii = 0; ii < RT; ++ii) rs[ii] = rsq[ii];
-      // Straight-line stores: column ii goes to H column nacc + (accepted
-      // proposals before ii).  A rejected proposal's (zero) column lands in the
-      // column of the next accepted one, whose own store comes later and covers
-      // every row the compaction reads (rows at or below that proposal).
+      // column ii of the factor (zero for a rejected proposal) into column
+      // 16 I + ii of H, rows of the block at and below ii
 #pragma unroll
       for (int ii = 0; ii < RT; ++ii) {
         const double col = (l16 >= ii) ? dr[ii] * rs[ii] : 0.0;
         if (lane < RT) LD[ii][lane] = col;
-        const int cidx = nacc + __popc(mask & ((1 << ii) - 1));
-        if (lane < RT && lane >= ii && iL < b && cidx < b) H[(int64_t)cidx * b + iL] = col;
+        if (lane < RT && lane >= ii && iL < b && RT * I + ii < b) H[(int64_t)(RT * I + ii) * b + iL] = col;
       }
       // X = L^{-1} restricted to the accepted proposals (rejected rows and
       // columns come out zero): lane c forms column c by forward
@@ -622,14 +616,13 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
           for (int ks = 0; ks < 4; ++ks) pj = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], pj, 0, 0, 0);
 #pragma unroll
           for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = pj[i];
-          if ((mask >> l16) & 1) {
-            const int64_t c = nacc + __popc(mask & ((1 << l16) - 1));
+          // column l16 of the panel (zero if rejected) into column 16 I + l16 of H
+          if (RT * I + l16 < b)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int row = RT * J + g + 4 * i;
-              if (row < b) H[c * b + row] = pj[i];
+              if (row < b) H[(int64_t)(RT * I + l16) * b + row] = pj[i];
             }
-          }
         }
       });
       __syncthreads();   // (3)
@@ -637,23 +630,6 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
     }
   }
   __syncthreads();
-  // L = L(T,T), dense column-major: L(a, c) = scaled column c at row accl[a];
-  // eight loads in flight per thread
-  const int nn = nacc * nacc;
-  for (int q0 = tid; q0 < nn; q0 += 8 * REJECT_T_THREADS) {
-    double v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int q = q0 + k * REJECT_T_THREADS;
-      const int a = q % nacc, c = q / nacc;
-      v[k] = (q < nn && a >= c) ? H[(int64_t)c * b + accl[a]] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int q = q0 + k * REJECT_T_THREADS;
-      if (q < nn) Lout[(int64_t)(q / nacc) * b + q % nacc] = v[k];
-    }
-  }
   for (int a = tid; a < nacc; a += REJECT_T_THREADS) {
     const int64_t pv = props[accl[a]];
     acc_out[a] = accl[a];
@@ -665,8 +641,7 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
 
 __global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, int b,
                                                         const int64_t* __restrict__ props, Unif un,
-                                                        RoundState* st, double* __restrict__ Lout,
-                                                        int32_t* __restrict__ acc_out,
+                                                        RoundState* st, int32_t* __restrict__ acc_out,
                                                         int64_t* __restrict__ pivots,
                                                         double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
@@ -674,7 +649,7 @@ __global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, 
   __shared__ short accl[BMAX];
   __shared__ int dec[2];
   FullGlobal S{H, b};
-  reject_body(S, b, props, un, st, Lout, acc_out, pivots, u, kmax, tk, dec, accl);
+  reject_body(S, b, props, un, st, acc_out, pivots, u, kmax, tk, dec, accl);
 }
 
 // --------------------------------------------------------- update preparation
@@ -699,13 +674,14 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ Fs, int
     }
 }
 
-// Inverse of the s x s lower factor L (column-major, ld b), one column per
-// workgroup by forward substitution with wavefront dot products.  Writes
+// Inverse of the s x s lower factor L (read from H through the accepted
+// indices), one column per workgroup by forward substitution with wavefront
+// dot products.  Writes
 // Bt2(t, c) = Linv(c, t) in the GEMM type (row-major, ld b): the B operand of
 // the triangular-solve product G = C Linv^T.
 template <typename T>
-__global__ __launch_bounds__(64) void k_trinv(const double* __restrict__ L, int b, T* __restrict__ Bt2,
-                                              const RoundState* st) {
+__global__ __launch_bounds__(64) void k_trinv(LFactor L, T* __restrict__ Bt2, const RoundState* st) {
+  const int b = L.b;
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
@@ -714,14 +690,14 @@ __global__ __launch_bounds__(64) void k_trinv(const double* __restrict__ L, int 
   const int lane = threadIdx.x;
   for (int i = lane; i < s; i += 64) x[i] = 0.0;
   __syncthreads();
-  if (lane == 0) x[c] = 1.0 / L[(int64_t)c * b + c];
+  if (lane == 0) x[c] = 1.0 / L.at(c, c);
   __syncthreads();
   for (int i = c + 1; i < s; ++i) {
     double p = 0.0;
-    for (int t = c + lane; t < i; t += 64) p += L[(int64_t)t * b + i] * x[t];
+    for (int t = c + lane; t < i; t += 64) p += L.at(i, t) * x[t];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-    if (lane == 0) x[i] = -p / L[(int64_t)i * b + i];
+    if (lane == 0) x[i] = -p / L.at(i, i);
     __syncthreads();
   }
   // row c of Bt2 holds column c of Linv: Bt2(c, i) = Linv(i, c), zero for i < c
@@ -821,22 +797,21 @@ template void launch_gather<float>(hipStream_t, const float*, int64_t, const dou
                                    const RoundState*);
 
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
-                   double* L, int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
+                   int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
   if (b <= REJECT_T_BMAX)
-    hipLaunchKernelGGL(k_reject_tiled, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, L, acc, pivots,
+    hipLaunchKernelGGL(k_reject_tiled, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc, pivots,
                        u, kmax);
   else
-    hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, L, acc, pivots, u,
-                       kmax);
+    hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, acc, pivots, u, kmax);
 }
 
 template <typename T>
 void launch_prep(hipStream_t s, const double* Fs, int64_t ldf, const int32_t* acc, const int64_t* props,
-                 const double* X, int d, T* Bt, int ldb, double* Xp, const double* L, int b, T* Bt2,
+                 const double* X, int d, T* Bt, int ldb, double* Xp, const double* H, int b, T* Bt2,
                  int64_t kmax, const RoundState* st) {
   hipLaunchKernelGGL(k_prep<T>, dim3((unsigned)((kmax + 255) / 256)), dim3(256), 0, s, Fs, ldf, acc, props, X,
                      d, Bt, ldb, Xp, st);
-  hipLaunchKernelGGL(k_trinv<T>, dim3(b), dim3(64), 0, s, L, b, Bt2, st);
+  hipLaunchKernelGGL(k_trinv<T>, dim3(b), dim3(64), 0, s, LFactor{H, acc, b}, Bt2, st);
 }
 template void launch_prep<double>(hipStream_t, const double*, int64_t, const int32_t*, const int64_t*,
                                   const double*, int, double*, int, double*, const double*, int, double*,
