@@ -106,7 +106,14 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   constexpr int XPS = RING + TRI;
   constexpr int YN = XPS + CP * DX * 4;         // squared norms of the accepted points
   constexpr int DUMMY = YN + CP * 4;            // 16-byte sink of surplus staging pieces
-  __shared__ __attribute__((aligned(16))) unsigned char lds[DUMMY + 16];
+  // SEPW: the store window has its own LDS (when it fits), so no barrier
+  // separates one tile's stores from the next tile's ring; with nothing to
+  // contract (k_r = 0) a tile then needs no barrier at all, and the
+  // wavefronts drift apart, one's stores overlapping another's arithmetic.
+  constexpr int WIN = FW * WC * EROW * 4;
+  constexpr bool SEPW = RES && (DUMMY + 16 + WIN <= 160 * 1024);
+  constexpr int WINOFF = DUMMY + 16;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[SEPW ? WINOFF + WIN : DUMMY + 16];
   float* xps = (float*)(lds + XPS);
   float* yn = (float*)(lds + YN);
   // Distances: the three-product mode differences the coordinates directly;
@@ -156,10 +163,11 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 
   if constexpr (RES) {
     // the inverse factor's triangle, once per launch (ordered before its first
-    // use by the first barrier of the tile loop)
+    // use by the barrier below, or the first barrier of the tile loop)
     for (int q = tid0; q < TRI / 16; q += 64 * FW)
       *(u4*)(lds + RING + q * 16) = *(const u4*)(a.Bm2 + (size_t)q * 16);
   }
+  if constexpr (SEPW) __syncthreads();
 
   // ---- small-operand ring: stream position q < nk is chunk q of Bm1, then
   // (streaming form) the NT chunks of the inverse factor.  Chunks are loaded
@@ -267,8 +275,10 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // are never consumed); only the products are guarded.  The
     // load counter is in-order, so the fetch goes first: the wait before its
     // commit leaves the F loads in flight.
-    commit_from(sbq[0], 0);
-    __syncthreads();
+    if (!SEPW || nk > 0) {   // uniform
+      commit_from(sbq[0], 0);
+      __syncthreads();
+    }
 
     for (int64_t ch0 = 0; ch0 < nk; ch0 += FD) {
 #pragma unroll
@@ -556,9 +566,10 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         }
       }
     }
-    // E[col][row]: WC columns x 32 rows of this wavefront (the ring area: no
-    // wavefront reads the ring after the last barrier of the contraction)
-    float* E = (float*)lds + w * (WC * EROW);
+    // E[col][row]: WC columns x 32 rows of this wavefront (its own area with
+    // SEPW, else the ring area: no wavefront reads the ring after the last
+    // barrier of the contraction)
+    float* E = (float*)(lds + (SEPW ? WINOFF : 0)) + w * (WC * EROW);
     const int nrows = (N - row_w) < (FNB * 16) ? (int)(N - row_w) : FNB * 16;
     const bool vec_cols = (N & 3) == 0;          // 16-byte aligned columns of F
 #pragma unroll
@@ -585,7 +596,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         }
       }
     }
-    __syncthreads();   // the window area is the ring of the next tile
+    if constexpr (!SEPW) __syncthreads();   // the window area is the ring of the next tile
   }
 }
 
