@@ -95,6 +95,8 @@ Layout layout_of(const arpc_problem& p) {
   l.Bm2 = take(mb);
   l.Fb = take(valu ? 0 : mfma_blocked_bytes(p.prec, p.N, p.k));
   l.C = take(valu ? es * p.N * p.b : (fused ? 0 : mfma_blocked_bytes(p.prec, p.N, p.b)));
+  l.dist = !valu && !fused && mfma_dist_contraction((int)p.d);
+  l.C0 = take(l.dist ? es * p.N * p.b : 0);
   l.P = take(sizeof(double) * nparts * p.N);
   l.trace = take(sizeof(double));
   l.total = off;
@@ -149,7 +151,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   launch_propose(s, u, csum, cpre, nch, N, b, un, st, props);
   prof.end();
   MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
-               (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k};
+               (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k, l.dist ? (void*)(ws + l.C0) : nullptr};
   prof.begin(ARPC_KC_GATHER);
   launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, (double*)(ws + l.Hp), H, st);
   prof.end();
@@ -182,6 +184,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
     launch_mfma_prep(s, p.prec, mr, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
+    if (mr.C0) launch_dist(s, p.prec, mr, st);
     launch_mfma_colgemm(s, p.prec, mr, st);
     prof.end();
     prof.begin(ARPC_KC_TRSM);

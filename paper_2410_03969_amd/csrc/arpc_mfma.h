@@ -29,6 +29,8 @@ struct MfmaRound {
   const double* H;         // H as left by RejectionSampleSubmatrix (holds L(T,T), see LFactor)
   int b;
   int64_t kmax;
+  void* C0;                // kernel columns for d > 16 (FP64 in the FP64 mode, else FP32; N x b
+                           // column-major), or null
 };
 
 // Device pointers and sizes of the one-kernel round product of the BF16
@@ -63,6 +65,10 @@ size_t mfma_blocked_bytes(int prec, int64_t N, int64_t cols);
 int mfma_part_cols(int prec, int b);
 void launch_mfma_prep(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
 void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
+// Kernel columns on the matrix cores for d > 16 (into r.C0, read by the
+// update GEMM's epilogue).
+bool mfma_dist_contraction(int d);
+void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
 void launch_mfma_trsm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
 void launch_prep_xp(hipStream_t s, const int32_t* acc, const int64_t* props, const double* X, int d,
                     double* Xp, const RoundState* st);

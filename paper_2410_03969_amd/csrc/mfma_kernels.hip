@@ -115,6 +115,7 @@ struct PanelArgs {
   const RoundState* st;
   int npanels;         // row panels of this kernel
   int ngroups;         // column groups
+  const void* C0;      // colgemm: kernel columns precomputed by k_dist (T, column-major, ld N), or null
 };
 
 // Byte offset of element (k, c) of the chunked small operand.
@@ -390,7 +391,9 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
       for (int cc = my_part; cc < wv; cc += LPR) {
         const int c = w0 + cc;
         T& v = E[cc * EROW + my_row];
-        if (MODE == MODE_COLGEMM) {
+        if (MODE == MODE_COLGEMM && a.C0) {
+          v = (T)((double)((const T*)a.C0)[(int64_t)c * N + row] - (double)v);
+        } else if (MODE == MODE_COLGEMM) {
           const double* xp = a.Xp + (int64_t)c * d;
           double r2 = 0.0;
           if (d <= XREG) {
@@ -437,6 +440,103 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
     if (LPR == 2) g2 += __shfl_xor(g2, 32, 64);
     if (my_part == 0 && rok) a.P[(int64_t)grp * N + row] = g2;
   }
+}
+
+// ------------------------------------------- kernel columns for large d
+// C0(row, c) = kappa(|x_row - x_c|^2) for c < s_r, column-major (ld N), when
+// d > XREG: the distances come from |x|^2 + |y|^2 - 2 x.y with x.y on the
+// matrix cores (16x16x4, FP64 in the FP64 mode, FP32 otherwise) instead of a
+// d-long difference loop per entry.  Where the expansion cancels (r^2 below
+// a fraction of |x|^2 + |y|^2: 2^-10 in FP64, 2^-6 in FP32) the entry is
+// recomputed by direct differences in FP64, so nearby and identical points
+// keep the direct-difference accuracy.  Wavefront w of workgroup (x, y) owns
+// rows 64 y + 16 w .. + 15 and columns 64 x .. + 63 (the column groups of a
+// row block are consecutive workgroups, so the rows are reused from L2).
+// Contraction slot j of lane group g in the step over dims 16 q .. 16 q + 15
+// is dim 16 q + 4 g + j, so each lane reads four consecutive coordinates of
+// each operand per four products.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int d, const double* __restrict__ Xp,
+                                              KParams kp, T* __restrict__ C0, int64_t N, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  typedef T V4 __attribute__((ext_vector_type(4)));
+  const int s = st->s_r;
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= s) return;
+  __shared__ T ynl[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int64_t rowl = (int64_t)blockIdx.y * 64 + w * 16 + l16;   // this lane's row (B operand)
+  const double* xrow = X + (rowl < N ? rowl : N - 1) * d;
+  const double* xc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int c = c0 + 16 * ct + l16;                               // this lane's column (A operand)
+    xc[ct] = Xp + (int64_t)(c < s ? c : s - 1) * d;
+  }
+  V4 acc[4];
+  T yp[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    acc[ct] = V4{0, 0, 0, 0};
+    yp[ct] = 0;
+  }
+  T xp = 0;
+  for (int k0 = 0; k0 < d; k0 += 16) {
+    const int kb = k0 + 4 * g;
+    T bv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bv[j] = kb + j < d ? (T)xrow[kb + j] : (T)0;
+      xp += bv[j] * bv[j];
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      T av[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        av[j] = kb + j < d ? (T)xc[ct][kb + j] : (T)0;
+        yp[ct] += av[j] * av[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (sizeof(T) == 8) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[ct], 0, 0, 0);
+        else acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc[ct], 0, 0, 0);
+      }
+    }
+  }
+  // norms: the four lane groups of a row (column) hold its partial sums
+  xp += __shfl_xor(xp, 16, 64);
+  xp += __shfl_xor(xp, 32, 64);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    T y = yp[ct];
+    y += __shfl_xor(y, 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    if (g == 0) ynl[w][16 * ct + l16] = y;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const T frac = sizeof(T) == 8 ? (T)0x1p-10 : (T)0x1p-6;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      // accumulator entry i of lane (g, l16): column 16 ct + m, row l16
+      const int m = sizeof(T) == 8 ? g + 4 * i : 4 * g + i;
+      const int c = c0 + 16 * ct + m;
+      if (c < s && rowl < N) {
+        const T yn = ynl[w][16 * ct + m];
+        T r2 = xp + yn - 2 * acc[ct][i];
+        double kap;
+        if (r2 < frac * (xp + yn)) {
+          const double r2d = sqdist(xrow, Xp + (int64_t)c * d, d);
+          kap = sizeof(T) == 8 ? kappa_r2(r2d, kp) : (double)kappa_r2_f32((float)r2d, kp);
+        } else {
+          kap = sizeof(T) == 8 ? kappa_r2((double)r2, kp) : (double)kappa_r2_f32((float)r2, kp);
+        }
+        C0[(int64_t)c * N + rowl] = (T)kap;
+      }
+    }
 }
 
 // ------------------------------------------ small operands in chunk layout
@@ -520,11 +620,11 @@ static void launch_panel(hipStream_t s, const MfmaRound& r, const RoundState* st
   const int64_t nkcF = (r.kmax + Pol::KC - 1) / Pol::KC, nkcC = (r.b + Pol::KC - 1) / Pol::KC;
   if (which == 0) {
     PanelArgs a1{r.Fb, nkcF, r.N, r.Bm1, r.Ctot, r.X, r.d, r.Xp, r.kp, nullptr, r.C, nkcC, nullptr, st,
-                 npanels, ngroups};
+                 npanels, ngroups, r.C0};
     hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_COLGEMM, PASSES>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0, s, a1);
   } else {
     PanelArgs a2{r.C, nkcC, r.N, r.Bm2, r.Ctot, nullptr, 0, nullptr, r.kp, r.F, r.Fb, nkcF, r.P, st,
-                 npanels, ngroups};
+                 npanels, ngroups, nullptr};
     hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_TRSM, PASSES>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0, s, a2);
   }
 }
@@ -602,6 +702,16 @@ void launch_mfma_prep(hipStream_t s, int prec, const MfmaRound& r, const RoundSt
     case 2: prep_impl<PolBF<3>, 3>(s, r, st); break;
     default: prep_impl<PolBF<1>, 1>(s, r, st); break;
   }
+}
+
+bool mfma_dist_contraction(int d) { return d > XREG; }
+
+void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
+  const dim3 grid((unsigned)((r.b + 63) / 64), (unsigned)((r.N + 63) / 64));
+  if (prec == 0)
+    hipLaunchKernelGGL(k_dist<double>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, (double*)r.C0, r.N, st);
+  else
+    hipLaunchKernelGGL(k_dist<float>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, (float*)r.C0, r.N, st);
 }
 
 void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
