@@ -349,9 +349,13 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
 // so a block's copy does not overwrite the previous panel while it is still
 // being applied.  The scaled column of proposal i goes to column i of H (no
 // longer read once in registers), where the solve's preparation reads it.
+// For 256 < b <= 512 the triangle (up to 528 tiles, 1 MiB) does not fit the
+// register file; the GT form keeps the trailing tiles in H and streams them
+// through the same steps (wavefront 0 and the LDS side unchanged).
 constexpr int RT = 16;                  // tile edge
 constexpr int REJECT_T_THREADS = 512;
 constexpr int REJECT_T_BMAX = 256;
+constexpr int REJECT_G_BMAX = 512;      // the form with the trailing tiles in global memory
 constexpr int REJECT_T_TW = 7;          // tile wavefronts
 constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
@@ -367,21 +371,23 @@ __device__ inline void tile_advance(int& J, int& L) {
   }
 }
 
+template <bool GT>
 __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __restrict__ H, int b,
                                                                    const int64_t* __restrict__ props, Unif un,
                                                                    RoundState* st, int32_t* __restrict__ acc_out,
                                                                    int64_t* __restrict__ pivots,
                                                                    double* __restrict__ u, int64_t kmax) {
   if (st->status != ST_RUNNING) return;
-  __shared__ __attribute__((aligned(16))) double Q[2][REJECT_T_BMAX][QS];  // block columns
+  constexpr int BM = GT ? REJECT_G_BMAX : REJECT_T_BMAX;
+  __shared__ __attribute__((aligned(16))) double Q[2][BM][QS];  // block columns
   __shared__ double LD[RT][RT];            // LD[ii][r]: scaled accepted column ii at row r of the block
   __shared__ double BC[RT][RT];            // BC[ii][r]: column ii of the block when its test runs;
                                            // then X = L^{-1} of the block's accepted part, X(r, c) at BC[r][c]
   __shared__ double rsq[RT];               // 1/sqrt(h) of the accepted proposals (0: rejected)
-  __shared__ double uv[REJECT_T_BMAX];     // u_i V_i of the test
-  __shared__ int64_t pr[REJECT_T_BMAX];
-  __shared__ short prv[REJECT_T_BMAX], accl[REJECT_T_BMAX];
-  __shared__ unsigned char tk[REJECT_T_BMAX];
+  __shared__ double uv[BM];     // u_i V_i of the test
+  __shared__ int64_t pr[BM];
+  __shared__ short prv[BM], accl[BM];
+  __shared__ unsigned char tk[BM];
   __shared__ int bmask;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: tile coordinates stay scalar
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
       __syncthreads();   // (3) the panel is solved
       nacc += __popc(mask);
     }
-  } else {
+  } else if constexpr (!GT) {
     const int wt = w - 1;
     rd4 tr[REJECT_T_TPW];
     // coordinates of this wavefront's tiles, four bits each of J and L, four
@@ -625,6 +631,135 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
             }
         }
       });
+      __syncthreads();   // (3)
+      nacc += __popc(mask);
+    }
+  } else {
+    // Trailing tiles in H itself: tile (J, L), J >= L, element (r, c) (row
+    // 16 J + r, column 16 L + c of the residual) at H[(16 J + r) b + 16 L + c],
+    // which is the upper triangle of the column-major H for J > L and the
+    // whole diagonal block for J = L.  The factor goes to the lower triangle
+    // of block columns already consumed, so the two never overlap.  At most
+    // 2 MiB, held in the L2 of the workgroup's XCD; each update is a load,
+    // four matrix-core products and a store per tile.
+    const int wt = w - 1;
+    // tile (J, L) from H (indices clamped into the matrix; see tpad)
+    auto tload = [&](int J, int L) __attribute__((always_inline)) {
+      rd4 t;
+      const int col = RT * L + l16;
+      const int cc = col < b ? col : b - 1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = RT * J + g + 4 * i;
+        t[i] = H[(int64_t)(row < b ? row : b - 1) * b + cc];
+      }
+      return t;
+    };
+    // zero padding outside the b x b matrix
+    auto tpad = [&](rd4& t, int J, int L) __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (RT * J + g + 4 * i >= b || RT * L + l16 >= b) t[i] = 0.0;
+    };
+    auto tstore = [&](const rd4& t, int J, int L) __attribute__((always_inline)) {
+      const int col = RT * L + l16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = RT * J + g + 4 * i;
+        if (row < b && col < b) H[(int64_t)row * b + col] = t[i];
+      }
+    };
+    // T(J, L) -= P_J P_L^T, P the previous block's solved panel
+    auto tupd = [&](rd4 t, double(*P)[QS], int J, int L) __attribute__((always_inline)) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        av[ks] = P[RT * J + l16][4 * ks + g];
+        bv[ks] = P[RT * L + l16][4 * ks + g];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) t = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ks], bv[ks], t, 0, 0, 0);
+      return t;
+    };
+    constexpr int NB1 = (REJECT_G_BMAX / RT + REJECT_T_TW - 1) / REJECT_T_TW;   // tiles of a block column per wavefront
+    constexpr int NB = 8;                                                       // tiles in flight in the update
+    int pmask = 0;
+    for (int I = 0; I < nbk && nacc < cap; ++I) {
+      double(*Qb)[QS] = Q[I & 1];
+      double(*Qp)[QS] = Q[(I + 1) & 1];
+      // 1. block column I (tiles (J, I), J >= I) with the pending update, to LDS
+      {
+        rd4 t[NB1];
+#pragma unroll
+        for (int n = 0; n < NB1; ++n) {
+          const int J = I + wt + REJECT_T_TW * n;
+          t[n] = tload(J < nbk ? J : nbk - 1, I);
+        }
+#pragma unroll
+        for (int n = 0; n < NB1; ++n) {
+          const int J = I + wt + REJECT_T_TW * n;
+          if (J < nbk) {
+            tpad(t[n], J, I);
+            if (pmask) t[n] = tupd(t[n], Qp, J, I);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = t[n][i];
+          }
+        }
+      }
+      __syncthreads();   // (1)
+      // 2. the rest of the pending update, beside the tests: the trailing
+      // tiles (J, L), J >= L > I, numbered down the block columns, tile q to
+      // tile wavefront q mod 7, eight loads in flight
+      if (pmask) {
+        const int nt = nbk - I - 1, m = nt * (nt + 1) / 2;
+        int L = I + 1, off = wt;   // tile q: (L + off, L)
+        for (int q = wt; q < m; q += REJECT_T_TW * NB) {
+          int Js[NB], Ls[NB];
+          rd4 t[NB];
+#pragma unroll
+          for (int n = 0; n < NB; ++n) {
+            while (off >= nbk - L && L < nbk - 1) {
+              off -= nbk - L;
+              ++L;
+            }
+            Js[n] = L + off < nbk ? L + off : nbk - 1;
+            Ls[n] = L;
+            t[n] = tload(Js[n], Ls[n]);
+            off += REJECT_T_TW;
+          }
+#pragma unroll
+          for (int n = 0; n < NB; ++n) {
+            if (q + REJECT_T_TW * n < m) {
+              tpad(t[n], Js[n], Ls[n]);
+              tstore(tupd(t[n], Qp, Js[n], Ls[n]), Js[n], Ls[n]);
+            }
+          }
+        }
+      }
+      __syncthreads();   // (2)
+      const int mask = bmask;
+      pmask = mask;
+      if (mask == 0) continue;
+      // 3. the panel below the block, as in the register-resident form
+      for (int J = I + 1 + wt; J < nbk; J += REJECT_T_TW) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          av[ks] = Qb[RT * J + l16][4 * ks + g];
+          bv[ks] = BC[l16][4 * ks + g];
+        }
+        rd4 pj = rd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) pj = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], pj, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = pj[i];
+        if (RT * I + l16 < b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = RT * J + g + 4 * i;
+            if (row < b) H[(int64_t)(RT * I + l16) * b + row] = pj[i];
+          }
+      }
       __syncthreads();   // (3)
       nacc += __popc(mask);
     }
@@ -799,8 +934,11 @@ template void launch_gather<float>(hipStream_t, const float*, int64_t, const dou
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
                    int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
   if (b <= REJECT_T_BMAX)
-    hipLaunchKernelGGL(k_reject_tiled, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc, pivots,
-                       u, kmax);
+    hipLaunchKernelGGL(k_reject_tiled<false>, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc,
+                       pivots, u, kmax);
+  else if (b <= REJECT_G_BMAX)
+    hipLaunchKernelGGL(k_reject_tiled<true>, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc,
+                       pivots, u, kmax);
   else
     hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, acc, pivots, u, kmax);
 }

@@ -91,6 +91,32 @@ def test_large_block_global_rejection_path():
     assert_parity(F, piv, out, oracle_run(X, prob))
 
 
+@pytest.mark.parametrize("b", [400, 512, 513])
+def test_large_blocks_two_rounds(b):
+    """b = 400 and 512: trailing tiles in global memory (ragged and full last
+    block column); b = 513: the one-proposal-at-a-time global kernel.  Two
+    full rounds and a partial third (the pivot cap)."""
+    rng = np.random.default_rng(b)
+    X = rng.standard_normal((5000, 6))
+    prob = W.Problem(N=5000, d=6, k=2 * b + 11, b=b, kernel=W.MATERN32, sigma=1.5, seed=b)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
+@pytest.mark.parametrize("b", [300, 520])
+def test_identity_matrix_exact_large_block(b):
+    """A = I with blocks above the register-resident limit: repeated proposals
+    of one point inside a block must be rejected exactly as in sampling
+    without replacement."""
+    X = W.grid(5, levels=5)
+    N = X.shape[0]
+    prob = W.Problem(N=N, d=5, k=1500, b=b, kernel=W.GAUSSIAN, sigma=1.0, seed=13)
+    F, piv, out = gpu_factor(X, prob)
+    want = simulate_identity(N, prob.k, prob.b, philox_stream(prob.seed))
+    assert list(piv) == want
+    assert np.array_equal(F, np.eye(N)[:, want])
+
+
 def test_lds_limit_block_size():
     rng = np.random.default_rng(3)
     X = rng.standard_normal((3000, 4))
