@@ -53,7 +53,13 @@ typedef enum arpc_prec {
   ARPC_FP32 = 1,    /* F stored FP32; update GEMM and solve in FP32 */
   ARPC_BF16X3 = 2,  /* F stored FP32; update GEMM on BF16 matrix cores with a
                        hi/lo split of both operands (three products), FP32 accumulation */
-  ARPC_BF16 = 3     /* F stored FP32; update GEMM with BF16-rounded operands, FP32 accumulation */
+  ARPC_BF16 = 3,    /* F stored FP32; update GEMM with BF16-rounded operands, FP32 accumulation */
+  ARPC_FP8 = 4      /* the kernel matrix of the points rounded to FP8 e4m3 (OCP: 3 fraction
+                       bits, exponent bias 7, ties to even, saturating at +-448), factored as
+                       in ARPC_BF16; the distances of the kernel columns contract the e4m3
+                       coordinates on FP8 matrix cores with FP32 accumulation (exact products),
+                       the b x b steps use the same rounded points in FP64.  Workspace holds
+                       the rounded copy (8 N d bytes). */
 } arpc_prec;
 
 typedef struct arpc_problem {

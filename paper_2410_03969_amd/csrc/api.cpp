@@ -60,18 +60,23 @@ inline int64_t nchunks_of(int64_t N) { return (N + CHUNK - 1) / CHUNK; }
 
 size_t elem_size(int prec) { return prec == ARPC_FP64 ? sizeof(double) : sizeof(float); }
 
+// The FP8 mode runs the BF16 mode's update GEMM and solve; only the kernel
+// columns differ (FP8 contraction of the rounded points).
+int gemm_prec(int prec) { return prec == ARPC_FP8 ? ARPC_BF16 : prec; }
+
 Layout layout_of(const arpc_problem& p) {
   Layout l{};
   const size_t es = elem_size(p.prec);
   const int64_t nch = nchunks_of(p.N);
+  const int gp = gemm_prec(p.prec);
   const bool valu = use_valu_gemm() && p.prec <= ARPC_FP32;
   l.valu = valu;
-  l.ncbt = (!valu && !fused_disabled() && p.d <= 16) ? fused_ncbt(p.prec, (int)p.b) : -1;
+  l.ncbt = (!valu && !fused_disabled() && p.d <= 16 && p.prec != ARPC_FP8) ? fused_ncbt(gp, (int)p.b) : -1;
   const bool fused = l.ncbt > 0;
-  l.part_cols = valu ? 64 : (fused ? BMAX : mfma_part_cols(p.prec, (int)p.b));
+  l.part_cols = valu ? 64 : (fused ? BMAX : mfma_part_cols(gp, (int)p.b));
   const int64_t nparts = (p.b + l.part_cols - 1) / l.part_cols;
-  const size_t mb = valu ? 0 : (fused ? fused_operand_bytes(p.prec, p.k, (int)p.b)
-                                      : mfma_operand_bytes(p.prec, p.k, (int)p.b));
+  const size_t mb = valu ? 0 : (fused ? fused_operand_bytes(gp, p.k, (int)p.b)
+                                      : mfma_operand_bytes(gp, p.k, (int)p.b));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -93,11 +98,12 @@ Layout layout_of(const arpc_problem& p) {
   l.Bt2 = take(valu ? es * p.b * p.b : 0);
   l.Bm1 = take(mb);
   l.Bm2 = take(mb);
-  l.Fb = take(valu ? 0 : mfma_blocked_bytes(p.prec, p.N, p.k));
-  l.C = take(valu ? es * p.N * p.b : (fused ? 0 : mfma_blocked_bytes(p.prec, p.N, p.b)));
-  l.dist = !valu && !fused && mfma_dist_contraction((int)p.d);
+  l.Fb = take(valu ? 0 : mfma_blocked_bytes(gp, p.N, p.k));
+  l.C = take(valu ? es * p.N * p.b : (fused ? 0 : mfma_blocked_bytes(gp, p.N, p.b)));
+  l.dist = !valu && !fused && (mfma_dist_contraction((int)p.d) || p.prec == ARPC_FP8);
   l.C0 = take(l.dist ? es * p.N * p.b : 0);
   l.P = take(sizeof(double) * nparts * p.N);
+  l.Xq = take(p.prec == ARPC_FP8 ? sizeof(double) * p.N * p.d : 0);
   l.trace = take(sizeof(double));
   l.total = off;
   return l;
@@ -110,7 +116,7 @@ arpc_status validate(const arpc_problem* p) {
   if (p->k < 1 || p->k > p->N) return ARPC_EINVAL;
   if (p->b < 1 || p->b > BMAX) return ARPC_EINVAL;
   if (p->kernel < ARPC_GAUSSIAN || p->kernel > ARPC_MATERN52) return ARPC_EINVAL;
-  if (p->prec < ARPC_FP64 || p->prec > ARPC_BF16) return ARPC_EINVAL;
+  if (p->prec < ARPC_FP64 || p->prec > ARPC_FP8) return ARPC_EINVAL;
   if (!std::isfinite(p->bandwidth) || !(p->bandwidth > 0.0)) return ARPC_EINVAL;
   if (p->max_rounds < 0) return ARPC_EINVAL;
   return ARPC_OK;
@@ -163,10 +169,10 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
                   (unsigned char*)(ws + l.Bm2), P, b, l.ncbt, l.grid};
     prof.begin(ARPC_KC_PREP);
     launch_prep_xp(s, acc, props, X, d, Xp, st);
-    launch_fused_prep(s, p.prec, fr, props, acc, H, st);
+    launch_fused_prep(s, gemm_prec(p.prec), fr, props, acc, H, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
-    launch_fused_round(s, p.prec, fr, st);
+    launch_fused_round(s, gemm_prec(p.prec), fr, st);
     prof.end();
   } else if (l.valu) {  // vector-unit kernels (cross-check path)
     prof.begin(ARPC_KC_PREP);
@@ -181,14 +187,14 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   } else {
     prof.begin(ARPC_KC_PREP);
     launch_prep_xp(s, acc, props, X, d, Xp, st);
-    launch_mfma_prep(s, p.prec, mr, st);
+    launch_mfma_prep(s, gemm_prec(p.prec), mr, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
     if (mr.C0) launch_dist(s, p.prec, mr, st);
-    launch_mfma_colgemm(s, p.prec, mr, st);
+    launch_mfma_colgemm(s, gemm_prec(p.prec), mr, st);
     prof.end();
     prof.begin(ARPC_KC_TRSM);
-    launch_mfma_trsm(s, p.prec, mr, st);
+    launch_mfma_trsm(s, gemm_prec(p.prec), mr, st);
     prof.end();
   }
   prof.begin(ARPC_KC_DIAG);
@@ -225,10 +231,12 @@ struct Job final : JobBase {
   int64_t known_k = 0, enqueued = 0;
   hipGraphExec_t round_graph = nullptr;
 
+  const double* Xin;   // the caller's points (X: the points every round reads)
+
   Job(const arpc_problem& p_, const double* X_, T* F_, int64_t* piv_, char* ws_, const Layout& l_,
       hipStream_t s_, const Unif& un_, RoundState* h_, Profiler* prof_)
-      : p(p_), X(X_), F(F_), pivots(piv_), ws(ws_), l(l_), s(s_), un(un_), kp(kparams_of(p_)), hstate(h_),
-        prof(prof_) {}
+      : p(p_), X(p_.prec == ARPC_FP8 ? (const double*)(ws_ + l_.Xq) : X_), F(F_), pivots(piv_), ws(ws_), l(l_),
+        s(s_), un(un_), kp(kparams_of(p_)), hstate(h_), prof(prof_), Xin(X_) {}
   ~Job() override {
     if (round_graph) (void)hipGraphExecDestroy(round_graph);
   }
@@ -238,6 +246,7 @@ struct Job final : JobBase {
     const int64_t nch = nchunks_of(p.N);
     HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
     prof->begin(ARPC_KC_INIT);
+    if (p.prec == ARPC_FP8) launch_round_e4m3(s, Xin, (double*)(ws + l.Xq), p.N * p.d);
     launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, p.N, (int)p.d, kp, st, nch);
     prof->end();
     HIPCHK(hipGetLastError());
@@ -320,7 +329,7 @@ struct Job final : JobBase {
       // row norm; the two-kernel path also writes and reads C
       double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0;
       const double es = (double)sizeof(T);
-      const double eb = p.prec == ARPC_FP64 ? 8.0 : (p.prec == ARPC_BF16 ? 2.0 : 4.0);
+      const double eb = p.prec == ARPC_FP64 ? 8.0 : (gemm_prec(p.prec) == ARPC_BF16 ? 2.0 : 4.0);
       const bool fused = l.ncbt > 0;
       for (int64_t r = 0; r < h.round; ++r) {
         const double sr = hist[r];

@@ -7,6 +7,8 @@ namespace arpc {
 
 void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_t N, int d, KParams kp,
                  RoundState* st, int64_t nchunks);
+// Xq = X with every coordinate rounded to FP8 e4m3 (the FP8 mode's points), n values.
+void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n);
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
                     int64_t N, int b, Unif un, RoundState* st, int64_t* props);
 // Partitions of the contraction index in the product F(S',:) F(S',:)^T of

@@ -28,6 +28,7 @@
 #include "arpc_mfma.h"
 
 #include <cstdlib>
+#include <type_traits>
 #include <utility>
 
 namespace arpc {
@@ -443,98 +444,179 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
 }
 
 // ------------------------------------------- kernel columns for large d
-// C0(row, c) = kappa(|x_row - x_c|^2) for c < s_r, column-major (ld N), when
-// d > XREG: the distances come from |x|^2 + |y|^2 - 2 x.y with x.y on the
-// matrix cores (16x16x4, FP64 in the FP64 mode, FP32 otherwise) instead of a
-// d-long difference loop per entry.  Where the expansion cancels (r^2 below
-// a fraction of |x|^2 + |y|^2: 2^-10 in FP64, 2^-6 in FP32) the entry is
-// recomputed by direct differences in FP64, so nearby and identical points
-// keep the direct-difference accuracy.  Wavefront w of workgroup (x, y) owns
-// rows 64 y + 16 w .. + 15 and columns 64 x .. + 63 (the column groups of a
-// row block are consecutive workgroups, so the rows are reused from L2).
-// Contraction slot j of lane group g in the step over dims 16 q .. 16 q + 15
-// is dim 16 q + 4 g + j, so each lane reads four consecutive coordinates of
-// each operand per four products.
-template <typename T>
+// C0(row, c) = kappa(|x_row - x_c|^2) for c < s_r, column-major (ld N), on
+// the two-kernel path when d > XREG and in the FP8 mode: the distances come
+// from |x|^2 + |y|^2 - 2 x.y with x.y on the matrix cores instead of a d-long
+// difference loop per entry.  DM selects the contraction: FP64 16x16x4 (FP64
+// mode), FP32 16x16x4 (FP32 and BF16 modes), or FP8 e4m3 16x16x32 with FP32
+// accumulation (FP8 mode: the points are already rounded to e4m3, so their
+// conversion is exact and so are the products and the squares in FP32).
+// Where the expansion cancels (r^2 below a fraction of |x|^2 + |y|^2: 2^-10
+// in FP64, 2^-6 otherwise) the entry is recomputed by direct differences in
+// FP64, so nearby and identical points keep the direct-difference accuracy.
+// Wavefront w of workgroup (x, y) owns rows 256 y + 64 w .. + 63 (four row
+// tiles) and columns 16 CT x .. + 16 CT - 1 (CT column tiles, shared by the
+// four wavefronts through L1).  In a step over 4 KL dims, lane (g, l16) holds
+// dims KL g .. KL g + KL - 1 of the step for row (or column) l16 of each
+// tile: KL = 4 consecutive values, one per 16x16x4 product, or 8, the eight
+// bytes of one FP8 product.
+enum { DIST_F64 = 0, DIST_F32 = 1, DIST_F8 = 2 };
+
+template <int DM>
+struct DistCfg {
+  typedef float T;
+  static constexpr int KL = DM == DIST_F8 ? 8 : 4;
+  static constexpr int CT = 4;
+};
+template <>
+struct DistCfg<DIST_F64> {
+  typedef double T;
+  static constexpr int KL = 4;
+  static constexpr int CT = 2;   // 2 x 4 FP64 accumulator tiles keep the wavefront within 256 registers
+};
+
+// eight values already on the e4m3 grid -> their FP8 codes, byte j = value j
+__device__ inline long pack_e4m3(const double (&v)[8]) {
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0], (float)v[1], 0, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2], (float)v[3], lo, true);
+  int hi = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4], (float)v[5], 0, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6], (float)v[7], hi, true);
+  return (long)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+template <int DM>
 __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int d, const double* __restrict__ Xp,
-                                              KParams kp, T* __restrict__ C0, int64_t N, const RoundState* st) {
+                                              KParams kp, KFast kf, void* __restrict__ C0v, int64_t N,
+                                              int ncb, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
+  typedef typename DistCfg<DM>::T T;
   typedef T V4 __attribute__((ext_vector_type(4)));
+  constexpr int KL = DistCfg<DM>::KL, CT = DistCfg<DM>::CT, KD = 4 * KL;
+  T* __restrict__ C0 = (T*)C0v;
   const int s = st->s_r;
-  const int c0 = blockIdx.x * 64;
+  // tile order: workgroup i runs on XCD i mod 8; each XCD takes a contiguous
+  // range of (row block, column block) tiles, column blocks fastest, so the
+  // column blocks of a row block share that XCD's L2 for the rows
+  // (the grid is 8 * per workgroups, so tile x per + j is workgroup 8 j + x)
+  const int64_t ntile = (N + 255) / 256 * ncb, per = (ntile + 7) / 8;
+  const int64_t t = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (t >= ntile) return;
+  const int64_t rb = t / ncb;
+  const int c0 = (int)(t % ncb) * 16 * CT;
   if (c0 >= s) return;
-  __shared__ T ynl[4][64];
+  __shared__ T ynl[4][16 * CT];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int64_t rowl = (int64_t)blockIdx.y * 64 + w * 16 + l16;   // this lane's row (B operand)
-  const double* xrow = X + (rowl < N ? rowl : N - 1) * d;
-  const double* xc[4];
+  const int64_t r0 = rb * 256 + w * 64;   // first row of this wavefront
+  const double* xr[4];
+  const double* xc[CT];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int c = c0 + 16 * ct + l16;                               // this lane's column (A operand)
-    xc[ct] = Xp + (int64_t)(c < s ? c : s - 1) * d;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t row = r0 + 16 * q + l16;
+    xr[q] = X + (row < N ? row : N - 1) * d;
   }
-  V4 acc[4];
-  T yp[4];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    acc[ct] = V4{0, 0, 0, 0};
-    yp[ct] = 0;
+  for (int q = 0; q < CT; ++q) {
+    const int c = c0 + 16 * q + l16;
+    xc[q] = Xp + (int64_t)(c < s ? c : s - 1) * d;
   }
-  T xp = 0;
-  for (int k0 = 0; k0 < d; k0 += 16) {
-    const int kb = k0 + 4 * g;
-    T bv[4];
+  V4 acc[CT][4];   // [column tile][row tile]
+  T xn[4], yn[CT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      bv[j] = kb + j < d ? (T)xrow[kb + j] : (T)0;
-      xp += bv[j] * bv[j];
-    }
+  for (int q = 0; q < 4; ++q) {
+    xn[q] = 0;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      T av[4];
+    for (int ct = 0; ct < CT; ++ct) acc[ct][q] = V4{0, 0, 0, 0};
+  }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        av[j] = kb + j < d ? (T)xc[ct][kb + j] : (T)0;
-        yp[ct] += av[j] * av[j];
+  for (int ct = 0; ct < CT; ++ct) yn[ct] = 0;
+  // one step over dims k0 .. k0 + KD - 1; only the last (ragged) step guards
+  auto step = [&](int k0, auto ragged) __attribute__((always_inline)) {
+    const int kb = k0 + KL * g;
+    double bv[4][KL], av[CT][KL];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < KL; ++j) {
+        if constexpr (decltype(ragged)::value) bv[q][j] = kb + j < d ? xr[q][kb + j] : 0.0;
+        else bv[q][j] = xr[q][kb + j];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if constexpr (sizeof(T) == 8) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[ct], 0, 0, 0);
-        else acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc[ct], 0, 0, 0);
+    for (int q = 0; q < CT; ++q)
+#pragma unroll
+      for (int j = 0; j < KL; ++j) {
+        if constexpr (decltype(ragged)::value) av[q][j] = kb + j < d ? xc[q][kb + j] : 0.0;
+        else av[q][j] = xc[q][kb + j];
       }
+#pragma unroll
+    for (int j = 0; j < KL; ++j) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xn[q] += (T)bv[q][j] * (T)bv[q][j];
+#pragma unroll
+      for (int q = 0; q < CT; ++q) yn[q] += (T)av[q][j] * (T)av[q][j];
     }
-  }
+    if constexpr (DM == DIST_F8) {
+      long ap[CT], bp[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bp[q] = pack_e4m3(bv[q]);
+#pragma unroll
+      for (int q = 0; q < CT; ++q) ap[q] = pack_e4m3(av[q]);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+          acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ap[ct], bp[rt], acc[ct][rt], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < KL; ++j)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            if constexpr (DM == DIST_F64)
+              acc[ct][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ct][j], bv[rt][j], acc[ct][rt], 0, 0, 0);
+            else
+              acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av[ct][j], (float)bv[rt][j], acc[ct][rt],
+                                                                 0, 0, 0);
+          }
+    }
+  };
+  const int dfull = d - d % KD;
+  for (int k0 = 0; k0 < dfull; k0 += KD) step(k0, std::false_type{});
+  if (dfull < d) step(dfull, std::true_type{});
   // norms: the four lane groups of a row (column) hold its partial sums
-  xp += __shfl_xor(xp, 16, 64);
-  xp += __shfl_xor(xp, 32, 64);
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    T y = yp[ct];
+  for (int q = 0; q < 4; ++q) {
+    xn[q] += __shfl_xor(xn[q], 16, 64);
+    xn[q] += __shfl_xor(xn[q], 32, 64);
+  }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    T y = yn[ct];
     y += __shfl_xor(y, 16, 64);
     y += __shfl_xor(y, 32, 64);
     if (g == 0) ynl[w][16 * ct + l16] = y;
   }
   __builtin_amdgcn_wave_barrier();
-  const T frac = sizeof(T) == 8 ? (T)0x1p-10 : (T)0x1p-6;
+  const T frac = DM == DIST_F64 ? (T)0x1p-10 : (T)0x1p-6;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct)
+  for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      // accumulator entry i of lane (g, l16): column 16 ct + m, row l16
-      const int m = sizeof(T) == 8 ? g + 4 * i : 4 * g + i;
-      const int c = c0 + 16 * ct + m;
-      if (c < s && rowl < N) {
-        const T yn = ynl[w][16 * ct + m];
-        T r2 = xp + yn - 2 * acc[ct][i];
-        double kap;
-        if (r2 < frac * (xp + yn)) {
-          const double r2d = sqdist(xrow, Xp + (int64_t)c * d, d);
-          kap = sizeof(T) == 8 ? kappa_r2(r2d, kp) : (double)kappa_r2_f32((float)r2d, kp);
-        } else {
-          kap = sizeof(T) == 8 ? kappa_r2((double)r2, kp) : (double)kappa_r2_f32((float)r2, kp);
+    for (int rt = 0; rt < 4; ++rt) {
+      const int64_t row = r0 + 16 * rt + l16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // accumulator entry i of lane (g, l16): column 16 ct + m, row l16 of the tile
+        const int m = DM == DIST_F64 ? g + 4 * i : 4 * g + i;
+        const int c = c0 + 16 * ct + m;
+        const T y = ynl[w][16 * ct + m];
+        T r2 = xn[rt] + y - 2 * acc[ct][rt][i];
+        if (__builtin_expect(r2 < frac * (xn[rt] + y), 0))   // cancellation: direct differences
+          r2 = (T)sqdist(xr[rt], Xp + (int64_t)(c < s ? c : s - 1) * d, d);
+        if (c < s && row < N) {
+          if constexpr (DM == DIST_F64) C0[(int64_t)c * N + row] = kappa_r2(r2, kp);
+          else C0[(int64_t)c * N + row] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
         }
-        C0[(int64_t)c * N + rowl] = (T)kap;
       }
     }
 }
@@ -707,11 +789,16 @@ void launch_mfma_prep(hipStream_t s, int prec, const MfmaRound& r, const RoundSt
 bool mfma_dist_contraction(int d) { return d > XREG; }
 
 void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
-  const dim3 grid((unsigned)((r.b + 63) / 64), (unsigned)((r.N + 63) / 64));
+  const int64_t nrb = (r.N + 255) / 256;
+  const KFast kf = kfast_of(r.kp);
+  const int ncb = prec == 0 ? (r.b + 31) / 32 : (r.b + 63) / 64;
+  const dim3 grid((unsigned)((nrb * ncb + 7) / 8 * 8));   // every XCD range complete (see k_dist)
   if (prec == 0)
-    hipLaunchKernelGGL(k_dist<double>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, (double*)r.C0, r.N, st);
+    hipLaunchKernelGGL(k_dist<DIST_F64>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, kf, r.C0, r.N, ncb, st);
+  else if (prec == 4)
+    hipLaunchKernelGGL(k_dist<DIST_F8>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, kf, r.C0, r.N, ncb, st);
   else
-    hipLaunchKernelGGL(k_dist<float>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, (float*)r.C0, r.N, st);
+    hipLaunchKernelGGL(k_dist<DIST_F32>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, kf, r.C0, r.N, ncb, st);
 }
 
 void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {

@@ -61,6 +61,28 @@ __global__ __launch_bounds__(CHUNK) void k_init(double* __restrict__ u, double* 
   if (threadIdx.x == 0) csum[blockIdx.x] = s;
 }
 
+// The FP8 mode's point set: each coordinate rounded to the nearest value of
+// the OCP FP8 e4m3 format (sign, 4 exponent bits with bias 7, 3 fraction
+// bits: normal values (1 + f/8) 2^e for e = -6 .. 8, subnormal steps of
+// 2^-9, largest finite value 448), ties to the even fraction, saturating to
+// +-448 beyond it; non-finite coordinates pass through unchanged (the
+// finiteness scan then reports them).  Stored as FP64 (exact).
+__device__ inline double round_e4m3(double x) {
+  if (!isfinite(x)) return x;
+  const double a = fabs(x);
+  if (a >= 448.0) return copysign(448.0, x);
+  int e;
+  (void)frexp(a, &e);                       // a in [2^(e-1), 2^e), or a = 0
+  const int ex = e - 1 < -6 ? -6 : e - 1;   // binade of a; subnormals share the spacing of 2^-6
+  return copysign(ldexp(rint(ldexp(a, 3 - ex)), ex - 3), x);   // 8 steps per binade, rint: ties to even
+}
+
+__global__ __launch_bounds__(256) void k_round_e4m3(const double* __restrict__ X, double* __restrict__ Xq,
+                                                    int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    Xq[i] = round_e4m3(X[i]);
+}
+
 // trace(A) from the chunk sums, and the initial round state.
 __global__ __launch_bounds__(1024) void k_init_state(const double* __restrict__ csum, int64_t nchunks,
                                                      RoundState* st) {
@@ -890,6 +912,11 @@ __global__ __launch_bounds__(1024) void k_trace(const double* __restrict__ csum,
 // ------------------------------------------------------------------ launchers
 void launch_trace(hipStream_t s, const double* csum, int64_t nchunks, double* out) {
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(1024), 0, s, csum, nchunks, out);
+}
+
+void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n) {
+  const int64_t blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_round_e4m3, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, X, Xq, n);
 }
 
 void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_t N, int d, KParams kp,

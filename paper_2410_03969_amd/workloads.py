@@ -28,8 +28,8 @@ GAUSSIAN, LAPLACE_L2, MATERN32, MATERN52 = 0, 1, 2, 3
 KERNEL_NAMES = {GAUSSIAN: "gaussian", LAPLACE_L2: "laplace_l2",
                 MATERN32: "matern32", MATERN52: "matern52"}
 
-FP64, FP32, BF16X3, BF16 = 0, 1, 2, 3
-PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16: "bf16"}
+FP64, FP32, BF16X3, BF16, FP8 = 0, 1, 2, 3, 4
+PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16: "bf16", FP8: "fp8"}
 
 
 @dataclass(frozen=True)

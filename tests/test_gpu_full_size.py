@@ -7,14 +7,15 @@ At these sizes the factor stays on the device.  Checks:
 - sampled rows of F against the FP64 oracle's factor of the same pivots
   (F = A(:,S) chol(A(S,S))^{-T}, computed one row at a time on the host);
 - properties that hold at any size: |F|_F^2 <= tr A, and the trace error of a
-  reduced-precision run within 1.05x of the FP64 run's (mixture workload).
+  reduced-precision run within 1.05x of the FP64 run's (mixture workload);
+- the FP8 mode against the oracle's factor of the e4m3-rounded points.
 """
 import sys
 
 import numpy as np
 import pytest
 
-from oracle import PointsAccess, factor_from_pivots
+from oracle import PointsAccess, factor_from_pivots, round_e4m3
 from paper_2410_03969_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -82,3 +83,9 @@ def test_sparse_high_dim_full_size():
     out = _run(X, prob.with_(prec=W.BF16X3))
     te = _check(X, prob.with_(prec=W.BF16X3), out, rows, 2 * prob.b, 2e-3)
     print(f"  trace error ratio bf16x3 / fp64 = {te / te64:.5f}", flush=True)
+    del out
+    # FP8 mode: the factor of the e4m3-rounded points (its own oracle), and the
+    # trace error that rounding costs against the FP64 run
+    out8 = _run(X, prob.with_(prec=W.FP8))
+    te8 = _check(round_e4m3(X), prob.with_(prec=W.FP8), out8, rows, 2 * prob.b, 5e-2)
+    print(f"  trace error ratio fp8 / fp64 = {te8 / te64:.5f}", flush=True)

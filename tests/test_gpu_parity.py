@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import (PointsAccess, array_stream, factor_from_pivots, philox_stream,
-                    rpc_accel)
+                    round_e4m3, rpc_accel)
 from paper_2410_03969_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -141,7 +141,7 @@ def simulate_identity(N, k, b, stream):
     return piv
 
 
-ALL_PRECS = [W.FP64, W.FP32, W.BF16X3, W.BF16]
+ALL_PRECS = [W.FP64, W.FP32, W.BF16X3, W.BF16, W.FP8]
 
 
 @pytest.mark.parametrize("prec", ALL_PRECS)
@@ -323,3 +323,31 @@ def test_reduced_precision_trace_error(prec):
     nym = nystrom_err(acc, pivm[:outm["stats"]["k_out"]]).sum() / trA
     print(f"prec={prec} trace err F: {tem:.6e} vs fp64 {te64:.6e}; nystrom {nym:.6e} vs {ny64:.6e}")
     assert tem <= 1.05 * te64 and nym <= 1.05 * ny64
+
+
+@pytest.mark.parametrize("d", [24, 40])
+def test_fp8_mode_factors_the_rounded_points(d):
+    """The FP8 mode factors the kernel matrix of the points rounded to e4m3:
+    its factor matches the FP64 factor of its pivots on round_e4m3(X) to the
+    BF16 update's accuracy, and is clearly further from that of the unrounded
+    points.  Coordinates reach (240, 448] (OCP e4m3 only) and beyond 448
+    (saturation); d = 24 and 40 leave a ragged 32-wide contraction step."""
+    rng = np.random.default_rng(d)
+    N = 4000
+    X = 100.0 * rng.standard_normal((N, d))
+    X[0, 0], X[1, 1], X[2, 2] = 1000.0, -460.0, 300.0
+    prob = W.Problem(N=N, d=d, k=300, b=60, kernel=W.GAUSSIAN, sigma=60.0 * np.sqrt(d), seed=d, prec=W.FP8)
+    F, piv, out = gpu_factor(X, prob)
+    k_out = out["stats"]["k_out"]
+    assert out["stats"]["fused"] == 0
+    assert k_out == prob.k and len(set(piv.tolist())) == k_out
+    rows = np.concatenate([np.arange(8), rng.choice(N, 200, replace=False), np.arange(N - 8, N)])
+    ncols = 120
+    Xq = round_e4m3(X)
+    assert np.count_nonzero(np.abs(Xq) > 240) > 50
+    ref_q = factor_from_pivots(PointsAccess(Xq, prob.kernel, prob.sigma), piv[:ncols], rows=rows)
+    ref_x = factor_from_pivots(PointsAccess(X, prob.kernel, prob.sigma), piv[:ncols], rows=rows)
+    err_q = np.linalg.norm(F[rows, :ncols] - ref_q) / np.linalg.norm(ref_q)
+    err_x = np.linalg.norm(F[rows, :ncols] - ref_x) / np.linalg.norm(ref_x)
+    print(f"fp8 d={d}: relF vs rounded points {err_q:.3e}, vs unrounded {err_x:.3e}")
+    assert err_q < 2e-2 and err_q < 0.25 * err_x
