@@ -454,44 +454,47 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
 // Where the expansion cancels (r^2 below a fraction of |x|^2 + |y|^2: 2^-10
 // in FP64, 2^-6 otherwise) the entry is recomputed by direct differences in
 // FP64, so nearby and identical points keep the direct-difference accuracy.
-// Wavefront w of workgroup (x, y) owns rows 256 y + 64 w .. + 63 (four row
-// tiles) and columns 16 CT x .. + 16 CT - 1 (CT column tiles, shared by the
-// four wavefronts through L1).  In a step over 4 KL dims, lane (g, l16) holds
-// dims KL g .. KL g + KL - 1 of the step for row (or column) l16 of each
-// tile: KL = 4 consecutive values, one per 16x16x4 product, or 8, the eight
-// bytes of one FP8 product.
+//
+// A workgroup owns 256 rows and 16 CT columns.  The dims go in chunks of DC:
+// the workgroup stages the chunk of its rows and columns into LDS in the
+// operand format with whole-line loads (LPR lanes per row, four FP64 values
+// each; the squares are summed into the norms on the way), then wavefront w
+// multiplies rows 64 w .. 64 w + 63 (four row tiles) by all column tiles.
+// Operand slots: FP8, byte j of lane group g is dim 8 g + j of the chunk;
+// 16x16x4, slot j of lane group g in dim group q is dim 16 q + 4 g + j.
 enum { DIST_F64 = 0, DIST_F32 = 1, DIST_F8 = 2 };
 
 template <int DM>
-struct DistCfg {
+struct DistCfg {   // FP32
+  typedef float T;      // accumulator and norms
+  typedef float Op;     // operand in LDS
+  static constexpr int CT = 4, DC = 32, RS = 36;   // RS: LDS row stride in Op (32 + 4 of padding)
+};
+template <>
+struct DistCfg<DIST_F8> {
   typedef float T;
-  static constexpr int KL = DM == DIST_F8 ? 8 : 4;
-  static constexpr int CT = 4;
+  typedef unsigned char Op;
+  static constexpr int CT = 4, DC = 32, RS = 32;
 };
 template <>
 struct DistCfg<DIST_F64> {
   typedef double T;
-  static constexpr int KL = 4;
-  static constexpr int CT = 2;   // 2 x 4 FP64 accumulator tiles keep the wavefront within 256 registers
+  typedef double Op;
+  static constexpr int CT = 2, DC = 16, RS = 18;
 };
-
-// eight values already on the e4m3 grid -> their FP8 codes, byte j = value j
-__device__ inline long pack_e4m3(const double (&v)[8]) {
-  int lo = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0], (float)v[1], 0, false);
-  lo = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2], (float)v[3], lo, true);
-  int hi = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4], (float)v[5], 0, false);
-  hi = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6], (float)v[7], hi, true);
-  return (long)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
-}
 
 template <int DM>
 __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int d, const double* __restrict__ Xp,
                                               KParams kp, KFast kf, void* __restrict__ C0v, int64_t N,
                                               int ncb, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
-  typedef typename DistCfg<DM>::T T;
+  typedef DistCfg<DM> Cfg;
+  typedef typename Cfg::T T;
+  typedef typename Cfg::Op Op;
   typedef T V4 __attribute__((ext_vector_type(4)));
-  constexpr int KL = DistCfg<DM>::KL, CT = DistCfg<DM>::CT, KD = 4 * KL;
+  constexpr int CT = Cfg::CT, DC = Cfg::DC, RS = Cfg::RS, NC = 16 * CT;
+  constexpr int LPR = DC / 4, RPP = 256 / LPR;          // staging: lanes per row, rows per pass
+  constexpr int NPR = 256 / RPP, NPC = (NC + RPP - 1) / RPP;
   T* __restrict__ C0 = (T*)C0v;
   const int s = st->s_r;
   // tile order: workgroup i runs on XCD i mod 8; each XCD takes a contiguous
@@ -502,65 +505,84 @@ __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int 
   const int64_t t = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (t >= ntile) return;
   const int64_t rb = t / ncb;
-  const int c0 = (int)(t % ncb) * 16 * CT;
+  const int c0 = (int)(t % ncb) * NC;
   if (c0 >= s) return;
-  __shared__ T ynl[4][16 * CT];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ __attribute__((aligned(16))) Op rowsL[256 * RS];
+  __shared__ __attribute__((aligned(16))) Op colsL[NC * RS];
+  __shared__ T xnl[256], ynl[NC];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int64_t r0 = rb * 256 + w * 64;   // first row of this wavefront
-  const double* xr[4];
-  const double* xc[CT];
+  const int sl = tid % LPR, sr = tid / LPR;             // staging lane: dims 4 sl .. + 3 of row sr (+ RPP p)
+  const int64_t r0 = rb * 256;
+  const double* sx[NPR];
+  const double* sc[NPC];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t row = r0 + 16 * q + l16;
-    xr[q] = X + (row < N ? row : N - 1) * d;
+  for (int p = 0; p < NPR; ++p) {
+    const int64_t row = r0 + RPP * p + sr;
+    sx[p] = X + (row < N ? row : N - 1) * d + 4 * sl;
   }
 #pragma unroll
-  for (int q = 0; q < CT; ++q) {
-    const int c = c0 + 16 * q + l16;
-    xc[q] = Xp + (int64_t)(c < s ? c : s - 1) * d;
+  for (int p = 0; p < NPC; ++p) {
+    const int c = c0 + RPP * p + sr;
+    sc[p] = Xp + (int64_t)(c < s ? c : s - 1) * d + 4 * sl;
   }
+  T nx[NPR], ny[NPC];
+#pragma unroll
+  for (int p = 0; p < NPR; ++p) nx[p] = 0;
+#pragma unroll
+  for (int p = 0; p < NPC; ++p) ny[p] = 0;
   V4 acc[CT][4];   // [column tile][row tile]
-  T xn[4], yn[CT];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    xn[q] = 0;
+  for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[ct][q] = V4{0, 0, 0, 0};
-  }
+    for (int q = 0; q < 4; ++q) acc[ct][q] = V4{0, 0, 0, 0};
+
+  // four values -> operand format at LDS element e of buf; squares into nrm
+  auto put = [&](Op* buf, int e, const double (&v)[4], T& nrm) __attribute__((always_inline)) {
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) yn[ct] = 0;
-  // one step over dims k0 .. k0 + KD - 1; only the last (ragged) step guards
-  auto step = [&](int k0, auto ragged) __attribute__((always_inline)) {
-    const int kb = k0 + KL * g;
-    double bv[4][KL], av[CT][KL];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int j = 0; j < KL; ++j) {
-        if constexpr (decltype(ragged)::value) bv[q][j] = kb + j < d ? xr[q][kb + j] : 0.0;
-        else bv[q][j] = xr[q][kb + j];
-      }
-#pragma unroll
-    for (int q = 0; q < CT; ++q)
-#pragma unroll
-      for (int j = 0; j < KL; ++j) {
-        if constexpr (decltype(ragged)::value) av[q][j] = kb + j < d ? xc[q][kb + j] : 0.0;
-        else av[q][j] = xc[q][kb + j];
-      }
-#pragma unroll
-    for (int j = 0; j < KL; ++j) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xn[q] += (T)bv[q][j] * (T)bv[q][j];
-#pragma unroll
-      for (int q = 0; q < CT; ++q) yn[q] += (T)av[q][j] * (T)av[q][j];
+    for (int j = 0; j < 4; ++j) nrm += (T)v[j] * (T)v[j];
+    if constexpr (DM == DIST_F8) {
+      int pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0], (float)v[1], 0, false);
+      pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2], (float)v[3], pk, true);
+      *(int*)(buf + e) = pk;
+    } else if constexpr (DM == DIST_F32) {
+      *(float4*)(buf + e) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+      *(double2*)(buf + e) = double2{v[0], v[1]};
+      *(double2*)(buf + e + 2) = double2{v[2], v[3]};
     }
+  };
+  // one chunk of dims k0 .. k0 + DC - 1; only the last (ragged) chunk guards
+  auto chunk = [&](int k0, auto ragged) __attribute__((always_inline)) {
+    constexpr bool RG = decltype(ragged)::value;
+    double vr[NPR][4], vc[NPC][4];
+#pragma unroll
+    for (int p = 0; p < NPR; ++p)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (RG) vr[p][j] = k0 + 4 * sl + j < d ? sx[p][k0 + j] : 0.0;
+        else vr[p][j] = sx[p][k0 + j];
+      }
+#pragma unroll
+    for (int p = 0; p < NPC; ++p)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (RG) vc[p][j] = k0 + 4 * sl + j < d ? sc[p][k0 + j] : 0.0;
+        else vc[p][j] = sc[p][k0 + j];
+      }
+    __syncthreads();   // the previous chunk's operands are consumed
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) put(rowsL, (RPP * p + sr) * RS + 4 * sl, vr[p], nx[p]);
+#pragma unroll
+    for (int p = 0; p < NPC; ++p)
+      if (RPP * p + sr < NC) put(colsL, (RPP * p + sr) * RS + 4 * sl, vc[p], ny[p]);
+    __syncthreads();
     if constexpr (DM == DIST_F8) {
       long ap[CT], bp[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bp[q] = pack_e4m3(bv[q]);
+      for (int q = 0; q < 4; ++q) bp[q] = *(const long*)(rowsL + (64 * w + 16 * q + l16) * RS + 8 * g);
 #pragma unroll
-      for (int q = 0; q < CT; ++q) ap[q] = pack_e4m3(av[q]);
+      for (int q = 0; q < CT; ++q) ap[q] = *(const long*)(colsL + (16 * q + l16) * RS + 8 * g);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
@@ -568,57 +590,72 @@ __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int 
           acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ap[ct], bp[rt], acc[ct][rt], 0, 0, 0);
     } else {
 #pragma unroll
-      for (int j = 0; j < KL; ++j)
+      for (int q = 0; q < DC / 16; ++q) {
+        Op av[CT][4], bv[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bv[rt][j] = rowsL[(64 * w + 16 * rt + l16) * RS + 16 * q + 4 * g + j];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            if constexpr (DM == DIST_F64)
-              acc[ct][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ct][j], bv[rt][j], acc[ct][rt], 0, 0, 0);
-            else
-              acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av[ct][j], (float)bv[rt][j], acc[ct][rt],
-                                                                 0, 0, 0);
-          }
+          for (int j = 0; j < 4; ++j) av[ct][j] = colsL[(16 * ct + l16) * RS + 16 * q + 4 * g + j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+              if constexpr (DM == DIST_F64)
+                acc[ct][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ct][j], bv[rt][j], acc[ct][rt], 0, 0, 0);
+              else
+                acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ct][j], bv[rt][j], acc[ct][rt], 0, 0, 0);
+            }
+      }
     }
   };
-  const int dfull = d - d % KD;
-  for (int k0 = 0; k0 < dfull; k0 += KD) step(k0, std::false_type{});
-  if (dfull < d) step(dfull, std::true_type{});
-  // norms: the four lane groups of a row (column) hold its partial sums
+  const int dfull = d - d % DC;
+  for (int k0 = 0; k0 < dfull; k0 += DC) chunk(k0, std::false_type{});
+  if (dfull < d) chunk(dfull, std::true_type{});
+  // norms: the LPR staging lanes of a row hold its partial sums
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    xn[q] += __shfl_xor(xn[q], 16, 64);
-    xn[q] += __shfl_xor(xn[q], 32, 64);
-  }
+  for (int m = 1; m < LPR; m <<= 1) {
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    T y = yn[ct];
-    y += __shfl_xor(y, 16, 64);
-    y += __shfl_xor(y, 32, 64);
-    if (g == 0) ynl[w][16 * ct + l16] = y;
+    for (int p = 0; p < NPR; ++p) nx[p] += __shfl_xor(nx[p], m, 64);
+#pragma unroll
+    for (int p = 0; p < NPC; ++p) ny[p] += __shfl_xor(ny[p], m, 64);
   }
-  __builtin_amdgcn_wave_barrier();
+  if (sl == 0) {
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) xnl[RPP * p + sr] = nx[p];
+#pragma unroll
+    for (int p = 0; p < NPC; ++p)
+      if (RPP * p + sr < NC) ynl[RPP * p + sr] = ny[p];
+  }
+  __syncthreads();
   const T frac = DM == DIST_F64 ? (T)0x1p-10 : (T)0x1p-6;
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct)
+  for (int rt = 0; rt < 4; ++rt) {
+    const int rl = 64 * w + 16 * rt + l16;
+    const int64_t row = r0 + rl;
+    const T xn = xnl[rl];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const int64_t row = r0 + 16 * rt + l16;
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         // accumulator entry i of lane (g, l16): column 16 ct + m, row l16 of the tile
         const int m = DM == DIST_F64 ? g + 4 * i : 4 * g + i;
         const int c = c0 + 16 * ct + m;
-        const T y = ynl[w][16 * ct + m];
-        T r2 = xn[rt] + y - 2 * acc[ct][rt][i];
-        if (__builtin_expect(r2 < frac * (xn[rt] + y), 0))   // cancellation: direct differences
-          r2 = (T)sqdist(xr[rt], Xp + (int64_t)(c < s ? c : s - 1) * d, d);
+        const T y = ynl[16 * ct + m];
+        T r2 = xn + y - 2 * acc[ct][rt][i];
+        if (__builtin_expect(r2 < frac * (xn + y), 0))   // cancellation: direct differences
+          r2 = (T)sqdist(X + (row < N ? row : N - 1) * d, Xp + (int64_t)(c < s ? c : s - 1) * d, d);
         if (c < s && row < N) {
           if constexpr (DM == DIST_F64) C0[(int64_t)c * N + row] = kappa_r2(r2, kp);
           else C0[(int64_t)c * N + row] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
         }
       }
-    }
+  }
 }
 
 // ------------------------------------------ small operands in chunk layout
