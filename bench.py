@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="bf16", choices=sorted(PREC_BY_NAME))
     ap.add_argument("--workload", default="mixture", choices=["mixture", "laplace", "small", "sparse_hd"])
+    ap.add_argument("--method", default="accel", choices=sorted(W.METHOD_NAMES.values()),
+                    help="pivot rule: accel (Alg. 2, the method) or block (Alg. 7, a baseline)")
+    ap.add_argument("--b", type=int, default=0,
+                    help="block size instead of the workload's (1 with --method accel: simple RPCholesky)")
     ap.add_argument("--cpu-rounds", type=int, default=3,
                     help="rounds of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-compare-fp64", action="store_true",
@@ -235,6 +239,11 @@ def main():
     X, prob = gen()
     prec = PREC_BY_NAME[args.prec]
     prob = prob.with_(prec=prec)
+    method = {v: k for k, v in W.METHOD_NAMES.items()}[args.method]
+    variant = args.workload
+    if args.b > 0 or method != W.ACCEL:
+        prob = prob.with_(b=args.b if args.b > 0 else prob.b, method=method)
+        variant = f"{args.workload}_{args.method}_b{prob.b}"   # no counter record for a variant
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     pr = B.make_problem(prob)
@@ -286,7 +295,7 @@ def main():
     agg["launches"] = {c: sum(r["launches"][c] for r in runs) for c in B.KERNEL_CLASSES}
     for key in ("flops_colgemm", "bytes_colgemm", "flops_trsm", "bytes_trsm"):
         agg[key] = sum(r[key] for r in runs)
-    roof, roof_alt = gemm_roofline(agg, prec, args.workload)
+    roof, roof_alt = gemm_roofline(agg, prec, variant)
 
     out = {
         "metric": "pivots/s", "value": round(k_out / elapsed, 2), "unit": "pivots/s",
@@ -295,8 +304,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": W.PREC_NAMES[prec], "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={prob.N} d={prob.d} "
                                f"{W.KERNEL_NAMES[prob.kernel]} sigma={prob.sigma} "
-                               f"k={prob.k} b={prob.b}",
-                   "N": prob.N, "d": prob.d, "k": prob.k, "b": prob.b,
+                               f"k={prob.k} b={prob.b}"
+                               + ("" if method == W.ACCEL else f" method={args.method}"),
+                   "N": prob.N, "d": prob.d, "k": prob.k, "b": prob.b, "method": args.method,
                    "parallelism": "single GPU"},
         "roofline": roof, "roofline_alt": roof_alt,
         "rounds": last["rounds"], "acceptance": round(last["k_out"] / last["proposals"], 4),
@@ -311,7 +321,7 @@ def main():
         out["fp64_compare"] = {"ms": round(out64["stats"]["ms_total"], 2), "trace_error_F": te64,
                                "ratio": trace_err / te64 if te64 > 0 else None}
         del out64, F64
-    if args.cpu_rounds > 0:
+    if args.cpu_rounds > 0 and method == W.ACCEL:
         out["cpu_baseline"] = cpu_baseline(X, prob, args.cpu_rounds)
     print(json.dumps(out), flush=True)
 

@@ -62,6 +62,17 @@ typedef enum arpc_prec {
                        the rounded copy (8 N d bytes). */
 } arpc_prec;
 
+/* The rule that picks each round's pivots from its b proposals. */
+typedef enum arpc_method {
+  ARPC_ACCEL = 0,   /* accelerated RPCholesky (Alg. 2): RejectionSampleSubmatrix (Alg. 1) keeps
+                       proposal i with probability h_ii / u_i.  With b = 1 every proposal with a
+                       positive residual is kept: simple RPCholesky (Alg. 6, Section 1.3.1). */
+  ARPC_BLOCK = 1    /* block RPCholesky (Alg. 7, Section 1.3.2): every distinct proposal is kept
+                       (the test of Alg. 1 with V = 0, so a proposal whose residual is not
+                       positive is still skipped).  A baseline: its columns can be wasted on
+                       near-duplicate proposals. */
+} arpc_method;
+
 typedef struct arpc_problem {
   int64_t N;          /* number of points, 1 <= N <= 2^31 - 1 */
   int64_t d;          /* dimension, 1 <= d <= 4096 */
@@ -72,6 +83,8 @@ typedef struct arpc_problem {
   double bandwidth;   /* sigma (length scale), finite and > 0 */
   uint64_t seed;      /* key of the uniform stream */
   int64_t max_rounds; /* 0: run until k pivots; > 0: stop after this many rounds */
+  int32_t method;     /* arpc_method */
+  int32_t reserved;   /* must be 0 */
 } arpc_problem;
 
 enum {

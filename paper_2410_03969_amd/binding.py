@@ -29,7 +29,8 @@ EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_facto
 class ArpcProblem(C.Structure):
     _fields_ = [("N", C.c_int64), ("d", C.c_int64), ("k", C.c_int64), ("b", C.c_int64),
                 ("kernel", C.c_int32), ("prec", C.c_int32), ("bandwidth", C.c_double),
-                ("seed", C.c_uint64), ("max_rounds", C.c_int64)]
+                ("seed", C.c_uint64), ("max_rounds", C.c_int64), ("method", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ArpcStats(C.Structure):
@@ -109,7 +110,8 @@ def make_problem(p) -> ArpcProblem:
     """From a workloads.Problem (or any object with the same fields)."""
     return ArpcProblem(N=p.N, d=p.d, k=p.k, b=p.b, kernel=p.kernel, prec=p.prec,
                        bandwidth=float(p.sigma), seed=int(p.seed),
-                       max_rounds=int(getattr(p, "max_rounds", 0) or 0))
+                       max_rounds=int(getattr(p, "max_rounds", 0) or 0),
+                       method=int(getattr(p, "method", 0) or 0), reserved=0)
 
 
 def arpc_status_str(status: int) -> str:

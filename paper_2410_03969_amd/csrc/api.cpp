@@ -119,6 +119,8 @@ arpc_status validate(const arpc_problem* p) {
   if (p->prec < ARPC_FP64 || p->prec > ARPC_FP8) return ARPC_EINVAL;
   if (!std::isfinite(p->bandwidth) || !(p->bandwidth > 0.0)) return ARPC_EINVAL;
   if (p->max_rounds < 0) return ARPC_EINVAL;
+  if (p->method != ARPC_ACCEL && p->method != ARPC_BLOCK) return ARPC_EINVAL;
+  if (p->reserved != 0) return ARPC_EINVAL;
   return ARPC_OK;
 }
 
@@ -162,7 +164,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, (double*)(ws + l.Hp), H, st);
   prof.end();
   prof.begin(ARPC_KC_REJECT);
-  launch_reject(s, H, b, props, un, st, acc, pivots, u, k);
+  launch_reject(s, H, b, props, un, st, acc, pivots, u, k, p.method == ARPC_BLOCK);
   prof.end();
   if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
     FusedRound fr{F, ws + l.Fb, (k + 31) / 32, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1),

@@ -19,9 +19,10 @@ template <typename T>
 void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
                    const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* Hp, double* H,
                    const RoundState* st);
-// RejectionSampleSubmatrix; L(T,T) is left in H (see LFactor).
+// RejectionSampleSubmatrix (keep_all: block RPCholesky, every distinct proposal
+// with a positive residual); L(T,T) is left in H (see LFactor).
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
-                   int32_t* acc, int64_t* pivots, double* u, int64_t kmax);
+                   int32_t* acc, int64_t* pivots, double* u, int64_t kmax, bool keep_all);
 template <typename T>
 void launch_prep(hipStream_t s, const double* Fs, int64_t ldf, const int32_t* acc, const int64_t* props,
                  const double* X, int d, T* Bt, int ldb, double* Xp, const double* H, int b, T* Bt2,

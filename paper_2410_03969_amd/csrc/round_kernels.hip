@@ -287,7 +287,8 @@ __global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X,
 // global memory.
 // Rules beyond the printed test u_i * V < h_ii: a proposal equal to one
 // already accepted in this round is rejected, and at most k - k_r proposals are
-// accepted.  Outputs: accepted local indices, the new pivots, u = 0 at the
+// accepted.  keep_all runs block RPCholesky (Alg. 7) instead: every test takes
+// V = 0, so each distinct proposal with a positive residual is kept.  Outputs: accepted local indices, the new pivots, u = 0 at the
 // new pivots, and the lower Cholesky factor L of H(T,T) left in H: the scaled
 // column of accepted proposal i is column i of H (rows at and below i), so
 // L(a, c) = H(acc[a], acc[c]) (read through LFactor).
@@ -301,7 +302,7 @@ template <class Store>
 __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, Unif un,
                             RoundState* st, int32_t* __restrict__ acc_out,
                             int64_t* __restrict__ pivots, double* __restrict__ u, int64_t kmax,
-                            unsigned char* tk, int* dec, short* accl) {
+                            int keep_all, unsigned char* tk, int* dec, short* accl) {
   const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
   const int64_t kr = st->k_r;
   const int64_t round = st->round;
@@ -310,7 +311,7 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
   int prev = -1;
   if (tid < b) {
     uloc = S.at(tid, tid);
-    V = stream_uniform(un, 2 * (int64_t)b * round + b + tid);
+    V = keep_all ? 0.0 : stream_uniform(un, 2 * (int64_t)b * round + b + tid);
     const int64_t me = props[tid];
     for (int q = tid - 1; q >= 0; --q)
       if (props[q] == me) { prev = q; break; }
@@ -398,7 +399,8 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
                                                                    const int64_t* __restrict__ props, Unif un,
                                                                    RoundState* st, int32_t* __restrict__ acc_out,
                                                                    int64_t* __restrict__ pivots,
-                                                                   double* __restrict__ u, int64_t kmax) {
+                                                                   double* __restrict__ u, int64_t kmax,
+                                                                   int keep_all) {
   if (st->status != ST_RUNNING) return;
   constexpr int BM = GT ? REJECT_G_BMAX : REJECT_T_BMAX;
   __shared__ __attribute__((aligned(16))) double Q[2][BM][QS];  // block columns
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
   const int ntile = nbk * (nbk + 1) / 2;
 
   if (tid < b) {
-    uv[tid] = H[(int64_t)tid * b + tid] * stream_uniform(un, 2 * (int64_t)b * round + b + tid);
+    uv[tid] = keep_all ? 0.0 : H[(int64_t)tid * b + tid] * stream_uniform(un, 2 * (int64_t)b * round + b + tid);
     pr[tid] = props[tid];
     tk[tid] = 0;
   }
@@ -800,13 +802,13 @@ __global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, 
                                                         const int64_t* __restrict__ props, Unif un,
                                                         RoundState* st, int32_t* __restrict__ acc_out,
                                                         int64_t* __restrict__ pivots,
-                                                        double* __restrict__ u, int64_t kmax) {
+                                                        double* __restrict__ u, int64_t kmax, int keep_all) {
   if (st->status != ST_RUNNING) return;
   __shared__ unsigned char tk[BMAX];
   __shared__ short accl[BMAX];
   __shared__ int dec[2];
   FullGlobal S{H, b};
-  reject_body(S, b, props, un, st, acc_out, pivots, u, kmax, tk, dec, accl);
+  reject_body(S, b, props, un, st, acc_out, pivots, u, kmax, keep_all, tk, dec, accl);
 }
 
 // --------------------------------------------------------- update preparation
@@ -959,15 +961,16 @@ template void launch_gather<float>(hipStream_t, const float*, int64_t, const dou
                                    const RoundState*);
 
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
-                   int32_t* acc, int64_t* pivots, double* u, int64_t kmax) {
+                   int32_t* acc, int64_t* pivots, double* u, int64_t kmax, bool keep_all) {
+  const int ka = keep_all ? 1 : 0;
   if (b <= REJECT_T_BMAX)
     hipLaunchKernelGGL(k_reject_tiled<false>, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc,
-                       pivots, u, kmax);
+                       pivots, u, kmax, ka);
   else if (b <= REJECT_G_BMAX)
     hipLaunchKernelGGL(k_reject_tiled<true>, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc,
-                       pivots, u, kmax);
+                       pivots, u, kmax, ka);
   else
-    hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, acc, pivots, u, kmax);
+    hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, acc, pivots, u, kmax, ka);
 }
 
 template <typename T>

@@ -29,6 +29,8 @@ KERNEL_NAMES = {GAUSSIAN: "gaussian", LAPLACE_L2: "laplace_l2",
                 MATERN32: "matern32", MATERN52: "matern52"}
 
 FP64, FP32, BF16X3, BF16, FP8 = 0, 1, 2, 3, 4
+ACCEL, BLOCK = 0, 1   # pivot rule: accelerated (Alg. 2; b = 1 is simple RPCholesky) or block (Alg. 7)
+METHOD_NAMES = {ACCEL: "accel", BLOCK: "block"}
 PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16: "bf16", FP8: "fp8"}
 
 
@@ -45,6 +47,7 @@ class Problem:
     seed: int = 0
     prec: int = FP64
     max_rounds: int = 0  # 0: run until k pivots are held
+    method: int = ACCEL
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)

@@ -84,10 +84,23 @@ def test_workspace_size_grows_with_problem():
 
 @pytest.mark.parametrize("bad", [dict(N=0), dict(d=0), dict(k=0), dict(k=1001), dict(b=0),
                                  dict(b=1025), dict(sigma=0.0), dict(sigma=float("nan")),
-                                 dict(sigma=float("inf")), dict(kernel=7), dict(prec=9)])
+                                 dict(sigma=float("inf")), dict(kernel=7), dict(prec=9), dict(prec=5),
+                                 dict(method=2), dict(method=-1)])
 def test_invalid_problems_rejected(bad):
     with pytest.raises(ValueError):
         B.arpc_workspace_size(_prob(**bad))
+
+
+def test_reserved_field_must_be_zero():
+    p = _prob()
+    p.reserved = 1
+    with pytest.raises(ValueError):
+        B.arpc_workspace_size(p)
+
+
+def test_fp8_workspace_holds_the_rounded_points():
+    extra = B.arpc_workspace_size(_prob(prec=W.FP8, d=24)) - B.arpc_workspace_size(_prob(prec=W.BF16, d=24))
+    assert extra >= 8 * 1000 * 24
 
 
 def test_factor_rejects_null_pointers_without_gpu_work():
