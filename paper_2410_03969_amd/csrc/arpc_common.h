@@ -161,24 +161,25 @@ struct LFactor {
   __device__ double at(int a, int c) const { return H[(int64_t)acc[c] * b + acc[a]]; }
 };
 
-// Column c of the inverse of the s x s lower-triangular L, s <= 256, in one
+// Column c of the inverse of the s x s lower-triangular L, s <= 64 M, in one
 // wavefront by column-oriented forward substitution: lane l keeps rows l,
-// l + 64, l + 128, l + 192 of the right-hand side e_c, which becomes column c
-// of L^{-1}.  Column t of L (gathered from one column of H) does not depend
-// on the solution, so it is loaded P steps ahead (an L2 round trip per step
-// otherwise); the dependency chain is one readlane and a few FMAs per step.
-// Rows outside [c, s) are zero.
-__device__ inline void linv_column(const LFactor& L, int s, int c, int lane, double (&r)[4]) {
+// l + 64, ..., l + 64 (M - 1) of the right-hand side e_c, which becomes
+// column c of L^{-1}.  Column t of L (gathered from one column of H) does not
+// depend on the solution, so it is loaded P steps ahead (an L2 round trip per
+// step otherwise); the dependency chain is one readlane and a few FMAs per
+// step.  Rows outside [c, s) are zero.
+template <int M>
+__device__ inline void linv_column(const LFactor& L, int s, int c, int lane, double (&r)[M]) {
   constexpr int P = 8;   // columns of L in flight ahead of the chain (divides 64)
-  double invd[4];
-  int64_t ic[4];         // H row of row i (clamped to s - 1; rows outside (t, s) are masked at use)
+  double invd[M];
+  int64_t ic[M];         // H row of row i (clamped to s - 1; rows outside (t, s) are masked at use)
   if (c >= s) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) r[m] = 0.0;
+    for (int m = 0; m < M; ++m) r[m] = 0.0;
     return;
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < M; ++m) {
     const int i = lane + 64 * m;
     r[m] = (i == c) ? 1.0 : 0.0;
     invd[m] = (i < s) ? 1.0 / L.at(i, i) : 0.0;
@@ -187,20 +188,20 @@ __device__ inline void linv_column(const LFactor& L, int s, int c, int lane, dou
   // Steps t run from c rounded down to a multiple of P (earlier ones are
   // skipped); column t of L sits in buf[t % P], loaded P steps ahead with an
   // unconditional load (column index clamped to s - 1).  The rows of step t
-  // live in register group t / 64 of lane t % 64; the four groups are walked
+  // live in register group t / 64 of lane t % 64; the M groups are walked
   // in turn, so that group is a compile-time choice and only groups at or
   // past it are updated.
   const int t0 = c & ~(P - 1);
-  double buf[P][4];
+  double buf[P][M];
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     const int tc = t0 + u < s ? t0 + u : s - 1;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) buf[u][m] = L.H[(int64_t)L.acc[tc] * L.b + ic[m]];
+    for (int m = 0; m < M; ++m) buf[u][m] = L.H[(int64_t)L.acc[tc] * L.b + ic[m]];
   }
   int t = t0;
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
+  for (int mt = 0; mt < M; ++mt) {
     const int te = s < 64 * (mt + 1) ? s : 64 * (mt + 1);
     for (; t < te; t += P) {
 #pragma unroll
@@ -211,7 +212,7 @@ __device__ inline void linv_column(const LFactor& L, int s, int c, int lane, dou
           const double xt = readlane_f64(r[mt], lt) * readlane_f64(invd[mt], lt);
           r[mt] = (lane == lt) ? xt : r[mt];
 #pragma unroll
-          for (int m = mt; m < 4; ++m) {
+          for (int m = mt; m < M; ++m) {
             const int i = lane + 64 * m;
             const double lv = (i > tt && i < s) ? buf[u][m] : 0.0;   // rows tt+1 .. s-1 of column tt
             r[m] = fma(-lv, xt, r[m]);
@@ -219,7 +220,7 @@ __device__ inline void linv_column(const LFactor& L, int s, int c, int lane, dou
         }
         const int tn = tt + P < s ? tt + P : s - 1;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) buf[u][m] = L.H[(int64_t)L.acc[tn] * L.b + ic[m]];
+        for (int m = 0; m < M; ++m) buf[u][m] = L.H[(int64_t)L.acc[tn] * L.b + ic[m]];
       }
     }
   }

@@ -702,6 +702,12 @@ __global__ __launch_bounds__(64) void k_trinv_bm(LFactor L, int Ctot, unsigned c
 #pragma unroll
     for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
     __syncthreads();
+  } else if (s <= 512) {
+    double r[8];
+    linv_column(L, s, c, lane, r);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[lane + 64 * m] = r[m];
+    __syncthreads();
   } else if (c < s) {
     for (int i = lane; i < s; i += 64) x[i] = 0.0;
     __syncthreads();

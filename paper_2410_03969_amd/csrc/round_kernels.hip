@@ -279,6 +279,52 @@ __global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X,
   H[q] = kappa_r2(sqdist(xi, xj, d), kp) - acc;
 }
 
+// The same for large d, one 16 x 16 block of H per workgroup: the coordinates
+// of its 16 + 16 proposals are staged through LDS 64 dims at a time (each row
+// is read from L2 once per block instead of once per entry); every entry sums
+// its squared differences in the same order as sqdist.
+constexpr int HS_T = 16, HS_DC = 64;
+__global__ __launch_bounds__(256) void k_gather_Hs_tiled(const double* __restrict__ X, int d, KParams kp,
+                                                         const int64_t* __restrict__ props, int b, int parts,
+                                                         const double* __restrict__ Hp, double* __restrict__ H,
+                                                         const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  __shared__ double xs[2][HS_T][HS_DC + 1];   // [0]: rows i of the block, [1]: rows j
+  const int tid = threadIdx.x, ti = tid % HS_T, tj = tid / HS_T;
+  const int i0 = blockIdx.x * HS_T, j0 = blockIdx.y * HS_T;
+  const int i = i0 + ti, j = j0 + tj;
+  // staging: thread tid copies dims (tid % 64) of rows (tid / 64) + 4 m, m < 8, of the 32 rows
+  const int sd = tid % HS_DC, sr = tid / HS_DC;
+  const double* src[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int r = sr + 4 * m;                       // 0..31: rows i0.. (r < 16), then j0..
+    const int li = r < HS_T ? i0 + r : j0 + r - HS_T;
+    src[m] = X + props[li < b ? li : b - 1] * d;
+  }
+  double sum = 0.0;
+  for (int k0 = 0; k0 < d; k0 += HS_DC) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int r = sr + 4 * m;
+      xs[r / HS_T][r % HS_T][sd] = k0 + sd < d ? src[m][k0 + sd] : 0.0;
+    }
+    __syncthreads();
+    const int ke = d - k0 < HS_DC ? d - k0 : HS_DC;
+    for (int t = 0; t < ke; ++t) {
+      const double e = xs[0][ti][t] - xs[1][tj][t];
+      sum += e * e;
+    }
+  }
+  if (i < b && j < b) {
+    const int64_t q = (int64_t)j * b + i;
+    double acc = 0.0;
+    for (int p = 0; p < parts; ++p) acc += Hp[(int64_t)p * b * b + q];
+    H[q] = kappa_r2(sum, kp) - acc;
+  }
+}
+
 // ------------------------------------------------- RejectionSampleSubmatrix
 // Alg. 1 on the b x b residual submatrix, in one workgroup, right-looking and
 // in place: accepted column i is scaled by 1/sqrt(h_ii) and the trailing
@@ -288,8 +334,9 @@ __global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X,
 // Rules beyond the printed test u_i * V < h_ii: a proposal equal to one
 // already accepted in this round is rejected, and at most k - k_r proposals are
 // accepted.  keep_all runs block RPCholesky (Alg. 7) instead: every test takes
-// V = 0, so each distinct proposal with a positive residual is kept.  Outputs: accepted local indices, the new pivots, u = 0 at the
-// new pivots, and the lower Cholesky factor L of H(T,T) left in H: the scaled
+// V = 0, so each distinct proposal with a positive residual is kept.
+// Outputs: accepted local indices, the new pivots, u = 0 at the new pivots,
+// and the lower Cholesky factor L of H(T,T) left in H: the scaled
 // column of accepted proposal i is column i of H (rows at and below i), so
 // L(a, c) = H(acc[a], acc[c]) (read through LFactor).
 struct FullGlobal {
@@ -950,8 +997,12 @@ void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d,
   const int64_t W = ((kmax + parts - 1) / parts + 63) / 64 * 64;   // columns per partition
   const unsigned nb = (unsigned)((b + 15) / 16);
   hipLaunchKernelGGL(k_gather_Hp, dim3(nb, nb, parts), dim3(256), 0, s, b, Fs, ldf, W, Hp, st);
-  hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp, props,
-                     b, parts, Hp, H, st);
+  if (d > 32)
+    hipLaunchKernelGGL(k_gather_Hs_tiled, dim3((unsigned)((b + HS_T - 1) / HS_T), (unsigned)((b + HS_T - 1) / HS_T)),
+                       dim3(256), 0, s, X, d, kp, props, b, parts, Hp, H, st);
+  else
+    hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp,
+                       props, b, parts, Hp, H, st);
 }
 template void launch_gather<double>(hipStream_t, const double*, int64_t, const double*, int, KParams,
                                     const int64_t*, int, double*, int64_t, int64_t, double*, double*,

@@ -81,6 +81,18 @@ def test_kernels_ragged_shapes(kernel):
     assert_parity(F, piv, out, oracle_run(X, prob))
 
 
+@pytest.mark.parametrize("kernel", [W.GAUSSIAN, W.MATERN32])
+def test_high_dimension_fp64(kernel):
+    """d = 70: kernel columns from the matrix-core distance kernel (two
+    contraction chunks, the second ragged) and H from the LDS-tiled gather
+    (a ragged second chunk of 64 dims); b = 150 leaves a ragged 16 x 16 block."""
+    rng = np.random.default_rng(70 + kernel)
+    X = rng.standard_normal((3001, 70))
+    prob = W.Problem(N=3001, d=70, k=400, b=150, kernel=kernel, sigma=6.0, seed=kernel)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
 def test_large_block_global_rejection_path():
     """b above the LDS-resident limit runs RejectionSampleSubmatrix on a
     global-memory matrix."""
