@@ -181,6 +181,76 @@ def rpc_accel(access, k: int, b: int, stream, max_rounds=None, record=False) -> 
                   round_sizes=sizes, u_history=hist)
 
 
+@dataclass
+class LowMemResult:
+    pivots: np.ndarray     # acceptance order
+    L: np.ndarray          # k_out x k_out lower Cholesky factor of A(S, S)
+    u: np.ndarray          # final residual diagonal
+    rounds: int
+    status: str
+    trace_A: float
+    round_sizes: list = field(default_factory=list)
+
+
+def rpc_accel_lowmem(access, k: int, b: int, stream, max_rounds=None) -> LowMemResult:
+    """Accelerated RPCholesky, low-memory implementation (Alg. 3; Section 2.4):
+    no N x k factor is kept; the pivots S and the Cholesky factor L of
+    A(S, S) define the approximation A(:,S) L^{-*} L^{-1} A(S,:), and the
+    entries A(R, S) are regenerated whenever a step needs them.  Same
+    rounds, uniform words and stopping rules as rpc_accel; the diagonal
+    update walks the rows in chunks of b, as printed."""
+    N = access.N
+    u = access.diag().astype(np.float64)
+    trace_A = float(np.sum(u))
+    L = np.zeros((0, 0))
+    S: list[int] = []
+    r = 0
+    status = "ok"
+    sizes = []
+    while len(S) < k and (max_rounds is None or r < max_rounds):
+        words = stream(2 * b * r, 2 * b)
+        props, T = draw_proposals(u, words[:b]) if np.sum(u) > 0 else (None, 0.0)
+        if not T > 0:
+            status = "early_stop"
+            break
+        kr = len(S)
+        Sa = np.array(S, dtype=np.int64)
+        # step 2: H = A(S',S') - A(S',S) L^{-*} L^{-1} A(S,S'), through Y = L^{-1} A(S,S')
+        if kr:
+            Y = solve_triangular(L, access.block(Sa, props), lower=True)
+        else:
+            Y = np.zeros((0, b))
+        H = access.block(props, props) - Y.T @ Y
+        Tacc, Li = reject_sample_submatrix(H, words[b:], props, cap=k - kr)
+        r += 1
+        sizes.append(int(Tacc.size))
+        if Tacc.size == 0:
+            status = "early_stop"
+            break
+        Si = props[Tacc]
+        # step 3: W = L^{-*} L^{-1} A(S, S_i); for each chunk R of b rows,
+        # G = (A(R,S_i) - A(R,S) W) L_i^{-*} and u(R) -= rowsqnorm(G)
+        W = solve_triangular(L.T, Y[:, Tacc], lower=False) if kr else np.zeros((0, Tacc.size))
+        for r0 in range(0, N, b):
+            R = np.arange(r0, min(r0 + b, N))
+            C = access.block(R, Si)
+            if kr:
+                C = C - access.block(R, Sa) @ W
+            G = solve_triangular(Li, C.T, lower=True).T
+            u[R] -= np.sum(G * G, axis=1)
+        # L <- [[L, 0], [A(S_i,S) L^{-*}, L_i]], where A(S_i,S) L^{-*} = Y(:,T)^*
+        Ln = np.zeros((kr + Tacc.size, kr + Tacc.size))
+        Ln[:kr, :kr] = L
+        Ln[kr:, :kr] = Y[:, Tacc].T
+        Ln[kr:, kr:] = Li
+        L = Ln
+        u = np.maximum(u, 0.0)
+        u[Si] = 0.0
+        S.extend(int(s) for s in Si)
+    return LowMemResult(pivots=np.array(S, dtype=np.int64), L=L, u=u, rounds=r, status=status,
+                        trace_A=trace_A, round_sizes=sizes)
+
+
 def rpc_plain(access, k: int, stream) -> Result:
     """Simple RPCholesky, one pivot per iteration (Alg. 6; Section 1.3.1).
     Iteration r reads uniform word 2r."""
