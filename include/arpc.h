@@ -157,6 +157,36 @@ arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, v
                                  int64_t* pivots, void* ws, size_t ws_bytes, void* stream,
                                  const double* U, int64_t nU, arpc_stats* stats);
 
+/* Bytes of device workspace that arpc_factor_lowmem needs for *problem:
+ * O(N ceil(b/64) + k (2d + 3b) + b^2) doubles, against the N k of arpc_factor's F.
+ * Returns ARPC_EINVAL for a problem arpc_factor_lowmem does not take. */
+arpc_status arpc_lowmem_workspace_size(const arpc_problem* problem, size_t* bytes);
+
+/* Accelerated RPCholesky, low-memory implementation (Alg. 3, Section 2.4): the
+ * same rounds, uniform words and pivots as arpc_factor (Alg. 2 with Alg. 1), but
+ * no N x k factor is stored.  The output is the pivot set S and the lower
+ * Cholesky factor L of A(S,S), which define the approximation
+ * A(:,S) L^{-*} L^{-1} A(S,:); the kernel entries A(R,S) are regenerated in
+ * every round, so the arithmetic grows to O(N k^2) kernel evaluations.
+ * Requirements: prec ARPC_FP64, method ARPC_ACCEL, k <= 4096, b <= 512,
+ * d <= 256.
+ *
+ *  X       device, N x d row-major FP64 points (read only).
+ *  L       device, k x k column-major FP64 output: L(i, j) for j <= i < k_out;
+ *          every other entry is zero.  Caller-allocated.
+ *  pivots  device, k int64 outputs in acceptance order (-1 past k_out).
+ *  ws      device workspace of at least arpc_lowmem_workspace_size bytes,
+ *          256-byte aligned.
+ *  stream  hipStream_t (NULL = default stream).
+ *  stats   host, may be NULL; k_out, rounds, proposals, status, trace_A,
+ *          trace_resid, ms_total and the per-class kernel times are filled.
+ *
+ * Returns ARPC_OK or ARPC_EARLY_STOP as arpc_factor does; errors ARPC_EINVAL,
+ * ARPC_ENUMERIC, ARPC_EDEVICE. */
+arpc_status arpc_factor_lowmem(const arpc_problem* problem, const double* X, double* L,
+                               int64_t* pivots, void* ws, size_t ws_bytes, void* stream,
+                               arpc_stats* stats);
+
 /* Host evaluation of the library's uniform stream: out[i] = uniform of word
  * start + i for key seed.  out is host memory of n doubles. */
 arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out);

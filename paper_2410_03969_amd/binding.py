@@ -21,7 +21,7 @@ NUM_KC = len(KERNEL_CLASSES)
 
 EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_factor",
            "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling",
-           "arpc_set_profiling_classes",
+           "arpc_set_profiling_classes", "arpc_lowmem_workspace_size", "arpc_factor_lowmem",
            "arpc_create", "arpc_destroy", "arpc_submit", "arpc_poll", "arpc_wait", "arpc_cancel",
            "arpc_serving_info"]
 
@@ -82,6 +82,11 @@ def lib():
                                            C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_int64,
                                            C.POINTER(ArpcStats)]
         L.arpc_stream_uniforms_host.restype = C.c_int
+        L.arpc_lowmem_workspace_size.restype = C.c_int
+        L.arpc_lowmem_workspace_size.argtypes = [C.POINTER(ArpcProblem), C.POINTER(C.c_size_t)]
+        L.arpc_factor_lowmem.restype = C.c_int
+        L.arpc_factor_lowmem.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(ArpcStats)]
         L.arpc_stream_uniforms_host.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_void_p]
         L.arpc_set_profiling.restype = None
         L.arpc_set_profiling.argtypes = [C.c_int]
@@ -147,6 +152,22 @@ def arpc_factor_uniforms(problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: 
     return st, stats
 
 
+def arpc_lowmem_workspace_size(problem: ArpcProblem) -> int:
+    n = C.c_size_t(0)
+    st = lib().arpc_lowmem_workspace_size(C.byref(problem), C.byref(n))
+    if st != ARPC_OK:
+        raise ValueError(f"arpc_lowmem_workspace_size: {arpc_status_str(st)}")
+    return int(n.value)
+
+
+def arpc_factor_lowmem(problem: ArpcProblem, X_ptr: int, L_ptr: int, piv_ptr: int, ws_ptr: int,
+                       ws_bytes: int, stream: int):
+    stats = ArpcStats()
+    st = lib().arpc_factor_lowmem(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(L_ptr), C.c_void_p(piv_ptr),
+                                  C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream), C.byref(stats))
+    return st, stats
+
+
 def arpc_stream_uniforms_host(seed: int, start: int, n: int) -> np.ndarray:
     out = np.empty(n, dtype=np.float64)
     st = lib().arpc_stream_uniforms_host(C.c_uint64(seed), C.c_int64(start), C.c_int64(n),
@@ -201,6 +222,32 @@ def factor(X, problem, U=None, device: str = "cuda", stream=None, workspace=None
     if status < 0:
         raise RuntimeError(f"arpc_factor failed: {arpc_status_str(status)}")
     return {"F": Ft.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}
+
+
+def factor_lowmem(X, problem, device: str = "cuda", stream=None):
+    """The low-memory implementation on the GPU.  Returns a dict with the
+    device tensors L (k x k lower factor of A(S,S)) and pivots, the status and
+    the stats.  Allocation only: all arithmetic runs in libarpc.so."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a GPU")
+    pr = make_problem(problem)
+    if isinstance(X, np.ndarray):
+        Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(device)
+    else:
+        Xd = X.contiguous()
+    # column-major k x k == row-major k x k transposed
+    Lt = torch.empty((problem.k, problem.k), dtype=torch.float64, device=device)
+    piv = torch.empty(problem.k, dtype=torch.int64, device=device)
+    nbytes = arpc_lowmem_workspace_size(pr)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    status, stats = arpc_factor_lowmem(pr, Xd.data_ptr(), Lt.data_ptr(), piv.data_ptr(), ws.data_ptr(), nbytes,
+                                       s.cuda_stream)
+    if status < 0:
+        raise RuntimeError(f"arpc_factor_lowmem failed: {arpc_status_str(status)}")
+    return {"L": Lt.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}
 
 
 # ------------------------------------------------------------------- serving

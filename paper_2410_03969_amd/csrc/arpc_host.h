@@ -86,6 +86,9 @@ struct JobBase {
   virtual arpc_status finish(arpc_stats* stats, double ms_total) = 0;
 };
 
+extern unsigned g_profiling;   // timed kernel classes (arpc_set_profiling*)
+arpc_status validate(const arpc_problem* p);
+KParams kparams_of(const arpc_problem& p);
 Layout layout_of(const arpc_problem& p);
 int fused_grid();
 arpc_status check_factor_args(const arpc_problem* p, const double* X, const void* F, const int64_t* pivots);

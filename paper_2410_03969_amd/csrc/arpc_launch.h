@@ -19,6 +19,9 @@ template <typename T>
 void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
                    const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* Hp, double* H,
                    const RoundState* st);
+// H = kappa(X(props), X(props)) (b x b, column-major), direct differences in FP64.
+void launch_kernel_block(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b, double* H,
+                         const RoundState* st);
 // RejectionSampleSubmatrix (keep_all: block RPCholesky, every distinct proposal
 // with a positive residual); L(T,T) is left in H (see LFactor).
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,

@@ -1004,6 +1004,16 @@ void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d,
     hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp,
                        props, b, parts, Hp, H, st);
 }
+void launch_kernel_block(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b, double* H,
+                         const RoundState* st) {
+  if (d > 32)
+    hipLaunchKernelGGL(k_gather_Hs_tiled, dim3((unsigned)((b + HS_T - 1) / HS_T), (unsigned)((b + HS_T - 1) / HS_T)),
+                       dim3(256), 0, s, X, d, kp, props, b, 0, nullptr, H, st);
+  else
+    hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp,
+                       props, b, 0, nullptr, H, st);
+}
+
 template void launch_gather<double>(hipStream_t, const double*, int64_t, const double*, int, KParams,
                                     const int64_t*, int, double*, int64_t, int64_t, double*, double*,
                                     const RoundState*);

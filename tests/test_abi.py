@@ -103,6 +103,19 @@ def test_fp8_workspace_holds_the_rounded_points():
     assert extra >= 8 * 1000 * 24
 
 
+def test_lowmem_rejects_unsupported_problems():
+    good = dict(N=5000, d=3, k=100, b=20, kernel=W.GAUSSIAN, sigma=0.5, seed=0, prec=W.FP64)
+    assert B.arpc_lowmem_workspace_size(B.make_problem(W.Problem(**good))) > 0
+    for bad in (dict(prec=W.FP32), dict(method=W.BLOCK), dict(k=4097), dict(b=513, k=1000), dict(d=257)):
+        with pytest.raises(ValueError):
+            B.arpc_lowmem_workspace_size(B.make_problem(W.Problem(**{**good, **bad})))
+
+
+def test_lowmem_workspace_is_far_below_the_factor():
+    p = B.make_problem(W.Problem(N=1_000_000, d=8, k=2000, b=200, kernel=W.GAUSSIAN, sigma=2.0, prec=W.FP64))
+    assert B.arpc_lowmem_workspace_size(p) < B.arpc_workspace_size(p) / 20
+
+
 def test_factor_rejects_null_pointers_without_gpu_work():
     st, _ = B.arpc_factor(_prob(), 0, 0, 0, 0, 0, 0)
     assert st == B.ARPC_EINVAL
