@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--workload", default="mixture", choices=["mixture", "laplace", "small", "sparse_hd"])
     ap.add_argument("--method", default="accel", choices=sorted(W.METHOD_NAMES.values()),
                     help="pivot rule: accel (Alg. 2, the method) or block (Alg. 7, a baseline)")
+    ap.add_argument("--lowmem", action="store_true",
+                    help="time the low-memory implementation (Alg. 3, FP64) instead of arpc_factor")
     ap.add_argument("--b", type=int, default=0,
                     help="block size instead of the workload's (1 with --method accel: simple RPCholesky)")
     ap.add_argument("--cpu-rounds", type=int, default=3,
@@ -246,6 +248,8 @@ def main():
         variant = f"{args.workload}_{args.method}_b{prob.b}"   # no counter record for a variant
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
+    if args.lowmem:
+        return run_lowmem(args, B, torch, X, Xd, prob.with_(prec=W.FP64), variant)
     pr = B.make_problem(prob)
     fdt = torch.float64 if prec == W.FP64 else torch.float32
     Ft = torch.empty((prob.k, prob.N), dtype=fdt, device=dev)
@@ -323,6 +327,52 @@ def main():
         del out64, F64
     if args.cpu_rounds > 0 and method == W.ACCEL:
         out["cpu_baseline"] = cpu_baseline(X, prob, args.cpu_rounds)
+    print(json.dumps(out), flush=True)
+
+
+def run_lowmem(args, B, torch, X, Xd, prob, variant):
+    """Pivots/s of the low-memory implementation (FP64), with its device
+    footprint beside that of arpc_factor (workspace + F) on the same problem."""
+    pr = B.make_problem(prob)
+    dev = Xd.device
+    Lt = torch.empty((prob.k, prob.k), dtype=torch.float64, device=dev)
+    piv = torch.empty(prob.k, dtype=torch.int64, device=dev)
+    nbytes = B.arpc_lowmem_workspace_size(pr)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(classes):
+        B.arpc_set_profiling_classes(classes)
+        st, stats = B.arpc_factor_lowmem(pr, Xd.data_ptr(), Lt.data_ptr(), piv.data_ptr(), ws.data_ptr(), nbytes,
+                                         stream.cuda_stream)
+        if st < 0:
+            raise RuntimeError(B.arpc_status_str(st))
+        return stats.as_dict()
+
+    for _ in range(args.warmup):
+        step([])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step([]) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    breakdown = step(list(B.KERNEL_CLASSES))
+    B.arpc_set_profiling(False)
+    last = runs[-1]
+    std_bytes = B.arpc_workspace_size(pr) + 8 * prob.N * prob.k
+    out = {
+        "metric": "pivots/s", "value": round(sum(r["k_out"] for r in runs) / elapsed, 2), "unit": "pivots/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{variant}: N={prob.N} d={prob.d} {W.KERNEL_NAMES[prob.kernel]} "
+                               f"sigma={prob.sigma} k={prob.k} b={prob.b} low-memory (Alg. 3)",
+                   "N": prob.N, "d": prob.d, "k": prob.k, "b": prob.b, "parallelism": "single GPU"},
+        "roofline": None,
+        "rounds": last["rounds"], "trace_error": (last["trace_resid"]) / last["trace_A"],
+        "device_bytes": nbytes + 8 * prob.k * prob.k, "device_bytes_standard_fp64": std_bytes,
+        "kernel_ms_per_step": {c: round(v, 3) for c, v in breakdown["ms_kernel"].items()},
+    }
     print(json.dumps(out), flush=True)
 
 
