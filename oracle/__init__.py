@@ -11,6 +11,7 @@ pivoted Cholesky", arXiv 2410.03969, that it follows):
 * ``stream``  - the uniform stream that replaces the paper's ``Rand()``
 * ``kernels`` - kernel functions evaluated by direct differences
 * ``fp8``     - rounding to FP8 e4m3 (the point set of the FP8 mode)
+* ``rpqr``    - accelerated randomly pivoted QR (Alg. 5)
 * ``rpc``     - simple RPCholesky (Alg. 6), block RPCholesky (Alg. 7),
                 RejectionSampleSubmatrix (Alg. 1), accelerated
                 RPCholesky (Alg. 2) and its low-memory implementation
@@ -19,6 +20,7 @@ pivoted Cholesky", arXiv 2410.03969, that it follows):
 from .stream import philox_stream, array_stream  # noqa: F401
 from .kernels import kappa, kernel_block  # noqa: F401
 from .fp8 import round_e4m3  # noqa: F401
+from .rpqr import orth, rpqr_accel  # noqa: F401
 from .rpc import (PointsAccess, DenseAccess, rpc_accel, rpc_accel_lowmem, rpc_plain, rpc_block,  # noqa: F401
                   reject_sample_submatrix, factor_from_pivots, nystrom_err,
                   draw_proposals)
