@@ -187,6 +187,36 @@ arpc_status arpc_factor_lowmem(const arpc_problem* problem, const double* X, dou
                                int64_t* pivots, void* ws, size_t ws_bytes, void* stream,
                                arpc_stats* stats);
 
+/* Bytes of device workspace that arpc_qr_factor needs: O(N + M b + k b + b^2)
+ * doubles.  Returns ARPC_EINVAL for sizes arpc_qr_factor does not take. */
+arpc_status arpc_qr_workspace_size(int64_t M, int64_t N, int64_t k, int64_t b, size_t* bytes);
+
+/* Accelerated randomly pivoted QR (Alg. 5, Section 5) of a general matrix B:
+ * column pivots proposed from the residual squared column norms and filtered
+ * by RejectionSampleSubmatrix (Alg. 1) on the residual Gram matrix C^* C of the
+ * proposals, so the pivots are those accelerated RPCholesky takes on B^* B
+ * (Proposition qr_cholesky) from the same uniform words (the stream of
+ * arpc_factor keyed by seed).  Output: Q with orthonormal columns and
+ * F = B^* Q, B_hat = Q F^*; each round's new columns of Q are orthonormalized
+ * after one extra Gram-Schmidt pass, by the QR factorization with a positive
+ * diagonal in R.  FP64; plain products in rocBLAS.
+ *
+ *  M, N    rows and columns of B, 1 <= k <= min(M, N), 1 <= b <= 512.
+ *  B       device, M x N column-major FP64 (read only).
+ *  Q       device, M x k column-major FP64 output.
+ *  F       device, N x k column-major FP64 output.
+ *  pivots  device, k int64 column indices in acceptance order (-1 past k_out).
+ *  ws      device workspace of at least arpc_qr_workspace_size bytes, 256-byte
+ *          aligned.  stream: hipStream_t (NULL = default).  stats: host, may be
+ *          NULL (trace_A is |B|_F^2 and trace_resid the residual's).
+ *
+ * Returns ARPC_OK or ARPC_EARLY_STOP (the residual reached zero or a round
+ * accepted nothing; Q and F columns k_out..k-1 are zero); errors ARPC_EINVAL,
+ * ARPC_ENUMERIC (a non-finite entry of B), ARPC_EDEVICE. */
+arpc_status arpc_qr_factor(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t seed, int64_t max_rounds,
+                           const double* B, double* Q, double* F, int64_t* pivots, void* ws,
+                           size_t ws_bytes, void* stream, arpc_stats* stats);
+
 /* Host evaluation of the library's uniform stream: out[i] = uniform of word
  * start + i for key seed.  out is host memory of n doubles. */
 arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out);

@@ -22,6 +22,7 @@ NUM_KC = len(KERNEL_CLASSES)
 EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_factor",
            "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling",
            "arpc_set_profiling_classes", "arpc_lowmem_workspace_size", "arpc_factor_lowmem",
+           "arpc_qr_workspace_size", "arpc_qr_factor",
            "arpc_create", "arpc_destroy", "arpc_submit", "arpc_poll", "arpc_wait", "arpc_cancel",
            "arpc_serving_info"]
 
@@ -87,6 +88,12 @@ def lib():
         L.arpc_factor_lowmem.restype = C.c_int
         L.arpc_factor_lowmem.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(ArpcStats)]
+        L.arpc_qr_workspace_size.restype = C.c_int
+        L.arpc_qr_workspace_size.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
+        L.arpc_qr_factor.restype = C.c_int
+        L.arpc_qr_factor.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint64, C.c_int64,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.POINTER(ArpcStats)]
         L.arpc_stream_uniforms_host.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_void_p]
         L.arpc_set_profiling.restype = None
         L.arpc_set_profiling.argtypes = [C.c_int]
@@ -166,6 +173,14 @@ def arpc_factor_lowmem(problem: ArpcProblem, X_ptr: int, L_ptr: int, piv_ptr: in
     st = lib().arpc_factor_lowmem(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(L_ptr), C.c_void_p(piv_ptr),
                                   C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream), C.byref(stats))
     return st, stats
+
+
+def arpc_qr_workspace_size(M: int, N: int, k: int, b: int) -> int:
+    n = C.c_size_t(0)
+    st = lib().arpc_qr_workspace_size(int(M), int(N), int(k), int(b), C.byref(n))
+    if st != ARPC_OK:
+        raise ValueError(f"arpc_qr_workspace_size: {arpc_status_str(st)}")
+    return int(n.value)
 
 
 def arpc_stream_uniforms_host(seed: int, start: int, n: int) -> np.ndarray:
@@ -248,6 +263,37 @@ def factor_lowmem(X, problem, device: str = "cuda", stream=None):
     if status < 0:
         raise RuntimeError(f"arpc_factor_lowmem failed: {arpc_status_str(status)}")
     return {"L": Lt.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}
+
+
+def qr_factor(B, k: int, b: int, seed: int = 0, max_rounds: int = 0, device: str = "cuda", stream=None):
+    """Accelerated randomly pivoted QR on the GPU.  B: numpy (M x N) or a
+    device tensor laid out column-major (the transpose of a contiguous N x M
+    tensor).  Returns a dict with the device tensors Q (M x k), F (N x k),
+    pivots, the status and the stats.  Allocation only."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a GPU")
+    if isinstance(B, np.ndarray):
+        M, N = B.shape
+        Bt = torch.from_numpy(np.ascontiguousarray(np.asarray(B, dtype=np.float64).T)).to(device)   # N x M rows
+    else:
+        Bt = B.t().contiguous()
+        N, M = Bt.shape
+    Qt = torch.empty((k, M), dtype=torch.float64, device=device)
+    Ft = torch.empty((k, N), dtype=torch.float64, device=device)
+    piv = torch.empty(k, dtype=torch.int64, device=device)
+    nbytes = arpc_qr_workspace_size(M, N, k, b)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    stats = ArpcStats()
+    status = lib().arpc_qr_factor(int(M), int(N), int(k), int(b), C.c_uint64(seed), int(max_rounds),
+                                  C.c_void_p(Bt.data_ptr()), C.c_void_p(Qt.data_ptr()), C.c_void_p(Ft.data_ptr()),
+                                  C.c_void_p(piv.data_ptr()), C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes),
+                                  C.c_void_p(s.cuda_stream), C.byref(stats))
+    if status < 0:
+        raise RuntimeError(f"arpc_qr_factor failed: {arpc_status_str(status)}")
+    return {"Q": Qt.t(), "F": Ft.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}
 
 
 # ------------------------------------------------------------------- serving

@@ -7,6 +7,10 @@ namespace arpc {
 
 void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_t N, int d, KParams kp,
                  RoundState* st, int64_t nchunks);
+// Round state and chunk sums from a residual diagonal u already in place
+// (the state must have been zeroed; a set nonfinite flag stops the run).
+void launch_init_from_diag(hipStream_t s, const double* u, int64_t N, double* csum, RoundState* st,
+                           int64_t nchunks);
 // Xq = X with every coordinate rounded to FP8 e4m3 (the FP8 mode's points), n values.
 void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n);
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,

@@ -83,6 +83,16 @@ __global__ __launch_bounds__(256) void k_round_e4m3(const double* __restrict__ X
     Xq[i] = round_e4m3(X[i]);
 }
 
+// Chunk sums of a residual diagonal u given by the caller (the squared column
+// norms in the QR method).
+__global__ __launch_bounds__(CHUNK) void k_chunk_sums(const double* __restrict__ u, int64_t N,
+                                                      double* __restrict__ csum) {
+  __shared__ double sh[CHUNK];
+  const int64_t j = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+  const double t = block_sum<CHUNK>(j < N ? u[j] : 0.0, sh);
+  if (threadIdx.x == 0) csum[blockIdx.x] = t;
+}
+
 // trace(A) from the chunk sums, and the initial round state.
 __global__ __launch_bounds__(1024) void k_init_state(const double* __restrict__ csum, int64_t nchunks,
                                                      RoundState* st) {
@@ -971,6 +981,12 @@ void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n) {
 void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_t N, int d, KParams kp,
                  RoundState* st, int64_t nchunks) {
   hipLaunchKernelGGL(k_init, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, csum, X, N, d, kp, st);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, csum, nchunks, st);
+}
+
+void launch_init_from_diag(hipStream_t s, const double* u, int64_t N, double* csum, RoundState* st,
+                           int64_t nchunks) {
+  hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, N, csum);
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, csum, nchunks, st);
 }
 
