@@ -141,3 +141,17 @@ def serving_stream(n_jobs: int = 512, rate: float = 10.0, seed: int = 4,
         jobs.append(Job(j, t, X, Problem(N=N, d=d, k=k, b=b, kernel=GAUSSIAN,
                                          sigma=float(np.sqrt(d)), seed=j, prec=prec)))
     return jobs
+
+
+def qr_matrix(M: int = 1000, N: int = 100_000, rank: int = 300, decay: float = 0.99, noise: float = 1e-3,
+              seed: int = 0):
+    """A dense M x N test matrix for the QR method: U diag(decay^i) V^* with
+    orthonormal random U (M x rank) and V (N x rank), plus i.i.d. Gaussian
+    noise of the given scale; returned column-major as the transpose of a
+    C-contiguous N x M array (so B.T is contiguous)."""
+    rng = np.random.default_rng(seed)
+    U = np.linalg.qr(rng.standard_normal((M, rank)))[0]
+    V = np.linalg.qr(rng.standard_normal((N, rank)))[0]
+    Bt = (V * decay ** np.arange(rank)) @ U.T          # N x M = B^T
+    Bt += noise * rng.standard_normal((N, M))
+    return Bt.T
