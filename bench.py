@@ -357,7 +357,7 @@ def run_qr(args, B, torch):
         "unit": "pivots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"qr: M={M} N={N} rank 300 decay 0.99 noise 1e-3 k={k} b={b} (Alg. 5)",
+        "config": {"workload": f"qr: M={M} N={N} rank 300 decay 0.99 noise 1e-5 k={k} b={b} (Alg. 5)",
                    "M": M, "N": N, "k": k, "b": b, "parallelism": "single GPU"},
         "roofline": None, "rounds": last["rounds"],
         "residual_rel_frobenius": float(np.sqrt(max(last["trace_resid"], 0.0) / last["trace_A"])),

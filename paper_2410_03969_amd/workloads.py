@@ -143,7 +143,7 @@ def serving_stream(n_jobs: int = 512, rate: float = 10.0, seed: int = 4,
     return jobs
 
 
-def qr_matrix(M: int = 1000, N: int = 100_000, rank: int = 300, decay: float = 0.99, noise: float = 1e-3,
+def qr_matrix(M: int = 1000, N: int = 100_000, rank: int = 300, decay: float = 0.99, noise: float = 1e-5,
               seed: int = 0):
     """A dense M x N test matrix for the QR method: U diag(decay^i) V^* with
     orthonormal random U (M x rank) and V (N x rank), plus i.i.d. Gaussian
