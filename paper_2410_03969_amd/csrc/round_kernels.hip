@@ -451,6 +451,17 @@ __device__ inline void tile_advance(int& J, int& L) {
   }
 }
 
+// Workgroup barrier for LDS traffic only (it does not wait for global stores
+// in flight): the register-resident form exchanges data between its waves
+// only through LDS (the factor columns stored to H are read by later
+// kernels, and every tile load from a column block of H has been consumed
+// before that block's columns are written).
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <bool GT>
 __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __restrict__ H, int b,
                                                                    const int64_t* __restrict__ props, Unif un,
@@ -465,6 +476,9 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
   __shared__ double BC[RT][RT];            // BC[ii][r]: column ii of the block when its test runs;
                                            // then X = L^{-1} of the block's accepted part, X(r, c) at BC[r][c]
   __shared__ double rsq[RT];               // 1/sqrt(h) of the accepted proposals (0: rejected)
+  // register form (look-ahead): X of the last two blocks, XB[I & 1] for block I
+  constexpr bool LA = !GT;
+  __shared__ double XB[LA ? 2 * RT * RT : 1];
   __shared__ double uv[BM];     // u_i V_i of the test
   __shared__ int64_t pr[BM];
   __shared__ short prv[BM], accl[BM];
@@ -512,9 +526,14 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
     // Lane ii also holds what the test of proposal 16 I + ii needs: u V, and
     // whether an earlier proposal of the same point was taken (before this
     // block: from tk; inside it: the scalar mask).
+    int pm = 0;   // accepted columns of the previous block (register form: its panel is pending)
     for (int I = 0; I < nbk && nacc < cap; ++I) {
       double(*Qb)[QS] = Q[I & 1];
-      __syncthreads();   // (1) block column I is in LDS
+      if constexpr (LA) {
+        lds_sync();   // (1) the diagonal block of block column I is in LDS
+      } else {
+        __syncthreads();   // (1) block column I is in LDS
+      }
       double dr[RT];
 #pragma unroll
       for (int c = 0; c < RT; ++c) dr[c] = Qb[RT * I + l16][c];
@@ -563,6 +582,9 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
         mask |= a ? (1 << ii) : 0;
         cnt += a ? 1 : 0;
       }
+      if constexpr (LA) {
+        if (pm) lds_sync();   // (m) the previous panel is complete
+      }
       // the block's outputs: lane c forms 1/sqrt(h_c); row r keeps the
       // unscaled entries T(r, ii) of the steps, which scale into column ii
       const double rsL = ((mask >> l16) & 1) ? 1.0 / sqrt(hL) : 0.0;
@@ -596,14 +618,21 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
 #pragma unroll
           for (int r = k + 1; r < RT; ++r) y[r] = fma(-LD[k][r], xk, y[r]);
         }
+        double* xo = LA ? XB + (I & 1) * RT * RT : &BC[0][0];
         if (lane < RT)
 #pragma unroll
-          for (int r = 0; r < RT; ++r) BC[r][lane] = y[r];
+          for (int r = 0; r < RT; ++r) xo[r * RT + lane] = y[r];
       }
       if (lane == 0) bmask = mask;
-      __syncthreads();   // (2) decisions, LD, rsq and X are in LDS
-      if (mask == 0) continue;
-      __syncthreads();   // (3) the panel is solved
+      if constexpr (LA) {
+        lds_sync();   // (2) decisions, LD, rsq and X are in LDS
+        pm = mask;
+        if (mask == 0) continue;
+      } else {
+        __syncthreads();   // (2) decisions, LD, rsq and X are in LDS
+        if (mask == 0) continue;
+        __syncthreads();   // (3) the panel is solved
+      }
       nacc += __popc(mask);
     }
   } else if constexpr (!GT) {
@@ -651,12 +680,12 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
       for (int i = 0; i < 4; ++i)
         if (RT * J + g + 4 * i >= b || RT * L + l16 >= b) tr[k][i] = 0.0;
     });
-    // T(J, L) -= P_J P_L^T for the tiles selected by pick, four k-steps of
-    // four columns (rejected columns of P are zero), P the previous block's
+    // T(J, L) -= P_J P_L^T for the tiles selected by pick(J, L), four k-steps
+    // of four columns (rejected columns of P are zero), P the previous block's
     // solved panel; a tile's eight operands are read before its products
-    auto update = [&](double(*P)[QS], auto pick) __attribute__((always_inline)) {
+    auto update2 = [&](double(*P)[QS], auto pick) __attribute__((always_inline)) {
       for_tiles([&](int k, int J, int L) {
-        if (__builtin_expect(pick(L), 0)) {
+        if (__builtin_expect(pick(J, L), 0)) {
           double av[4], bv[4];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
@@ -668,51 +697,69 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
         }
       });
     };
-    int pmask = 0;   // accepted columns of the previous block (update pending)
+    // tiles selected by pick(J, L) into the rows of block J of the buffer
+    auto copy_to = [&](double(*Qd)[QS], auto pick) __attribute__((always_inline)) {
+      for_tiles([&](int k, int J, int L) {
+        if (__builtin_expect(pick(J, L), 0))
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Qd[RT * J + g + 4 * i][l16] = tr[k][i];
+      });
+    };
+    // panel rows J >= Jlo of block Ip (spread: row J to tile wavefront
+    // (J - Jlo) mod 7; else row Jlo only, by the caller): P_J = Q_J X^T from the copy of block column Ip, in place, and the
+    // accepted columns into H.  A loop over J, not over this wavefront's tiles
+    // (it touches no tile registers).
+    auto panel = [&](double(*Qs)[QS], const double* X, int Ip, int Jlo, bool spread) __attribute__((always_inline)) {
+      const int j0 = spread ? Jlo + wt : Jlo, je = spread ? nbk : Jlo + 1;
+      for (int J = j0; J < je; J += REJECT_T_TW) {
+        rd4 pj = rd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          pj = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[RT * J + l16][4 * ks + g], X[l16 * RT + 4 * ks + g], pj, 0,
+                                                    0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Qs[RT * J + g + 4 * i][l16] = pj[i];
+        if (RT * Ip + l16 < b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = RT * J + g + 4 * i;
+            if (row < b) H[(int64_t)(RT * Ip + l16) * b + row] = pj[i];
+          }
+      }
+    };
+    // Look-ahead: the panel and the rank-16 update of block I - 1 run during
+    // block I.  Before the tests of block I only the panel row P_I and the
+    // diagonal tile (I, I) are computed (by that tile's owner); the rest of
+    // the panel runs beside the tests and the rest of the update beside the
+    // block's outputs and its inverse factor (wavefront 0 takes the barrier
+    // (m) between them after its last test).
+    int pmask = 0;   // accepted columns of the previous block (panel and update pending)
     for (int I = 0; I < nbk && nacc < cap; ++I) {
       double(*Qb)[QS] = Q[I & 1];
-      double(*Qp)[QS] = Q[(I + 1) & 1];
-      // 1. the pending update on block column I, then its copy to LDS
-      if (pmask) update(Qp, [&](int l) { return l == I; });
-      for_tiles([&](int k, int J, int L) {
-        if (__builtin_expect(L == I, 0))
-#pragma unroll
-          for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = tr[k][i];
-      });
-      __syncthreads();   // (1)
-      // 2. the rest of the pending update, beside the tests
-      if (pmask) update(Qp, [&](int l) { return l > I; });
-      __syncthreads();   // (2)
+      double(*Qp)[QS] = Q[(I + 1) & 1];         // block column I - 1, becoming its panel
+      const double* Xp = XB + ((I + 1) & 1) * RT * RT;   // X of block I - 1
+      if (pmask) {
+        // panel row I of block I - 1 (P_I = Q_I X^T), by the owner of the
+        // diagonal tile (I, I), which then updates that tile with it (its own
+        // LDS writes are ordered before its reads); the other waves read P_I
+        // only after (m)
+        if ((I * (I + 1) / 2 + I) % REJECT_T_TW == wt) {
+          panel(Qp, Xp, I - 1, I, false);
+          update2(Qp, [&](int J, int L) { return J == I && L == I; });
+        }
+      }
+      copy_to(Qb, [&](int J, int L) { return J == I && L == I; });
+      lds_sync();   // (1)
+      if (pmask) {
+        panel(Qp, Xp, I - 1, I + 1, true);
+        lds_sync();   // (m)
+        update2(Qp, [&](int J, int L) { return L >= I && !(J == I && L == I); });
+      }
+      copy_to(Qb, [&](int J, int L) { return L == I && J > I; });
+      lds_sync();   // (2)
       const int mask = bmask;
       pmask = mask;
       if (mask == 0) continue;
-      // 3. the panel below the block: P_J = Q_J X^T for this wavefront's
-      // tiles (J, I), J > I, four 16x16x4 products each (rejected columns of
-      // X^T are zero), into the panel rows of the buffer (for the update)
-      // and the accepted columns into H
-      for_tiles([&](int k, int J, int L) {
-        if (__builtin_expect(L == I && J > I, 0)) {
-          double av[4], bv[4];
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            av[ks] = Qb[RT * J + l16][4 * ks + g];
-            bv[ks] = BC[l16][4 * ks + g];
-          }
-          rd4 pj = rd4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) pj = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], pj, 0, 0, 0);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = pj[i];
-          // column l16 of the panel (zero if rejected) into column 16 I + l16 of H
-          if (RT * I + l16 < b)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int row = RT * J + g + 4 * i;
-              if (row < b) H[(int64_t)(RT * I + l16) * b + row] = pj[i];
-            }
-        }
-      });
-      __syncthreads();   // (3)
       nacc += __popc(mask);
     }
   } else {
