@@ -553,6 +553,9 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
 #pragma unroll
       for (int ii = 0; ii < RT; ++ii) {
         const int i = RT * I + ii;
+        if constexpr (LA) {
+          if (ii == RT / 2 && pm) lds_sync();   // (m)
+        }
         // column ii is final: T(ii + 1, ii), needed by the next test, by
         // readlane; the rest through LDS (lanes r and r + 16 k write the same
         // value), needed no earlier than the test after next
@@ -581,9 +584,6 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
         hL = (l16 == ii) ? h : hL;
         mask |= a ? (1 << ii) : 0;
         cnt += a ? 1 : 0;
-      }
-      if constexpr (LA) {
-        if (pm) lds_sync();   // (m) the previous panel is complete
       }
       // the block's outputs: lane c forms 1/sqrt(h_c); row r keeps the
       // unscaled entries T(r, ii) of the steps, which scale into column ii
@@ -730,9 +730,10 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
     // Look-ahead: the panel and the rank-16 update of block I - 1 run during
     // block I.  Before the tests of block I only the panel row P_I and the
     // diagonal tile (I, I) are computed (by that tile's owner); the rest of
-    // the panel runs beside the tests and the rest of the update beside the
-    // block's outputs and its inverse factor (wavefront 0 takes the barrier
-    // (m) between them after its last test).
+    // the panel runs beside the first half of the tests and the rest of the
+    // update beside the second half, the block's outputs and its inverse
+    // factor (wavefront 0 takes the barrier (m) between them inside its test
+    // loop).
     int pmask = 0;   // accepted columns of the previous block (panel and update pending)
     for (int I = 0; I < nbk && nacc < cap; ++I) {
       double(*Qb)[QS] = Q[I & 1];
