@@ -217,6 +217,49 @@ arpc_status arpc_qr_factor(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t 
                            const double* B, double* Q, double* F, int64_t* pivots, void* ws,
                            size_t ws_bytes, void* stream, arpc_stats* stats);
 
+/* ------------------------------------------------------- kernel ridge regression
+ * (A + mu I) beta = y for the kernel matrix A of the points X (Section 3.2), by
+ * preconditioned conjugate gradients with the low-rank preconditioner
+ * P = F F^* + mu I, F the N x k factor of arpc_factor (k = 0: P = mu I). */
+typedef struct arpc_krr_stats {
+  int64_t iterations;   /* PCG iterations run */
+  double rel_residual;  /* |y - (A + mu I) beta| / |y| as tracked by the recurrence */
+  double ms_total;      /* host wall time of the call */
+  double ms_setup;      /* forming and factoring mu I + F^* F */
+  double ms_matvec;     /* products with A + mu I (host-timed, includes the dot product) */
+  double ms_precond;    /* applications of P^{-1} */
+  int32_t status;       /* ARPC_OK: converged to tol; ARPC_EARLY_STOP: max_iter reached */
+  int32_t reserved;
+} arpc_krr_stats;
+
+/* Bytes of device workspace of arpc_krr_pcg: O(N + k^2) doubles, plus N k
+ * doubles when F is FP32 (converted once). */
+arpc_status arpc_krr_workspace_size(int64_t N, int64_t d, int64_t k, int32_t f_prec, size_t* bytes);
+
+/* Solves (A + mu I) beta = y by PCG from beta = 0 (Golub and Van Loan,
+ * Alg. 11.5.1), stopping when |r| <= tol |y| or after max_iter iterations.
+ * The products with A regenerate the kernel entries in FP64 (direct
+ * differences, the diagonal exactly kappa(0)); P^{-1} r is applied through the
+ * Woodbury identity (r - F (mu I + F^* F)^{-1} F^* r) / mu.
+ *
+ *  X       device, N x d row-major FP64 points, 1 <= d <= 128.
+ *  kernel, bandwidth  as in arpc_problem; mu > 0.
+ *  y       device, N FP64 right-hand side.
+ *  F       device, N x k column-major factor, FP64 if f_prec is ARPC_FP64, else
+ *          FP32 (the layout arpc_factor writes); unused when k = 0.  k <= 2048.
+ *  beta    device, N FP64 output.
+ *  ws      device workspace of at least arpc_krr_workspace_size bytes, 256-byte aligned.
+ *  stream  hipStream_t; the host waits on it once per iteration (the PCG scalars).
+ *  stats   host, may be NULL.
+ *
+ * Returns ARPC_OK (converged), ARPC_EARLY_STOP (max_iter reached), ARPC_EINVAL,
+ * ARPC_ENUMERIC (mu I + F^* F not positive definite, or a non-finite residual),
+ * ARPC_EDEVICE. */
+arpc_status arpc_krr_pcg(int64_t N, int64_t d, int32_t kernel, double bandwidth, double mu,
+                         const double* X, const double* y, const void* F, int32_t f_prec, int64_t k,
+                         double tol, int64_t max_iter, double* beta, void* ws, size_t ws_bytes,
+                         void* stream, arpc_krr_stats* stats);
+
 /* Host evaluation of the library's uniform stream: out[i] = uniform of word
  * start + i for key seed.  out is host memory of n doubles. */
 arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out);

@@ -22,7 +22,7 @@ NUM_KC = len(KERNEL_CLASSES)
 EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_factor",
            "arpc_factor_uniforms", "arpc_stream_uniforms_host", "arpc_set_profiling",
            "arpc_set_profiling_classes", "arpc_lowmem_workspace_size", "arpc_factor_lowmem",
-           "arpc_qr_workspace_size", "arpc_qr_factor",
+           "arpc_qr_workspace_size", "arpc_qr_factor", "arpc_krr_workspace_size", "arpc_krr_pcg",
            "arpc_create", "arpc_destroy", "arpc_submit", "arpc_poll", "arpc_wait", "arpc_cancel",
            "arpc_serving_info"]
 
@@ -32,6 +32,15 @@ class ArpcProblem(C.Structure):
                 ("kernel", C.c_int32), ("prec", C.c_int32), ("bandwidth", C.c_double),
                 ("seed", C.c_uint64), ("max_rounds", C.c_int64), ("method", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class ArpcKrrStats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("rel_residual", C.c_double), ("ms_total", C.c_double),
+                ("ms_setup", C.c_double), ("ms_matvec", C.c_double), ("ms_precond", C.c_double),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class ArpcStats(C.Structure):
@@ -94,6 +103,12 @@ def lib():
         L.arpc_qr_factor.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint64, C.c_int64,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                      C.c_void_p, C.POINTER(ArpcStats)]
+        L.arpc_krr_workspace_size.restype = C.c_int
+        L.arpc_krr_workspace_size.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+        L.arpc_krr_pcg.restype = C.c_int
+        L.arpc_krr_pcg.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p, C.POINTER(ArpcKrrStats)]
         L.arpc_stream_uniforms_host.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_void_p]
         L.arpc_set_profiling.restype = None
         L.arpc_set_profiling.argtypes = [C.c_int]
@@ -294,6 +309,45 @@ def qr_factor(B, k: int, b: int, seed: int = 0, max_rounds: int = 0, device: str
     if status < 0:
         raise RuntimeError(f"arpc_qr_factor failed: {arpc_status_str(status)}")
     return {"Q": Qt.t(), "F": Ft.t(), "pivots": piv, "status": status, "stats": stats.as_dict()}
+
+
+def krr_pcg(X, y, F, kernel: int, sigma: float, mu: float, tol: float = 1e-8, max_iter: int = 1000,
+            device: str = "cuda", stream=None):
+    """(A + mu I) beta = y by PCG with P = F F^* + mu I on the GPU.  X, y:
+    numpy or device tensors; F: a device tensor N x k (FP64 or FP32, column
+    j = F[:, j], as factor() returns it) or None.  Returns a dict with the
+    device tensor beta, the status and the stats.  Allocation only."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a GPU")
+    Xd = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64) if isinstance(X, np.ndarray) else X,
+                         device=device).contiguous()
+    yd = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64) if isinstance(y, np.ndarray) else y,
+                         device=device).contiguous()
+    N, d = Xd.shape
+    if F is None:
+        k, f_prec, Fp = 0, 0, 0
+    else:
+        k = F.shape[1]
+        Ft = F.t().contiguous()          # column-major N x k
+        f_prec = 0 if Ft.dtype == torch.float64 else 1
+        Fp = Ft.data_ptr()
+    n = C.c_size_t(0)
+    st = lib().arpc_krr_workspace_size(int(N), int(d), int(k), int(f_prec), C.byref(n))
+    if st != ARPC_OK:
+        raise ValueError(f"arpc_krr_workspace_size: {arpc_status_str(st)}")
+    ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
+    beta = torch.empty(N, dtype=torch.float64, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    stats = ArpcKrrStats()
+    status = lib().arpc_krr_pcg(int(N), int(d), int(kernel), float(sigma), float(mu), C.c_void_p(Xd.data_ptr()),
+                                C.c_void_p(yd.data_ptr()), C.c_void_p(Fp), int(f_prec), int(k), float(tol),
+                                int(max_iter), C.c_void_p(beta.data_ptr()), C.c_void_p(ws.data_ptr()), n,
+                                C.c_void_p(s.cuda_stream), C.byref(stats))
+    if status < 0:
+        raise RuntimeError(f"arpc_krr_pcg failed: {arpc_status_str(status)}")
+    return {"beta": beta, "status": status, "stats": stats.as_dict()}
 
 
 # ------------------------------------------------------------------- serving

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libarpc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["round_kernels.hip", "gemm_kernels.hip", "mfma_kernels.hip", "fused_kernels.hip", "lowmem.hip", "rpqr.hip",
+SOURCES = ["round_kernels.hip", "gemm_kernels.hip", "mfma_kernels.hip", "fused_kernels.hip", "lowmem.hip", "rpqr.hip", "krr.hip",
            "api.cpp", "serving.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

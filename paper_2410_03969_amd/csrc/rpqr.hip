@@ -119,6 +119,14 @@ __global__ __launch_bounds__(256) void k_qr_rownorms(const double* __restrict__ 
 
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+}  // namespace
+
+void launch_dense_chol(hipStream_t s, double* G, int n, int* bad) {
+  hipLaunchKernelGGL(k_qr_chol, dim3(1), dim3(256), 0, s, G, n, bad);
+}
+
+namespace {
+
 struct QrLayout {
   size_t st, u, csum, cpre, props, acc, hist, Fs, C, H, Tm, Gr, P, trace, bad, total;
 };
@@ -246,7 +254,7 @@ arpc_status qr_run(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t seed, in
       }
       BCHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, sr, sr, (rocblas_int)M, &one, Qn,
                          (rocblas_int)M, Qn, (rocblas_int)M, &zero, Gr, sr));
-      hipLaunchKernelGGL(k_qr_chol, dim3(1), dim3(256), 0, s, Gr, sr, bad);
+      launch_dense_chol(s, Gr, sr, bad);
       BCHK(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                          rocblas_diagonal_non_unit, (rocblas_int)M, sr, &one, Gr, sr, Qn, (rocblas_int)M));
       prof.end();

@@ -43,7 +43,8 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     fields = {"arpc_problem": [f for f, _ in B.ArpcProblem._fields_],
               "arpc_stats": [f for f, _ in B.ArpcStats._fields_],
-              "arpc_serving_stats": [f for f, _ in B.ArpcServingStats._fields_]}
+              "arpc_serving_stats": [f for f, _ in B.ArpcServingStats._fields_],
+              "arpc_krr_stats": [f for f, _ in B.ArpcKrrStats._fields_]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "arpc.h"', 'int main(void){']
     for st, fs in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({st}));')
@@ -56,7 +57,7 @@ def test_struct_layout_matches_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = []
-    for cls in (B.ArpcProblem, B.ArpcStats, B.ArpcServingStats):
+    for cls in (B.ArpcProblem, B.ArpcStats, B.ArpcServingStats, B.ArpcKrrStats):
         want.append(ctypes.sizeof(cls))
         want += [getattr(cls, f).offset for f, _ in cls._fields_]
     assert got == want
