@@ -6,8 +6,9 @@
 // thread per row, the other points staged through LDS 64 at a time; FP64,
 // direct differences, the diagonal exactly kappa(0)).  P^{-1} r uses the
 // Woodbury identity, (r - F (mu I + F^* F)^{-1} F^* r) / mu, with the k x k
-// matrix formed once (rocBLAS dsyrk) and factored by the library's one-
-// workgroup Cholesky; the plain vector and matrix-vector products are rocBLAS.
+// matrix formed once (rocBLAS dsyrk) and factored blockwise (the library's
+// one-workgroup Cholesky on 64 x 64 diagonal blocks, rocBLAS dtrsm and dsyrk
+// for the rest); the plain vector and matrix-vector products are rocBLAS.
 // PCG is the textbook iteration from beta = 0 (Golub and Van Loan,
 // Alg. 11.5.1); the host reads the scalars of each iteration.
 #include <hip/hip_runtime.h>
@@ -98,7 +99,7 @@ __global__ void k_krr_add_diag(double* __restrict__ M, int k, double mu) {
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct KrrLayout {
-  size_t Fd, M, t, r, z, p, q, bad, total;
+  size_t Fd, M, D, t, r, z, p, q, bad, total;
 };
 
 KrrLayout krr_layout(int64_t N, int64_t k, bool convert) {
@@ -111,6 +112,7 @@ KrrLayout krr_layout(int64_t N, int64_t k, bool convert) {
   };
   l.Fd = take(convert ? sizeof(double) * N * k : 0);
   l.M = take(sizeof(double) * k * k);
+  l.D = take(sizeof(double) * 64 * 64);
   l.t = take(sizeof(double) * (k > 0 ? k : 1));
   l.r = take(sizeof(double) * N);
   l.z = take(sizeof(double) * N);
@@ -180,7 +182,32 @@ arpc_status krr_run(int64_t N, int64_t d, int32_t kernel, double bw, double mu, 
     KBCHK(rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, (rocblas_int)k, (rocblas_int)N, &one, Fd,
                         (rocblas_int)N, &zero, M, (rocblas_int)k));
     hipLaunchKernelGGL(k_krr_add_diag, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, M, (int)k, mu);
-    launch_dense_chol(s, M, (int)k, bad);
+    // blocked right-looking Cholesky, 64 columns at a time: the diagonal
+    // block by the one-workgroup kernel (it reads and writes only that block,
+    // which has leading dimension k here, so it is factored in a packed copy),
+    // the panel below by a triangular solve, the trailing matrix by a
+    // symmetric rank-64 update
+    constexpr int NBK = 64;
+    for (int64_t j = 0; j < k; j += NBK) {
+      const int nb = (int)(k - j < NBK ? k - j : NBK);
+      double* Ajj = M + j * k + j;
+      double* Dp = (double*)(ws + l.D);
+      KCHK(hipMemcpy2DAsync(Dp, sizeof(double) * nb, Ajj, sizeof(double) * k, sizeof(double) * nb, nb,
+                            hipMemcpyDeviceToDevice, s));
+      launch_dense_chol(s, Dp, nb, bad);
+      KCHK(hipMemcpy2DAsync(Ajj, sizeof(double) * k, Dp, sizeof(double) * nb, sizeof(double) * nb, nb,
+                            hipMemcpyDeviceToDevice, s));
+      const int64_t rest = k - j - nb;
+      if (rest > 0) {
+        double* Aij = M + j * k + j + nb;            // rows below the block, its columns
+        KBCHK(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                            rocblas_diagonal_non_unit, (rocblas_int)rest, nb, &one, Ajj, (rocblas_int)k, Aij,
+                            (rocblas_int)k));
+        const double mone = -1.0;
+        KBCHK(rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, (rocblas_int)rest, nb, &mone, Aij,
+                            (rocblas_int)k, &one, M + (j + nb) * k + j + nb, (rocblas_int)k));
+      }
+    }
   }
   // z = P^{-1} v
   auto precond = [&](const double* v, double* out) -> arpc_status {
