@@ -104,6 +104,9 @@ Layout layout_of(const arpc_problem& p) {
   l.C0 = take(l.dist ? es * p.N * p.b : 0);
   l.P = take(sizeof(double) * nparts * p.N);
   l.Xq = take(p.prec == ARPC_FP8 ? sizeof(double) * p.N * p.d : 0);
+  l.packed = p.prec == ARPC_FP8 && l.dist && p.d % 4 == 0;   // e4m3 codes for the distance kernel
+  l.X8 = take(l.packed ? (size_t)p.N * p.d : 0);
+  l.xn8 = take(l.packed ? sizeof(float) * p.N : 0);
   l.trace = take(sizeof(double));
   l.total = off;
   return l;
@@ -159,7 +162,8 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   launch_propose(s, u, csum, cpre, nch, N, b, un, st, props);
   prof.end();
   MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
-               (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k, l.dist ? (void*)(ws + l.C0) : nullptr};
+               (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k, l.dist ? (void*)(ws + l.C0) : nullptr,
+               l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr};
   prof.begin(ARPC_KC_GATHER);
   launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, (double*)(ws + l.Hp), H, st);
   prof.end();
@@ -249,6 +253,8 @@ struct Job final : JobBase {
     HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
     prof->begin(ARPC_KC_INIT);
     if (p.prec == ARPC_FP8) launch_round_e4m3(s, Xin, (double*)(ws + l.Xq), p.N * p.d);
+    if (l.packed)
+      launch_pack_e4m3(s, (const double*)(ws + l.Xq), p.N, (int)p.d, (unsigned*)(ws + l.X8), (float*)(ws + l.xn8));
     launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, p.N, (int)p.d, kp, st, nch);
     prof->end();
     HIPCHK(hipGetLastError());

@@ -31,6 +31,9 @@ struct MfmaRound {
   int64_t kmax;
   void* C0;                // kernel columns for d > 16 (FP64 in the FP64 mode, else FP32; N x b
                            // column-major), or null
+  const unsigned* X8;      // FP8 mode with d % 4 == 0: the rounded points as e4m3 codes (N x d
+                           // bytes, row-major), or null
+  const float* xn8;        // their squared norms (FP32), or null
 };
 
 // Device pointers and sizes of the one-kernel round product of the BF16
@@ -68,6 +71,9 @@ void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const Roun
 // Kernel columns on the matrix cores for d > 16 (into r.C0, read by the
 // update GEMM's epilogue).
 bool mfma_dist_contraction(int d);
+// X8 = e4m3 codes of the (already rounded) points Xq, xn = their squared
+// norms in FP32; d % 4 == 0.
+void launch_pack_e4m3(hipStream_t s, const double* Xq, int64_t N, int d, unsigned* X8, float* xn);
 void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
 void launch_mfma_trsm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
 void launch_prep_xp(hipStream_t s, const int32_t* acc, const int64_t* props, const double* X, int d,

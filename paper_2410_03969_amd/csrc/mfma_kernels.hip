@@ -658,6 +658,154 @@ __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int 
   }
 }
 
+// The FP8 mode's packed points: one wavefront per row, four dims per lane
+// per step (the values are on the e4m3 grid, so the conversion is exact);
+// the squared norm is summed in FP32 from the same values.
+__global__ __launch_bounds__(256) void k_pack_e4m3(const double* __restrict__ Xq, int64_t N, int d,
+                                                   unsigned* __restrict__ X8, float* __restrict__ xn) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int dw = d / 4;
+  const double* x = Xq + row * d;
+  float s = 0.f;
+  for (int q = lane; q < dw; q += 64) {
+    const double v0 = x[4 * q], v1 = x[4 * q + 1], v2 = x[4 * q + 2], v3 = x[4 * q + 3];
+    int pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)v0, (float)v1, 0, false);
+    pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)v2, (float)v3, pk, true);
+    X8[row * dw + q] = (unsigned)pk;
+    s += (float)v0 * (float)v0 + (float)v1 * (float)v1 + (float)v2 * (float)v2 + (float)v3 * (float)v3;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) xn[row] = s;
+}
+
+// k_dist for the FP8 mode when d % 4 == 0: the rows are staged from the
+// packed e4m3 codes (4 bytes per lane per pass instead of 32, prefetched one
+// chunk ahead while the current chunk's products run) with their norms from
+// the packed norms; the pivot columns are staged from their FP64 copy as in
+// k_dist.  Tile order, operand slots and the epilogue are those of k_dist.
+__global__ __launch_bounds__(256) void k_dist_f8b(const double* __restrict__ X, int d,
+                                                  const unsigned* __restrict__ X8, const float* __restrict__ xn8,
+                                                  const double* __restrict__ Xp, KFast kf, float* __restrict__ C0,
+                                                  int64_t N, int ncb, const RoundState* st) {
+  if (st->status != ST_RUNNING) return;
+  constexpr int CT = 4, DC = 32, NC = 16 * CT, LPR = DC / 4, RPP = 256 / LPR, NPR = 256 / RPP;
+  constexpr int NPC = (NC + RPP - 1) / RPP;
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  const int s = st->s_r;
+  const int64_t ntile = (N + 255) / 256 * ncb, per = (ntile + 7) / 8;
+  const int64_t t = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (t >= ntile) return;
+  const int64_t rb = t / ncb;
+  const int c0 = (int)(t % ncb) * NC;
+  if (c0 >= s) return;
+  __shared__ __attribute__((aligned(16))) unsigned rowsL[256 * DC / 4];
+  __shared__ __attribute__((aligned(16))) unsigned char colsL[NC * DC];
+  __shared__ float xnl[256], ynl[NC];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int sl = tid % LPR, sr = tid / LPR;
+  const int64_t r0 = rb * 256;
+  const int dw = d / 4;
+  {
+    const int64_t row = r0 + tid;
+    xnl[tid] = xn8[row < N ? row : N - 1];
+  }
+  const unsigned* sx[NPR];
+  const double* sc[NPC];
+#pragma unroll
+  for (int p = 0; p < NPR; ++p) {
+    const int64_t row = r0 + RPP * p + sr;
+    sx[p] = X8 + (row < N ? row : N - 1) * dw + sl;
+  }
+#pragma unroll
+  for (int p = 0; p < NPC; ++p) {
+    const int c = c0 + RPP * p + sr;
+    sc[p] = Xp + (int64_t)(c < s ? c : s - 1) * d + 4 * sl;
+  }
+  float ny[NPC];
+#pragma unroll
+  for (int p = 0; p < NPC; ++p) ny[p] = 0.f;
+  V4 acc[CT][4];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[ct][q] = V4{0, 0, 0, 0};
+  unsigned vr[NPR];
+  double vc[NPC][4];
+  auto load = [&](int k0) __attribute__((always_inline)) {
+    const bool in = k0 + 4 * sl < d;   // whole 4-dim groups (d % 4 == 0)
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) vr[p] = in ? sx[p][k0 / 4] : 0u;
+#pragma unroll
+    for (int p = 0; p < NPC; ++p)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vc[p][j] = in ? sc[p][k0 + j] : 0.0;
+  };
+  load(0);
+  for (int k0 = 0; k0 < d; k0 += DC) {
+    __syncthreads();   // the previous chunk's operands are consumed
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) rowsL[(RPP * p + sr) * (DC / 4) + sl] = vr[p];
+#pragma unroll
+    for (int p = 0; p < NPC; ++p)
+      if (RPP * p + sr < NC) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ny[p] += (float)vc[p][j] * (float)vc[p][j];
+        int pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)vc[p][0], (float)vc[p][1], 0, false);
+        pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)vc[p][2], (float)vc[p][3], pk, true);
+        *(int*)(colsL + (RPP * p + sr) * DC + 4 * sl) = pk;
+      }
+    __syncthreads();
+    if (k0 + DC < d) load(k0 + DC);   // the next chunk, in flight during the products
+    long ap[CT], bp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      bp[q] = *(const long*)((const unsigned char*)rowsL + (64 * w + 16 * q + l16) * DC + 8 * g);
+#pragma unroll
+    for (int q = 0; q < CT; ++q) ap[q] = *(const long*)(colsL + (16 * q + l16) * DC + 8 * g);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+        acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ap[ct], bp[rt], acc[ct][rt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int m = 1; m < LPR; m <<= 1)
+#pragma unroll
+    for (int p = 0; p < NPC; ++p) ny[p] += __shfl_xor(ny[p], m, 64);
+  if (sl == 0)
+#pragma unroll
+    for (int p = 0; p < NPC; ++p)
+      if (RPP * p + sr < NC) ynl[RPP * p + sr] = ny[p];
+  __syncthreads();
+  const float frac = 0x1p-6f;
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const int rl = 64 * w + 16 * rt + l16;
+    const int64_t row = r0 + rl;
+    const float xn = xnl[rl];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = 4 * g + i;
+        const int c = c0 + 16 * ct + m;
+        const float y = ynl[16 * ct + m];
+        float r2 = xn + y - 2 * acc[ct][rt][i];
+        if (__builtin_expect(r2 < frac * (xn + y), 0))   // cancellation: direct differences
+          r2 = (float)sqdist(X + (row < N ? row : N - 1) * d, Xp + (int64_t)(c < s ? c : s - 1) * d, d);
+        if (c < s && row < N) C0[(int64_t)c * N + row] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
+      }
+  }
+}
+
+void launch_pack_e4m3(hipStream_t s, const double* Xq, int64_t N, int d, unsigned* X8, float* xn) {
+  hipLaunchKernelGGL(k_pack_e4m3, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, Xq, N, d, X8, xn);
+}
+
 // ------------------------------------------ small operands in chunk layout
 // Bm(k, c) = F(S_r(c), k) for the update GEMM (zero outside k < k_r, c < s_r).
 template <class Pol, int PASSES>
@@ -838,6 +986,9 @@ void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* 
   const dim3 grid((unsigned)((nrb * ncb + 7) / 8 * 8));   // every XCD range complete (see k_dist)
   if (prec == 0)
     hipLaunchKernelGGL(k_dist<DIST_F64>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, kf, r.C0, r.N, ncb, st);
+  else if (prec == 4 && r.X8)
+    hipLaunchKernelGGL(k_dist_f8b, grid, dim3(256), 0, s, r.X, r.d, r.X8, r.xn8, r.Xp, kf, (float*)r.C0, r.N, ncb,
+                       st);
   else if (prec == 4)
     hipLaunchKernelGGL(k_dist<DIST_F8>, grid, dim3(256), 0, s, r.X, r.d, r.Xp, r.kp, kf, r.C0, r.N, ncb, st);
   else

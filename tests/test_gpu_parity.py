@@ -337,13 +337,14 @@ def test_reduced_precision_trace_error(prec):
     assert tem <= 1.05 * te64 and nym <= 1.05 * ny64
 
 
-@pytest.mark.parametrize("d", [24, 40])
+@pytest.mark.parametrize("d", [24, 30, 40])
 def test_fp8_mode_factors_the_rounded_points(d):
     """The FP8 mode factors the kernel matrix of the points rounded to e4m3:
     its factor matches the FP64 factor of its pivots on round_e4m3(X) to the
     BF16 update's accuracy, and is clearly further from that of the unrounded
     points.  Coordinates reach (240, 448] (OCP e4m3 only) and beyond 448
-    (saturation); d = 24 and 40 leave a ragged 32-wide contraction step."""
+    (saturation); d = 24 and 40 leave a ragged 32-wide contraction step (packed
+    e4m3 rows), d = 30 takes the unpacked path (d not a multiple of 4)."""
     rng = np.random.default_rng(d)
     N = 4000
     X = 100.0 * rng.standard_normal((N, d))
