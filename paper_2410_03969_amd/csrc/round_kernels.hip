@@ -414,24 +414,30 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
 // lower triangle, J >= L, belongs to tile wavefront t mod 7; entry i of lane
 // (g, n) is row 16 J + g + 4 i, column 16 L + n: the layout of the FP64
 // 16x16x4 product's accumulator).  The proposals are taken 16 at a time
-// (block column I):
+// (block column I), in this order in the GT form below:
 //  1. the tile wavefronts finish the previous block's update on block column
 //     I and copy it to LDS;
 //  2. wavefront 0 runs the tests of Alg. 1 on the diagonal block while the
 //     tile wavefronts apply the previous block's update to the rest of the
 //     trailing tiles;
 //  3. the panel below the block is solved against the accepted columns as a
-//     product with the inverse of their factor (formed by wavefront 0 with
+//     product with the inverse of their factor, X (formed by wavefront 0 with
 //     the tests), four matrix-core products per tile;
 //  4. (at the next block) the trailing tiles receive the rank-16 update on
 //     the matrix cores, four products per tile (rejected columns are zero).
-// Three barriers per 16 proposals; the block-column buffer is double-buffered
-// so a block's copy does not overwrite the previous panel while it is still
-// being applied.  The scaled column of proposal i goes to column i of H (no
-// longer read once in registers), where the solve's preparation reads it.
+// The register-resident form defers 3 and 4 of block I - 1 into block I
+// (look-ahead): before block I's tests only the panel row P_I and the
+// diagonal tile (I, I) are computed; the rest of the panel runs beside the
+// first half of the tests and the rest of the update beside the second half
+// (X double-buffered, barriers on LDS only).  The block-column buffer is
+// double-buffered so a block's copy does not overwrite the previous panel
+// while it is still being applied.  The scaled column of proposal i goes to
+// column i of H (no longer read once in registers), where the solve's
+// preparation reads it.
 // For 256 < b <= 512 the triangle (up to 528 tiles, 1 MiB) does not fit the
 // register file; the GT form keeps the trailing tiles in H and streams them
-// through the same steps (wavefront 0 and the LDS side unchanged).
+// through steps 1-4 (three full barriers per block; there the trailing
+// update, not the tests, sets the pace, so the look-ahead gains nothing).
 constexpr int RT = 16;                  // tile edge
 constexpr int REJECT_T_THREADS = 512;
 constexpr int REJECT_T_BMAX = 256;
