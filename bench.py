@@ -231,7 +231,7 @@ def run_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.serving:
         return run_serving(args)
