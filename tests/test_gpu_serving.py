@@ -20,9 +20,10 @@ pytestmark = pytest.mark.gpu
 def _jobs():
     """Twelve jobs shaped like the serving stream (points uniform on [0,1]^d,
     Gaussian kernel with bandwidth sqrt(d), b = k/10), small enough for a test,
-    over every precision mode and both round-product paths."""
+    over every precision mode (FP8 included), both round-product paths and
+    both pivot rules (jobs 5 and 11 run block RPCholesky)."""
     rng = np.random.default_rng(4)
-    precs = [W.BF16X3, W.BF16, W.FP64, W.FP32]
+    precs = [W.BF16X3, W.BF16, W.FP64, W.FP32, W.FP8]
     out = []
     for j in range(12):
         N = int(round(10 ** rng.uniform(3.3, 4.3)))
@@ -31,7 +32,7 @@ def _jobs():
         b = max(1, k // 10)
         X = np.random.default_rng(1000 + j).random((N, d))
         prob = W.Problem(N=N, d=d, k=k, b=b, kernel=W.GAUSSIAN, sigma=float(np.sqrt(d)), seed=j,
-                         prec=precs[j % len(precs)])
+                         prec=precs[j % len(precs)], method=W.BLOCK if j % 6 == 5 else W.ACCEL)
         out.append((X, prob))
     return out
 
@@ -54,7 +55,7 @@ def test_results_same_alone_and_in_the_mix(monkeypatch, graphs):
     jobs = _jobs()
     alone = []
     for X, prob in jobs:
-        _log(f"[serving alone] N={prob.N} d={prob.d} k={prob.k} b={prob.b} prec={prob.prec}")
+        _log(f"[serving alone] N={prob.N} d={prob.d} k={prob.k} b={prob.b} prec={prob.prec} method={prob.method}")
         alone.append(_alone(X, prob))
     ws = [binding.arpc_workspace_size(binding.make_problem(p)) for _, p in jobs]
     budget = int(2.5 * max(ws))   # a few jobs at a time: the rest wait for memory
