@@ -903,25 +903,31 @@ static void launch_panel(hipStream_t s, const MfmaRound& r, const RoundState* st
 }
 
 // Column blocks per workgroup (the accumulators of one wavefront are NB x NCB
-// tiles).  Four blocks keep a wavefront within 256 registers, so two
-// wavefronts share each SIMD and one hides the other's HBM latency; wider
-// groups read F fewer times but drop to one wavefront per SIMD, which costs
-// more than the extra L2 reads.  ARPC_NCB=4|7|8|13 overrides the choice.
-inline int ncb_for(int ncb_tot) {
+// tiles).  Groups that keep two wavefronts on each SIMD (one hides the other's
+// HBM latency) are four blocks wide, or five where that takes fewer groups:
+// every group reads the whole panel of its left operand.  Five blocks fit
+// the register budget except in the three-pass BF16 product; in the solve
+// they paid off only in FP64 (the FP32 and BF16 solves carry less per byte).
+// Wider groups (7, 8, 13 blocks) read F fewer times but run one wavefront per
+// SIMD, which costs more than the extra L2 reads.  ARPC_NCB=4|5|7|8|13
+// overrides the choice for both products.  `prec` is the product's precision
+// (0 FP64, 1 FP32, 2 BF16x3, 3 BF16), `which` 0 the column product, 1 the solve.
+inline int ncb_for(int prec, int which, int ncb_tot) {
   static int forced = -1;
   if (forced < 0) {
     const char* e = getenv("ARPC_NCB");
     forced = e ? atoi(e) : 0;
   }
-  if (forced == 4 || forced == 7 || forced == 8 || forced == 13) return forced;
-  (void)ncb_tot;
-  return 4;
+  if (forced == 4 || forced == 5 || forced == 7 || forced == 8 || forced == 13) return forced;
+  const bool five = which == 0 ? prec != 2 : prec == 0;
+  return five && (ncb_tot + 4) / 5 < (ncb_tot + 3) / 4 ? 5 : 4;
 }
 
 template <class Pol, int PASSES>
-static void dispatch(hipStream_t s, const MfmaRound& r, const RoundState* st, int which) {
-  switch (ncb_for(r.Ctot / 16)) {
+static void dispatch(hipStream_t s, const MfmaRound& r, const RoundState* st, int prec, int which) {
+  switch (ncb_for(prec, which, r.Ctot / 16)) {
     case 4: launch_panel<Pol, PASSES, 4>(s, r, st, which); break;
+    case 5: launch_panel<Pol, PASSES, 5>(s, r, st, which); break;
     case 7: launch_panel<Pol, PASSES, 7>(s, r, st, which); break;
     case 8: launch_panel<Pol, PASSES, 8>(s, r, st, which); break;
     default: launch_panel<Pol, PASSES, 13>(s, r, st, which); break;
@@ -956,8 +962,8 @@ size_t mfma_operand_bytes(int prec, int64_t kmax, int b) {
 }
 
 int mfma_part_cols(int prec, int b) {
-  (void)prec;
-  return 16 * ncb_for((b + 15) / 16);
+  // the solve writes one partial sum of squares per column group
+  return 16 * ncb_for(prec, 1, (b + 15) / 16);
 }
 
 size_t mfma_blocked_bytes(int prec, int64_t N, int64_t cols) {
@@ -997,19 +1003,19 @@ void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* 
 
 void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
   switch (prec) {
-    case 0: dispatch<Pol64, 1>(s, r, st, 0); break;
-    case 1: dispatch<Pol32, 1>(s, r, st, 0); break;
-    case 2: dispatch<PolBF<3>, 3>(s, r, st, 0); break;
-    default: dispatch<PolBF<1>, 1>(s, r, st, 0); break;
+    case 0: dispatch<Pol64, 1>(s, r, st, 0, 0); break;
+    case 1: dispatch<Pol32, 1>(s, r, st, 1, 0); break;
+    case 2: dispatch<PolBF<3>, 3>(s, r, st, 2, 0); break;
+    default: dispatch<PolBF<1>, 1>(s, r, st, 3, 0); break;
   }
 }
 
 void launch_mfma_trsm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
   switch (prec) {
-    case 0: dispatch<Pol64, 1>(s, r, st, 1); break;
-    case 1: dispatch<Pol32, 1>(s, r, st, 1); break;
-    case 2: dispatch<PolBF<3>, 3>(s, r, st, 1); break;
-    default: dispatch<PolBF<1>, 1>(s, r, st, 1); break;
+    case 0: dispatch<Pol64, 1>(s, r, st, 0, 1); break;
+    case 1: dispatch<Pol32, 1>(s, r, st, 1, 1); break;
+    case 2: dispatch<PolBF<3>, 3>(s, r, st, 2, 1); break;
+    default: dispatch<PolBF<1>, 1>(s, r, st, 3, 1); break;
   }
 }
 
