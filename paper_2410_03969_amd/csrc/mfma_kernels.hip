@@ -464,6 +464,42 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
 // 16x16x4, slot j of lane group g in dim group q is dim 16 q + 4 g + j.
 enum { DIST_F64 = 0, DIST_F32 = 1, DIST_F8 = 2 };
 
+// Column-major store of a wavefront's 64 x 16 FP32 tile of C0 (rows
+// row0 .. + 63, columns cbase .. + 15) through its LDS window (16 columns of
+// 68 floats): lane (g, l16) holds entry (row 16 rt + l16, column 4 g + i) as
+// v[rt][i].  Written back as 16-byte runs of one column per lane, a store
+// instruction covers 256-byte pieces of four columns, where storing the
+// accumulator entries directly covers 64-byte pieces at 4 bytes per lane.
+// The window is the wavefront's own, so no barrier is needed: its LDS writes
+// and reads run in program order.  vec: N % 4 == 0, so every run is aligned.
+__device__ __attribute__((always_inline)) inline void store_tile_cols(float* win, const float (&v)[4][4], int g,
+                                                                      int l16, int lane, float* __restrict__ C0,
+                                                                      int64_t N, int64_t row0, int cbase, int s,
+                                                                      bool vec) {
+  constexpr int WS = 68;   // window column stride: 64 rows + one run of padding, runs stay 16-byte aligned
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) win[(4 * g + i) * WS + 16 * rt + l16] = v[rt][i];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = 64 * q + lane;
+    const int col = idx >> 4, rr = 4 * (idx & 15);
+    const int c = cbase + col;
+    const int64_t row = row0 + rr;
+    if (c >= s) continue;
+    const float* src = win + col * WS + rr;
+    float* dst = C0 + (int64_t)c * N + row;
+    if (vec && row + 4 <= N) {
+      *(float4*)dst = *(const float4*)src;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (row + j < N) dst[j] = src[j];
+    }
+  }
+}
+
 template <int DM>
 struct DistCfg {   // FP32
   typedef float T;      // accumulator and norms
@@ -632,15 +668,24 @@ __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int 
     for (int p = 0; p < NPC; ++p)
       if (RPP * p + sr < NC) ynl[RPP * p + sr] = ny[p];
   }
-  __syncthreads();
+  __syncthreads();   // also: every wavefront is done with rowsL, which holds the store windows
   const T frac = DM == DIST_F64 ? (T)0x1p-10 : (T)0x1p-6;
+  // FP32 results go through a store window (FP32 mode: overlaying rowsL);
+  // the FP64 accumulator layout already stores whole 128-byte lines, and the
+  // window pass measured slower there
+  constexpr int WIN = 4 * 16 * 68 * 4;
+  static_assert(DM == DIST_F64 || WIN <= (int)sizeof(rowsL) || DM == DIST_F8, "store windows overlay rowsL");
+  __shared__ __attribute__((aligned(16))) unsigned char winL[DM == DIST_F8 ? WIN : 16];
+  T* win = (DM == DIST_F8 ? (T*)winL : (T*)rowsL) + w * 16 * 68;
+  const bool vec = N % 4 == 0;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    const int rl = 64 * w + 16 * rt + l16;
-    const int64_t row = r0 + rl;
-    const T xn = xnl[rl];
+  for (int ct = 0; ct < CT; ++ct) {
+    T v[4][4];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+    for (int rt = 0; rt < 4; ++rt) {
+      const int rl = 64 * w + 16 * rt + l16;
+      const int64_t row = r0 + rl;
+      const T xn = xnl[rl];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         // accumulator entry i of lane (g, l16): column 16 ct + m, row l16 of the tile
@@ -650,11 +695,22 @@ __global__ __launch_bounds__(256) void k_dist(const double* __restrict__ X, int 
         T r2 = xn + y - 2 * acc[ct][rt][i];
         if (__builtin_expect(r2 < frac * (xn + y), 0))   // cancellation: direct differences
           r2 = (T)sqdist(X + (row < N ? row : N - 1) * d, Xp + (int64_t)(c < s ? c : s - 1) * d, d);
-        if (c < s && row < N) {
-          if constexpr (DM == DIST_F64) C0[(int64_t)c * N + row] = kappa_r2(r2, kp);
-          else C0[(int64_t)c * N + row] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
-        }
+        if constexpr (DM == DIST_F64) v[rt][i] = kappa_r2(r2, kp);
+        else v[rt][i] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
       }
+    }
+    if constexpr (DM == DIST_F64) {
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = c0 + 16 * ct + g + 4 * i;
+          const int64_t row = r0 + 64 * w + 16 * rt + l16;
+          if (c < s && row < N) C0[(int64_t)c * N + row] = v[rt][i];
+        }
+    } else {
+      store_tile_cols(win, v, g, l16, lane, C0, N, r0 + 64 * w, c0 + 16 * ct, s, vec);
+    }
   }
 }
 
@@ -782,13 +838,17 @@ __global__ __launch_bounds__(256) void k_dist_f8b(const double* __restrict__ X, 
       if (RPP * p + sr < NC) ynl[RPP * p + sr] = ny[p];
   __syncthreads();
   const float frac = 0x1p-6f;
+  __shared__ __attribute__((aligned(16))) float winL[4 * 16 * 68];   // per-wavefront store windows
+  float* win = winL + w * 16 * 68;
+  const bool vec = N % 4 == 0;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    const int rl = 64 * w + 16 * rt + l16;
-    const int64_t row = r0 + rl;
-    const float xn = xnl[rl];
+  for (int ct = 0; ct < CT; ++ct) {
+    float v[4][4];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+    for (int rt = 0; rt < 4; ++rt) {
+      const int rl = 64 * w + 16 * rt + l16;
+      const int64_t row = r0 + rl;
+      const float xn = xnl[rl];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = 4 * g + i;
@@ -797,8 +857,10 @@ __global__ __launch_bounds__(256) void k_dist_f8b(const double* __restrict__ X, 
         float r2 = xn + y - 2 * acc[ct][rt][i];
         if (__builtin_expect(r2 < frac * (xn + y), 0))   // cancellation: direct differences
           r2 = (float)sqdist(X + (row < N ? row : N - 1) * d, Xp + (int64_t)(c < s ? c : s - 1) * d, d);
-        if (c < s && row < N) C0[(int64_t)c * N + row] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
+        v[rt][i] = kappa_fast(r2 > 0.f ? r2 : 0.f, kf);
       }
+    }
+    store_tile_cols(win, v, g, l16, lane, C0, N, r0 + 64 * w, c0 + 16 * ct, s, vec);
   }
 }
 

@@ -249,6 +249,27 @@ def test_fp32_mode_factor_consistent_with_its_pivots():
     assert err < 1e-4, err
 
 
+@pytest.mark.parametrize("d", [40, 70])
+def test_high_dimension_fp32_ragged_rows(d):
+    """d > 16 in FP32: kernel columns from the FP32 matrix-core distance
+    kernel, stored through its per-wavefront window; N = 3001 leaves a last
+    row tile whose 16-byte runs stop short of N, and rows not a multiple of
+    four.  The factor equals the FP64 factor of its own pivots to FP32
+    accuracy, the last rows included."""
+    rng = np.random.default_rng(d)
+    N = 3001
+    X = rng.standard_normal((N, d))
+    prob = W.Problem(N=N, d=d, k=300, b=100, kernel=W.MATERN32, sigma=4.0, seed=d, prec=W.FP32)
+    F, piv, out = gpu_factor(X, prob)
+    assert out["stats"]["fused"] == 0
+    assert out["stats"]["k_out"] == prob.k and len(set(piv.tolist())) == prob.k
+    rows = np.concatenate([np.random.default_rng(1).choice(N - 8, 200, replace=False), np.arange(N - 8, N)])
+    ref = factor_from_pivots(PointsAccess(X, prob.kernel, prob.sigma), piv[:150], rows=rows)
+    err = np.linalg.norm(F[rows, :150] - ref) / np.linalg.norm(ref)
+    print(f"fp32 d={d}: relF {err:.3e}")
+    assert err < 1e-4, err
+
+
 def test_laplace_workload_full_size_fp64():
     """The N = 1e5, d = 20, k = 1000, b = 120 Laplace workload at full size."""
     X, prob = W.laplace()
@@ -344,9 +365,11 @@ def test_fp8_mode_factors_the_rounded_points(d):
     BF16 update's accuracy, and is clearly further from that of the unrounded
     points.  Coordinates reach (240, 448] (OCP e4m3 only) and beyond 448
     (saturation); d = 24 and 40 leave a ragged 32-wide contraction step (packed
-    e4m3 rows), d = 30 takes the unpacked path (d not a multiple of 4)."""
+    e4m3 rows), d = 30 takes the unpacked path (d not a multiple of 4).
+    N = 4001 at d = 24: the stored kernel columns end in a run short of four
+    rows."""
     rng = np.random.default_rng(d)
-    N = 4000
+    N = 4001 if d == 24 else 4000
     X = 100.0 * rng.standard_normal((N, d))
     X[0, 0], X[1, 1], X[2, 2] = 1000.0, -460.0, 300.0
     prob = W.Problem(N=N, d=d, k=300, b=60, kernel=W.GAUSSIAN, sigma=60.0 * np.sqrt(d), seed=d, prec=W.FP8)
