@@ -462,6 +462,9 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
 // multiplies rows 64 w .. 64 w + 63 (four row tiles) by all column tiles.
 // Operand slots: FP8, byte j of lane group g is dim 8 g + j of the chunk;
 // 16x16x4, slot j of lane group g in dim group q is dim 16 q + 4 g + j.
+// The kernel values leave one 16-column tile at a time: FP32 ones through
+// the wavefront's LDS window (store_tile_cols), FP64 ones straight from the
+// accumulators, whose layout already covers whole 128-byte lines.
 enum { DIST_F64 = 0, DIST_F32 = 1, DIST_F8 = 2 };
 
 // Column-major store of a wavefront's 64 x 16 FP32 tile of C0 (rows
