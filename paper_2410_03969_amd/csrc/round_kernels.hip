@@ -225,6 +225,8 @@ __global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(
 }
 
 // ------------------------------------------------------- gathers at proposals
+typedef double rd4 __attribute__((ext_vector_type(4)));
+
 // Fs(i, c) = F(props_i, c) in FP64, row-major with leading dimension ldf.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ F, int64_t N,
@@ -241,35 +243,64 @@ __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ F, in
 
 // H = A(S',S') - F(S',:) F(S',:)^T (Alg. 2 step 2), FP64, column-major b x b
 // (ld = b), in two launches.  First the product, split along the contraction
-// index into partitions of W columns: workgroup (x, y, p) forms the 16 x 16
-// tile (x, y) of partition p's partial product (F rows staged through LDS)
-// into Hp(p).  The split keeps enough workgroups busy at any k_r; each tile
-// is summed in one fixed order, so H is symmetric and reproducible.
+// index into partitions of W columns, on the FP64 matrix cores: workgroup
+// (x, y, p) with x <= y forms the 16 x 16 tile of rows 16 y .., columns
+// 16 x .. of partition p's partial product and writes it and its transpose
+// into Hp(p) (workgroups above the diagonal have nothing to do).  Wavefront w
+// contracts the 16-column chunks w, w + 4, .. of the partition as four
+// 16x16x4 products (lane (g, l16) holds row l16 at column c + 4 g + m of
+// product m); the four partial tiles are then added in wavefront order, so
+// the result does not depend on scheduling, and a diagonal tile takes every
+// entry from its lower half, so each Hp(p), and H, is exactly symmetric.
+// The split keeps enough workgroups busy at any k_r.
 __global__ __launch_bounds__(256) void k_gather_Hp(int b, const double* __restrict__ Fs, int64_t ldf, int64_t W,
                                                    double* __restrict__ Hp, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
+  const int x = blockIdx.x, y = blockIdx.y;
+  if (x > y) return;
   const int64_t kr = st->k_r;
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
-  const int i = i0 + ty, j = j0 + tx;
+  const int i0 = 16 * y, j0 = 16 * x;
   const int64_t cbeg = (int64_t)blockIdx.z * W;
   const int64_t cend = (cbeg + W < kr) ? cbeg + W : kr;
-  double acc = 0.0;
-  for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
-    for (int q = threadIdx.x; q < 16 * 64; q += 256) {
-      const int r = q >> 6, cc = q & 63;
-      const int64_t c = c0 + cc;
-      As[r][cc] = (i0 + r < b && c < cend) ? Fs[(int64_t)(i0 + r) * ldf + c] : 0.0;
-      Bs[r][cc] = (j0 + r < b && c < cend) ? Fs[(int64_t)(j0 + r) * ldf + c] : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const bool ai = i0 + l16 < b, bj = j0 + l16 < b;
+  const double* ar = Fs + (int64_t)(ai ? i0 + l16 : 0) * ldf;
+  const double* br = Fs + (int64_t)(bj ? j0 + l16 : 0) * ldf;
+  rd4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = cbeg + 16 * w; c < cend; c += 64) {
+    double av[4], bv[4];
+    if (c + 16 <= cend) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        av[m] = ai ? ar[c + 4 * g + m] : 0.0;
+        bv[m] = bj ? br[c + 4 * g + m] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int64_t k = c + 4 * g + m;
+        av[m] = (ai && k < cend) ? ar[k] : 0.0;
+        bv[m] = (bj && k < cend) ? br[k] : 0.0;
+      }
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int cc = 0; cc < 64; ++cc) acc += As[ty][cc] * Bs[tx][cc];
-    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[m], acc, 0, 0, 0);
   }
-  if (i < b && j < b) Hp[(int64_t)blockIdx.z * b * b + (int64_t)j * b + i] = acc;
+  // entry e of lane (g, l16): row 16 y + g + 4 e, column 16 x + l16
+  __shared__ double red[4][16][17];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[w][g + 4 * e][l16] = acc[e];
+  __syncthreads();
+  const int r = tid >> 4, cc = tid & 15;
+  const bool up = x == y && cc > r;
+  const int rr = up ? cc : r, ck = up ? r : cc;
+  const double v = ((red[0][rr][ck] + red[1][rr][ck]) + red[2][rr][ck]) + red[3][rr][ck];
+  const int i = i0 + r, j = j0 + cc;
+  if (i < b && j < b) {
+    double* hp = Hp + (int64_t)blockIdx.z * b * b;
+    hp[(int64_t)j * b + i] = v;
+    hp[(int64_t)i * b + j] = v;
+  }
 }
 
 // Second launch: H(i, j) = kappa(x_i, x_j) - sum over the partitions, in
@@ -446,7 +477,6 @@ constexpr int REJECT_T_TW = 7;          // tile wavefronts
 constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
 
-typedef double rd4 __attribute__((ext_vector_type(4)));
 
 // (J, L) of lower-triangular tile index t, given those of t - step (L may
 // start past J: it is carried into the following rows).
