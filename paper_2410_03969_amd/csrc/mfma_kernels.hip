@@ -311,8 +311,8 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
   // chunk parity; one barrier per chunk.  FP64 and FP32 products run it
   // straight-line: past the last chunk the loads repeat it (clamped index)
   // and the commit fills the LDS buffer no product reads again, so the waits
-  // before each commit count exactly the loads issued after the fetch (faster
-  // by 4-7% in FP64).  The BF16 products guard the last chunk's loads instead,
+  // before each commit count exactly the loads issued after the fetch (about
+  // 4% faster in FP64).  The BF16 products guard the last chunk's loads instead,
   // which measured faster for them.
   F fr[2][NB];
   if constexpr (Pol::KC == 16) {

@@ -477,7 +477,6 @@ constexpr int REJECT_T_TW = 7;          // tile wavefronts
 constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
 
-
 // (J, L) of lower-triangular tile index t, given those of t - step (L may
 // start past J: it is carried into the following rows).
 __device__ inline void tile_advance(int& J, int& L) {
