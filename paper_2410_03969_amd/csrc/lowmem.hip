@@ -32,8 +32,11 @@ namespace {
 constexpr int LM_KMAX = 4096;   // longest solution vector kept in LDS
 constexpr int LM_BMAX = 512;    // inverse factor of L_i by linv_column
 constexpr int LM_DMAX = 256;    // staged pivot coordinates in the row kernel
-constexpr int LM_JC = 32;       // pivots per staged chunk in the row kernel
-constexpr int LM_CG = 64;       // columns of G per workgroup in the row kernel
+constexpr int LM_JC = 16;       // pivots per staged chunk in the row kernel (a multiple of 4)
+constexpr int LM_CG = 64;       // columns of G per row-norm partial (the group width k_diag reads)
+constexpr int LM_CS = 192;      // columns of G per workgroup in the row kernel (three groups)
+
+typedef double rd4 __attribute__((ext_vector_type(4)));
 
 // Kt(j, c) = kappa(x_{S_j}, x_{S'_c}) for j < k_r, c < b: A(S, S'), column-major (ld ldk).
 __global__ __launch_bounds__(256) void k_lm_cross(const double* __restrict__ X, int d, KParams kp,
@@ -228,47 +231,58 @@ __global__ __launch_bounds__(256) void k_lm_z(const double* __restrict__ W, int6
 }
 
 // P(g, row) = |G(row, 64 g .. 64 g + 63)|^2, G(row, :) = sum_j kappa(x_row,
-// x_{S_j}) Z(j, :) over all k_r + s_r pivots.  One thread per row; the
-// pivots' coordinates and the workgroup's 64 columns of Z are staged through
-// LDS 32 pivots at a time.  XR: the row's coordinates in registers (d <= 16).
+// x_{S_j}) Z(j, :) over all k_r + s_r pivots, on the FP64 matrix cores.
+// Workgroup (x, y) takes rows 64 x .. 64 x + 63 (16 per wavefront) and the
+// LM_CS columns from LM_CS y; the pivots' coordinates and that slice of Z are
+// staged through LDS LM_JC pivots at a time.  Per step of four pivots, lane
+// (g, l16) evaluates kappa(x_{row l16}, x_{S_{j + g}}) once, in FP64 with
+// direct differences, and that value is the A operand of the slice's
+// 16x16x4 products with Z (B operand: lane (g, l16) holds Z(j + g, column
+// l16 of the tile)).  Accumulator entry i of lane (g, l16) is G(row g + 4 i,
+// column l16 of the tile); the squares of each 64-column group are summed
+// over its four tiles and then across the 16 lanes of a row.  XR: the row's
+// coordinates in registers (d <= 16).
 template <bool XR>
 __global__ __launch_bounds__(256) void k_lm_rows(const double* __restrict__ X, int d, KParams kp,
                                                  const double* __restrict__ XS, const double* __restrict__ Z,
                                                  int b, double* __restrict__ P, int64_t N, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
+  constexpr int CT = LM_CS / 16;   // column tiles of the slice
   const int s = st->s_r;
   const int kt = (int)st->k_r + s;
-  const int c0 = blockIdx.y * LM_CG;
+  const int c0 = blockIdx.y * LM_CS;
   if (s == 0 || c0 >= s) return;
-  const int nc = s - c0 < LM_CG ? s - c0 : LM_CG;
   __shared__ double xs[LM_JC * LM_DMAX];
-  __shared__ double zs[LM_JC][LM_CG];
-  const int tid = threadIdx.x;
-  const int64_t row = (int64_t)blockIdx.x * 256 + tid;
-  const double* xrow = X + (row < N ? row : N - 1) * d;
+  __shared__ double zs[LM_JC][LM_CS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;   // this wavefront's 16 rows
+  const int64_t myrow = row0 + l16;                          // the row whose kernel values this lane forms
+  const double* xrow = X + (myrow < N ? myrow : N - 1) * d;
   double xr[16];
   if constexpr (XR) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) xr[t] = t < d ? xrow[t] : 0.0;
   }
-  double acc[LM_CG];
+  rd4 acc[CT];
 #pragma unroll
-  for (int m = 0; m < LM_CG; ++m) acc[m] = 0.0;
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = rd4{0.0, 0.0, 0.0, 0.0};
   const int64_t nxs = (int64_t)kt * d;
   for (int j0 = 0; j0 < kt; j0 += LM_JC) {
-    __syncthreads();
+    __syncthreads();   // the previous chunk is consumed
     for (int e = tid; e < LM_JC * d; e += 256) {
       const int64_t q = (int64_t)j0 * d + e;
       xs[e] = q < nxs ? XS[q] : 0.0;
     }
-    for (int e = tid; e < LM_JC * LM_CG; e += 256) {
-      const int jj = e / LM_CG, m = e % LM_CG;
-      zs[jj][m] = (j0 + jj < kt && m < nc) ? Z[(int64_t)(j0 + jj) * b + c0 + m] : 0.0;
+    for (int e = tid; e < LM_JC * LM_CS; e += 256) {
+      const int jj = e / LM_CS, m = e % LM_CS;
+      zs[jj][m] = (j0 + jj < kt && c0 + m < s) ? Z[(int64_t)(j0 + jj) * b + c0 + m] : 0.0;
     }
     __syncthreads();
-    const int je = kt - j0 < LM_JC ? kt - j0 : LM_JC;
-    for (int jj = 0; jj < je; ++jj) {
-      const double* xp = xs + jj * d;
+    // pivots past kt have zero rows of Z (their coordinates are staged as 0,
+    // so their kernel values are finite)
+#pragma unroll 1
+    for (int q = 0; q < LM_JC / 4; ++q) {
+      const double* xp = xs + (4 * q + g) * d;
       double r2 = 0.0;
       if constexpr (XR) {
 #pragma unroll
@@ -285,14 +299,25 @@ __global__ __launch_bounds__(256) void k_lm_rows(const double* __restrict__ X, i
       }
       const double kv = kappa_r2(r2, kp);
 #pragma unroll
-      for (int m = 0; m < LM_CG; ++m) acc[m] = fma(kv, zs[jj][m], acc[m]);
+      for (int ct = 0; ct < CT; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, zs[4 * q + g][16 * ct + l16], acc[ct], 0, 0, 0);
     }
   }
-  if (row < N) {
-    double g2 = 0.0;
+  // |G(row, group)|^2 for the slice's 64-column groups
+  const int ng = (s + 63) / 64;
 #pragma unroll
-    for (int m = 0; m < LM_CG; ++m) g2 = fma(acc[m], acc[m], g2);
-    P[(int64_t)blockIdx.y * N + row] = g2;
+  for (int pg = 0; pg < LM_CS / 64; ++pg) {
+    const int gi = c0 / 64 + pg;   // group index in P
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int ct = 4 * pg; ct < 4 * pg + 4; ++ct) v = fma(acc[ct][i], acc[ct][i], v);
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+      const int64_t row = row0 + g + 4 * i;
+      if (l16 == 0 && gi < ng && row < N) P[(int64_t)gi * N + row] = v;
+    }
   }
 }
 
@@ -396,7 +421,7 @@ void lm_round(hipStream_t s, const arpc_problem& p, const KParams& kp, const Uni
                      st);
   prof.end();
   prof.begin(ARPC_KC_COLGEMM);
-  const dim3 grows((unsigned)((N + 255) / 256), (unsigned)((b + LM_CG - 1) / LM_CG));
+  const dim3 grows((unsigned)((N + 63) / 64), (unsigned)((b + LM_CS - 1) / LM_CS));
   if (d <= 16)
     hipLaunchKernelGGL(k_lm_rows<true>, grows, dim3(256), 0, s, X, d, kp, XS, Z, b, P, N, st);
   else
