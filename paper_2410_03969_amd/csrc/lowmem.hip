@@ -234,16 +234,17 @@ __global__ __launch_bounds__(256) void k_lm_z(const double* __restrict__ W, int6
 // x_{S_j}) Z(j, :) over all k_r + s_r pivots, on the FP64 matrix cores.
 // Workgroup (x, y) takes rows 64 x .. 64 x + 63 (16 per wavefront) and the
 // LM_CS columns from LM_CS y; the pivots' coordinates and that slice of Z are
-// staged through LDS LM_JC pivots at a time.  Per step of four pivots, lane
-// (g, l16) evaluates kappa(x_{row l16}, x_{S_{j + g}}) once, in FP64 with
-// direct differences, and that value is the A operand of the slice's
-// 16x16x4 products with Z (B operand: lane (g, l16) holds Z(j + g, column
-// l16 of the tile)).  Accumulator entry i of lane (g, l16) is G(row g + 4 i,
+// staged through LDS LM_JC pivots at a time, the next chunk's Z (and, for
+// d <= 16, coordinates) loaded into registers during the current one.  Per
+// step of four pivots, lane (g, l16) evaluates kappa(x_{row l16},
+// x_{S_{j + g}}) once, in FP64 with direct differences, and that value is the
+// A operand of the slice's 16x16x4 products with Z (B operand: lane (g, l16)
+// holds Z(j + g, column l16 of the tile)).  Accumulator entry i of lane (g, l16) is G(row g + 4 i,
 // column l16 of the tile); the squares of each 64-column group are summed
 // over its four tiles and then across the 16 lanes of a row.  XR: the row's
 // coordinates in registers (d <= 16).
 template <bool XR>
-__global__ __launch_bounds__(256) void k_lm_rows(const double* __restrict__ X, int d, KParams kp,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_lm_rows(const double* __restrict__ X, int d, KParams kp,
                                                  const double* __restrict__ XS, const double* __restrict__ Z,
                                                  int b, double* __restrict__ P, int64_t N, const RoundState* st) {
   if (st->status != ST_RUNNING) return;
@@ -267,17 +268,47 @@ __global__ __launch_bounds__(256) void k_lm_rows(const double* __restrict__ X, i
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) acc[ct] = rd4{0.0, 0.0, 0.0, 0.0};
   const int64_t nxs = (int64_t)kt * d;
+  // the next chunk is loaded into registers while the current one is used
+  constexpr int ZPT = LM_JC * LM_CS / 256;                // Z values per thread per chunk
+  constexpr int XPT = (LM_JC * 16 + 255) / 256;   // coordinates per thread (prefetched when d <= 16)
+  double zn[ZPT], xn[XPT];
+  auto fetch = [&](int j0) {
+#pragma unroll
+    for (int r = 0; r < ZPT; ++r) {
+      const int e = tid + 256 * r, jj = e / LM_CS, m = e % LM_CS;
+      zn[r] = (j0 + jj < kt && c0 + m < s) ? Z[(int64_t)(j0 + jj) * b + c0 + m] : 0.0;
+    }
+    if constexpr (XR) {
+#pragma unroll
+      for (int r = 0; r < XPT; ++r) {
+        const int e = tid + 256 * r;
+        const int64_t q = (int64_t)j0 * d + e;
+        xn[r] = (e < LM_JC * d && q < nxs) ? XS[q] : 0.0;
+      }
+    }
+  };
+  fetch(0);
   for (int j0 = 0; j0 < kt; j0 += LM_JC) {
     __syncthreads();   // the previous chunk is consumed
-    for (int e = tid; e < LM_JC * d; e += 256) {
-      const int64_t q = (int64_t)j0 * d + e;
-      xs[e] = q < nxs ? XS[q] : 0.0;
+#pragma unroll
+    for (int r = 0; r < ZPT; ++r) {
+      const int e = tid + 256 * r;
+      zs[e / LM_CS][e % LM_CS] = zn[r];
     }
-    for (int e = tid; e < LM_JC * LM_CS; e += 256) {
-      const int jj = e / LM_CS, m = e % LM_CS;
-      zs[jj][m] = (j0 + jj < kt && c0 + m < s) ? Z[(int64_t)(j0 + jj) * b + c0 + m] : 0.0;
+    if constexpr (XR) {
+#pragma unroll
+      for (int r = 0; r < XPT; ++r) {
+        const int e = tid + 256 * r;
+        if (e < LM_JC * d) xs[e] = xn[r];
+      }
+    } else {
+      for (int e = tid; e < LM_JC * d; e += 256) {
+        const int64_t q = (int64_t)j0 * d + e;
+        xs[e] = q < nxs ? XS[q] : 0.0;
+      }
     }
     __syncthreads();
+    if (j0 + LM_JC < kt) fetch(j0 + LM_JC);
     // pivots past kt have zero rows of Z (their coordinates are staged as 0,
     // so their kernel values are finite)
 #pragma unroll 1
