@@ -29,11 +29,27 @@ namespace {
 constexpr int KRR_DMAX = 128;   // staged coordinates: 64 points x d doubles in LDS
 constexpr int KRR_JC = 64;
 
-// out = (A + mu I) v, one thread per row.  XR: the row's coordinates in registers (d <= 16).
+constexpr int KRR_PARTS_MAX = 32;   // column partitions of the product with A
+
+// Column partitions for N rows: enough workgroups to fill the chip (one
+// thread per row gives only N / 256 of them), each partition at least one
+// staged chunk wide.
+inline int krr_parts(int64_t N) {
+  const int64_t rowblocks = (N + 255) / 256;
+  int64_t p = (2048 + rowblocks - 1) / rowblocks;
+  const int64_t pmax = (N + KRR_JC - 1) / KRR_JC;
+  if (p > pmax) p = pmax;
+  if (p > KRR_PARTS_MAX) p = KRR_PARTS_MAX;
+  return (int)(p < 1 ? 1 : p);
+}
+
+// part(y, i) = sum over columns j of partition y (W columns from W y) of
+// A(i, j) v(j), one thread per row.  XR: the row's coordinates in registers
+// (d <= 16).
 template <bool XR>
 __global__ __launch_bounds__(256) void k_krr_matvec(const double* __restrict__ X, int d, KParams kp,
-                                                    const double* __restrict__ v, double mu, int64_t N,
-                                                    double* __restrict__ out) {
+                                                    const double* __restrict__ v, int64_t N, int64_t W,
+                                                    double* __restrict__ part) {
   __shared__ double xs[KRR_JC * KRR_DMAX];
   __shared__ double vs[KRR_JC];
   const int tid = threadIdx.x;
@@ -45,16 +61,18 @@ __global__ __launch_bounds__(256) void k_krr_matvec(const double* __restrict__ X
     for (int t = 0; t < 16; ++t) xr[t] = t < d ? xrow[t] : 0.0;
   }
   double acc = 0.0;
-  for (int64_t j0 = 0; j0 < N; j0 += KRR_JC) {
+  const int64_t jbeg = (int64_t)blockIdx.y * W;
+  const int64_t jend = jbeg + W < N ? jbeg + W : N;
+  for (int64_t j0 = jbeg; j0 < jend; j0 += KRR_JC) {
     __syncthreads();
     const int64_t nq = (int64_t)KRR_JC * d;
     for (int64_t e = tid; e < nq; e += 256) {
       const int64_t q = j0 * d + e;
-      xs[e] = q < N * d ? X[q] : 0.0;
+      xs[e] = q < jend * d ? X[q] : 0.0;
     }
-    if (tid < KRR_JC) vs[tid] = j0 + tid < N ? v[j0 + tid] : 0.0;
+    if (tid < KRR_JC) vs[tid] = j0 + tid < jend ? v[j0 + tid] : 0.0;
     __syncthreads();
-    const int je = N - j0 < KRR_JC ? (int)(N - j0) : KRR_JC;
+    const int je = jend - j0 < KRR_JC ? (int)(jend - j0) : KRR_JC;
     for (int jj = 0; jj < je; ++jj) {
       const double* xp = xs + jj * d;
       double r2 = 0.0;
@@ -74,7 +92,18 @@ __global__ __launch_bounds__(256) void k_krr_matvec(const double* __restrict__ X
       acc = fma(kappa_r2(r2, kp), vs[jj], acc);
     }
   }
-  if (i < N) out[i] = fma(mu, v[i], acc);
+  if (i < N) part[(int64_t)blockIdx.y * N + i] = acc;
+}
+
+// out = (A + mu I) v: the partitions' sums added in partition order.
+__global__ __launch_bounds__(256) void k_krr_sum(const double* __restrict__ part, int parts,
+                                                 const double* __restrict__ v, double mu, int64_t N,
+                                                 double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0.0;
+  for (int p = 0; p < parts; ++p) acc += part[(int64_t)p * N + i];
+  out[i] = fma(mu, v[i], acc);
 }
 
 // out(i) = a * x(i) + c * y(i)
@@ -99,7 +128,7 @@ __global__ void k_krr_add_diag(double* __restrict__ M, int k, double mu) {
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct KrrLayout {
-  size_t Fd, M, D, t, r, z, p, q, bad, total;
+  size_t Fd, M, D, t, r, z, p, q, part, bad, total;
 };
 
 KrrLayout krr_layout(int64_t N, int64_t k, bool convert) {
@@ -118,6 +147,7 @@ KrrLayout krr_layout(int64_t N, int64_t k, bool convert) {
   l.z = take(sizeof(double) * N);
   l.p = take(sizeof(double) * N);
   l.q = take(sizeof(double) * N);
+  l.part = take(sizeof(double) * krr_parts(N) * N);
   l.bad = take(sizeof(int));
   l.total = off;
   return l;
@@ -226,11 +256,15 @@ arpc_status krr_run(int64_t N, int64_t d, int32_t kernel, double bw, double mu, 
     hipLaunchKernelGGL(k_krr_axpby, dim3(gN), dim3(256), 0, s, 1.0 / mu, v, -1.0 / mu, out, out, N);
     return ARPC_OK;
   };
+  const int parts = krr_parts(N);
+  const int64_t pw = ((N + parts - 1) / parts + KRR_JC - 1) / KRR_JC * KRR_JC;   // columns per partition
+  double* part = (double*)(ws + l.part);
   auto matvec = [&](const double* v, double* out) {
     if (d <= 16)
-      hipLaunchKernelGGL(k_krr_matvec<true>, dim3(gN), dim3(256), 0, s, X, (int)d, kp, v, mu, N, out);
+      hipLaunchKernelGGL(k_krr_matvec<true>, dim3(gN, parts), dim3(256), 0, s, X, (int)d, kp, v, N, pw, part);
     else
-      hipLaunchKernelGGL(k_krr_matvec<false>, dim3(gN), dim3(256), 0, s, X, (int)d, kp, v, mu, N, out);
+      hipLaunchKernelGGL(k_krr_matvec<false>, dim3(gN, parts), dim3(256), 0, s, X, (int)d, kp, v, N, pw, part);
+    hipLaunchKernelGGL(k_krr_sum, dim3(gN), dim3(256), 0, s, part, parts, v, mu, N, out);
   };
   auto dot = [&](const double* a, const double* b, double* res) -> arpc_status {
     KBCHK(rocblas_ddot(h, (rocblas_int)N, a, 1, b, 1, res));   // host result: waits for the stream
