@@ -11,8 +11,10 @@ namespace arpc {
 // partial sum per chunk; the proposal kernel scans the chunk sums and then the
 // elements of a single chunk per draw.
 constexpr int CHUNK = 1024;
-// Largest block size whose b x b residual submatrix (lower triangle, FP64)
-// fits the 160 KiB of LDS of one gfx950 workgroup: 200*201/2*8 = 160800 bytes.
+// Largest block size.  The b x b residual submatrix is FP64 in global memory
+// (8 MiB at b = 1024); RejectionSampleSubmatrix keeps its trailing tiles in
+// registers for b <= 256, in L2 for b <= 512, and runs on the full matrix in
+// global memory above that (one workgroup of 1024 threads).
 constexpr int BMAX = 1024;
 
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_EARLY = 2, ST_NOUNIF = 3 };

@@ -390,7 +390,7 @@ template <class Store>
 __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, Unif un,
                             RoundState* st, int32_t* __restrict__ acc_out,
                             int64_t* __restrict__ pivots, double* __restrict__ u, int64_t kmax,
-                            int keep_all, unsigned char* tk, int* dec, short* accl) {
+                            int keep_all, unsigned char* tk, int* dec, short* accl, double* sqv) {
   const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
   const int64_t kr = st->k_r;
   const int64_t round = st->round;
@@ -414,11 +414,14 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
       const bool a = !dup && (uloc * V < h);
       tk[i] = (a || dup) ? 1 : 0;
       dec[i & 1] = a ? 1 : 0;
-      if (a) accl[nacc] = (short)i;
+      if (a) {
+        accl[nacc] = (short)i;
+        sqv[i & 1] = sqrt(h);   // every thread scales by this; H(i, i) itself is rewritten below
+      }
     }
     __syncthreads();
     if (!dec[i & 1]) continue;
-    const double sq = sqrt(S.at(i, i));
+    const double sq = sqv[i & 1];
     for (int j = i + tid; j < b; j += nthr) S.at(j, i) = S.at(j, i) / sq;
     __syncthreads();
     for (int l = i + 1 + w; l < b; l += nw) {
@@ -947,8 +950,9 @@ __global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, 
   __shared__ unsigned char tk[BMAX];
   __shared__ short accl[BMAX];
   __shared__ int dec[2];
+  __shared__ double sqv[2];
   FullGlobal S{H, b};
-  reject_body(S, b, props, un, st, acc_out, pivots, u, kmax, keep_all, tk, dec, accl);
+  reject_body(S, b, props, un, st, acc_out, pivots, u, kmax, keep_all, tk, dec, accl, sqv);
 }
 
 // --------------------------------------------------------- update preparation
