@@ -23,6 +23,6 @@ from .kernels import kappa, kernel_block  # noqa: F401
 from .fp8 import round_e4m3  # noqa: F401
 from .rpqr import orth, rpqr_accel  # noqa: F401
 from .krr import kernel_matvec, krr_pcg, pcg, woodbury_apply  # noqa: F401
-from .rpc import (PointsAccess, DenseAccess, rpc_accel, rpc_accel_lowmem, rpc_plain, rpc_block,  # noqa: F401
+from .rpc import (PointsAccess, ExpandedPointsAccess, DenseAccess, rpc_accel, rpc_accel_lowmem, rpc_plain, rpc_block,  # noqa: F401
                   reject_sample_submatrix, factor_from_pivots, nystrom_err,
                   draw_proposals)

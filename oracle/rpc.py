@@ -58,6 +58,33 @@ class PointsAccess:
         return kernel_block(self.X, slice(None), J, self.kernel, self.sigma)
 
 
+class ExpandedPointsAccess(PointsAccess):
+    """The same kernel matrix as PointsAccess, with squared distances formed as
+    |x|^2 + |y|^2 - 2 x.y (Appendix A.1), the dot products by one matrix
+    product, clamped at zero; an entry whose row and column are the same point
+    index is kappa(0) exactly.  A checker for pivot sets at sizes where direct
+    differences take minutes (tens of thousands of rows against thousands of
+    pivots at d = 256); its FP64 cancellation error is about
+    1e-16 (|x|^2 + |y|^2) per squared distance."""
+
+    def __init__(self, X, kernel: int, sigma: float):
+        super().__init__(X, kernel, sigma)
+        self.sq = np.einsum("ij,ij->i", self.X, self.X)
+
+    def block(self, I, J) -> np.ndarray:
+        I = np.arange(self.N)[I] if isinstance(I, slice) else np.asarray(I, dtype=np.int64)
+        J = np.arange(self.N)[J] if isinstance(J, slice) else np.asarray(J, dtype=np.int64)
+        r2 = self.sq[I][:, None] + self.sq[J][None, :] - 2.0 * (self.X[I] @ self.X[J].T)
+        np.maximum(r2, 0.0, out=r2)
+        out = kappa(r2, self.kernel, self.sigma)
+        same = I[:, None] == J[None, :]
+        out[same] = kappa(np.zeros(1), self.kernel, self.sigma)[0]
+        return out
+
+    def columns(self, J) -> np.ndarray:
+        return self.block(slice(None), J)
+
+
 class DenseAccess:
     """Submatrix access to an explicit psd matrix (lets tests use matrices
     whose diagonal is not constant)."""
@@ -88,6 +115,10 @@ class Result:
     u: np.ndarray            # final residual diagonal
     round_sizes: list = field(default_factory=list)
     u_history: list = field(default_factory=list)
+    # per round: (smallest relative distance of a proposal target U*T to the
+    # edges of its CDF interval, smallest |u_i V_i - h_ii| / u_i over the
+    # acceptance tests); how close each random decision came to flipping
+    margins: list = field(default_factory=list)
 
     @property
     def k_out(self) -> int:
@@ -100,30 +131,40 @@ class Result:
 
 
 # ------------------------------------------------------------ building blocks
-def draw_proposals(u: np.ndarray, U: np.ndarray):
+def draw_proposals(u: np.ndarray, U: np.ndarray, margin=None):
     """Inverse-CDF draws from the distribution u / sum(u) (Section 2.1 proposal
-    step; Alg. 2 step 1).  Returns (indices, total)."""
+    step; Alg. 2 step 1).  Returns (indices, total).  If ``margin`` is a list,
+    the smallest distance of a target U*T to the edges of its interval
+    [C_{s-1}, C_s), relative to the total, is appended to it."""
     C = np.cumsum(u)
     T = C[-1]
     s = np.searchsorted(C, U * T, side="right")
     if np.any(s >= u.size):
         last = np.flatnonzero(u > 0)[-1]
         s = np.where(s >= u.size, last, s)
+    if margin is not None:
+        t = U * T
+        lo = np.where(s > 0, C[np.maximum(s - 1, 0)], 0.0)
+        margin.append(float(np.min(np.minimum(np.abs(C[s] - t), np.abs(t - lo))) / T) if T > 0 else 0.0)
     return s.astype(np.int64), T
 
 
-def reject_sample_submatrix(H: np.ndarray, V: np.ndarray, proposals=None, cap=None):
+def reject_sample_submatrix(H: np.ndarray, V: np.ndarray, proposals=None, cap=None, margin=None):
     """RejectionSampleSubmatrix (Alg. 1, Section 2.2).
 
     H is the b x b residual submatrix at the proposals, V the b acceptance
     uniforms.  Returns (T, L): accepted local indices in order and the lower
-    Cholesky factor of the original H(T, T)."""
+    Cholesky factor of the original H(T, T).  If ``margin`` is a list, the
+    smallest |u_i V_i - h_ii| / u_i over the tests is appended to it."""
     H = np.array(H, dtype=np.float64, copy=True)
     b = H.shape[0]
     u_loc = np.diag(H).copy()
     L = np.zeros((b, b))
     T: list[int] = []
+    m = np.inf
     for i in range(b):
+        if u_loc[i] > 0 and (cap is None or len(T) < cap):
+            m = min(m, abs(u_loc[i] * V[i] - H[i, i]) / u_loc[i])
         accept = u_loc[i] * V[i] < H[i, i]
         if accept and cap is not None and len(T) >= cap:
             accept = False
@@ -133,6 +174,8 @@ def reject_sample_submatrix(H: np.ndarray, V: np.ndarray, proposals=None, cap=No
             T.append(i)
             L[i:, i] = H[i:, i] / np.sqrt(H[i, i])
             H[i + 1:, i + 1:] -= np.outer(L[i + 1:, i], L[i + 1:, i])
+    if margin is not None:
+        margin.append(float(m))
     T_arr = np.array(T, dtype=np.int64)
     return T_arr, L[np.ix_(T_arr, T_arr)]
 
@@ -148,10 +191,11 @@ def rpc_accel(access, k: int, b: int, stream, max_rounds=None, record=False) -> 
     S: list[int] = []
     r = 0
     status = "ok"
-    sizes, hist = [], []
+    sizes, hist, margins = [], [], []
     while len(S) < k and (max_rounds is None or r < max_rounds):
         words = stream(2 * b * r, 2 * b)
-        props, T = draw_proposals(u, words[:b]) if np.sum(u) > 0 else (None, 0.0)
+        mp, ma = [], []
+        props, T = draw_proposals(u, words[:b], margin=mp) if np.sum(u) > 0 else (None, 0.0)
         if not T > 0:
             status = "early_stop"
             break
@@ -159,7 +203,8 @@ def rpc_accel(access, k: int, b: int, stream, max_rounds=None, record=False) -> 
         # step 2: residual submatrix at the proposals, then rejection sampling
         Fp = F[props, :kr]
         H = access.block(props, props) - Fp @ Fp.T
-        Tacc, L = reject_sample_submatrix(H, words[b:], props, cap=k - kr)
+        Tacc, L = reject_sample_submatrix(H, words[b:], props, cap=k - kr, margin=ma)
+        margins.append((mp[0], ma[0]))
         r += 1
         sizes.append(int(Tacc.size))
         if Tacc.size == 0:
@@ -178,7 +223,7 @@ def rpc_accel(access, k: int, b: int, stream, max_rounds=None, record=False) -> 
     k_out = len(S)
     return Result(F=np.asfortranarray(F[:, :k_out]), pivots=np.array(S, dtype=np.int64),
                   rounds=r, proposals=r * b, status=status, trace_A=trace_A, u=u,
-                  round_sizes=sizes, u_history=hist)
+                  round_sizes=sizes, u_history=hist, margins=margins)
 
 
 @dataclass

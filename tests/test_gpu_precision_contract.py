@@ -1,0 +1,117 @@
+"""Mixed-precision contract at the full named workloads, through the C ABI.
+
+Each reduced-precision run is paired with the FP64 run of the same seed, and two
+relative trace errors are compared (accuracy measure of Section 1.4):
+
+1. from the factor: (tr A - |F|_F^2) / tr A, F as the run stored it;
+2. from the pivots alone: the Nystrom residual sum_j (A_jj - |L_S^{-1} A(S,j)|^2)
+   of the pivot set, re-evaluated in FP64 by the oracle on the TRUE points
+   (so an FP8 run, which factors the e4m3-rounded points, is judged on the
+   matrix the user asked for), estimated on 20000 seeded rows, the same rows for
+   both runs: N / n * sum over the sampled rows.
+
+Both must be at most 1.05x the FP64 run's.  The first can flatter a run whose
+perturbed matrix is not dominated by A; the second cannot.  The FP64 F-based
+trace error equals its Nystrom error (pinned in the oracle tests), so the seed
+spread printed by test_fp64_seed_spread is the scale against which a ratio
+near 1.05 should be read.
+
+Workloads: the Laplace workload in FP32 (N = 1e5, d = 20, k = 1000, b = 120),
+the mixture workload in BF16 (N = 1e6, d = 8, k = 2000, b = 200, the
+configuration bench.py times) and BF16x3, and the sparse high-dimensional
+workload (N = 2e5, d = 256, k = 4000, b = 400) in FP8 and BF16x3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ExpandedPointsAccess, nystrom_err
+from paper_2410_03969_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NY_ROWS = 20_000
+RATIO = 1.05
+
+_WORKLOADS = {"laplace": W.laplace, "mixture": W.mixture, "sparse_hd": W.sparse_hd}
+_cache = {}
+
+
+def _points(name):
+    if ("X", name) not in _cache:
+        _cache[("X", name)] = _WORKLOADS[name]()
+    return _cache[("X", name)]
+
+
+def _rows(N):
+    return np.sort(np.random.default_rng(99).choice(N, NY_ROWS, replace=False))
+
+
+def _errors(name, prec, seed=0):
+    """(F-based, sampled Nystrom) relative trace errors of one GPU run."""
+    import torch
+    from paper_2410_03969_amd import binding
+    X, prob = _points(name)
+    prob = prob.with_(prec=prec, seed=seed)
+    print(f"[gpu contract] workload={name} N={prob.N} d={prob.d} k={prob.k} b={prob.b} "
+          f"prec={W.PREC_NAMES[prec]} seed={seed}", flush=True)
+    sys.stdout.flush()
+    out = binding.factor(X, prob)
+    st = out["stats"]
+    assert out["status"] == 0 and st["k_out"] == prob.k
+    trA = st["trace_A"]
+    F = out["F"]
+    n2 = 0.0
+    for j in range(0, prob.k, 256):
+        n2 += float((F[:, j:j + 256].to(torch.float64) ** 2).sum().item())
+    piv = out["pivots"].cpu().numpy()
+    del out, F
+    torch.cuda.empty_cache()
+    assert len(set(piv.tolist())) == prob.k
+    te = (trA - n2) / trA
+    acc = ExpandedPointsAccess(X, prob.kernel, prob.sigma)
+    rows = _rows(prob.N)
+    ny = nystrom_err(acc, piv, rows=rows).sum() * (prob.N / rows.size) / trA
+    print(f"  trace error from F {te:.6e}, Nystrom (true points, {rows.size} rows) {ny:.6e}", flush=True)
+    return te, ny
+
+
+def _fp64(name):
+    if ("fp64", name) not in _cache:
+        _cache[("fp64", name)] = _errors(name, W.FP64)
+    return _cache[("fp64", name)]
+
+
+@pytest.mark.parametrize("name,prec", [("laplace", W.FP32), ("mixture", W.BF16), ("mixture", W.BF16X3),
+                                       ("sparse_hd", W.FP8), ("sparse_hd", W.BF16X3)])
+def test_trace_errors_within_contract(name, prec):
+    te64, ny64 = _fp64(name)
+    te, ny = _errors(name, prec)
+    print(f"  {name} {W.PREC_NAMES[prec]}: F-based ratio {te / te64:.5f}, Nystrom ratio {ny / ny64:.5f}",
+          flush=True)
+    assert te <= RATIO * te64
+    assert ny <= RATIO * ny64
+
+
+@pytest.mark.parametrize("name", ["mixture", "sparse_hd"])
+def test_fp64_seed_spread(name):
+    """The FP64 trace error over five seeds: the run-to-run spread that a
+    ratio to the seed-0 run is read against."""
+    import torch
+    from paper_2410_03969_amd import binding
+    X, prob = _points(name)
+    tes = []
+    for seed in range(5):
+        print(f"[gpu contract] spread workload={name} seed={seed}", flush=True)
+        out = binding.factor(X, prob.with_(prec=W.FP64, seed=seed))
+        trA = out["stats"]["trace_A"]
+        F = out["F"]
+        n2 = sum(float((F[:, j:j + 256] ** 2).sum().item()) for j in range(0, prob.k, 256))
+        tes.append((trA - n2) / trA)
+        del out, F
+        torch.cuda.empty_cache()
+    tes = np.array(tes)
+    print(f"  {name} FP64 trace error over 5 seeds: mean {tes.mean():.6e}, "
+          f"spread (max/min) {tes.max() / tes.min():.5f}, std/mean {tes.std() / tes.mean():.2e}", flush=True)
+    assert np.all(tes > 0) and np.all(tes < 1)

@@ -354,3 +354,48 @@ def test_central_error_bound():
     # a run that rejected everything after the first pivot of each round would
     # sit far above the bound; the accelerated method is well inside it
     assert tr.mean() < bound
+
+
+# --------------------------------------------------- checkers used at scale
+@pytest.mark.parametrize("ker,d", [(GAUSSIAN, 8), (LAPLACE_L2, 20), (MATERN32, 256)])
+def test_expanded_access_equals_direct_differences(ker, d):
+    """The expansion |x|^2 + |y|^2 - 2 x.y gives the direct-difference kernel
+    block to FP64 cancellation accuracy, with exact kappa(0) on repeated
+    indices; the Nystrom error of a pivot set agrees to 1e-9 relative."""
+    from oracle import ExpandedPointsAccess
+    rng = np.random.default_rng(d)
+    if d == 256:
+        X = np.where(rng.random((3000, d)) < 0.1, rng.standard_normal((3000, d)), 0.0)
+        sigma = 4.0
+    else:
+        X = rng.standard_normal((3000, d))
+        sigma = 2.0
+    a, e = PointsAccess(X, ker, sigma), ExpandedPointsAccess(X, ker, sigma)
+    I = rng.choice(3000, 400, replace=False)
+    J = np.concatenate([I[:50], rng.choice(3000, 150, replace=False)])
+    Bd, Be = a.block(I, J), e.block(I, J)
+    assert np.max(np.abs(Bd - Be)) < 1e-6 if ker != GAUSSIAN else np.max(np.abs(Bd - Be)) < 1e-12
+    assert np.all(Be[np.arange(50), np.arange(50)] == 1.0)
+    res = rpc_accel(a, k=150, b=30, stream=philox_stream(1))
+    rows = rng.choice(3000, 1000, replace=False)
+    nd = nystrom_err(a, res.pivots, rows=rows).sum()
+    ne = nystrom_err(e, res.pivots, rows=rows).sum()
+    assert abs(nd - ne) <= 1e-9 * nd
+
+
+def test_decision_margins():
+    """The proposal margin is the distance of U*T to the nearest edge of the
+    drawn index's CDF interval over T; the acceptance margin is
+    |u_i V_i - h_ii| / u_i, smallest over the round's tests."""
+    u = np.array([1.0, 2.0, 1.0])                    # C = 1, 3, 4; T = 4
+    m = []
+    draw_proposals(u, np.array([0.5, 0.24]), margin=m)  # targets 2.0 (in [1,3)), 0.96 (in [0,1))
+    assert m[0] == pytest.approx(min(1.0, 1.0, 0.04, 0.96) / 4.0)
+    H = np.array([[2.0, 1.0], [1.0, 2.0]])
+    ma = []
+    T, _ = reject_sample_submatrix(H, np.array([0.25, 0.5]), margin=ma)
+    # test 0: |2*0.25 - 2| / 2 = 0.75; test 1 after the update: h = 1.5, |2*0.5 - 1.5| / 2 = 0.25
+    assert list(T) == [0, 1] and ma[0] == pytest.approx(0.25)
+    res = rpc_accel(PointsAccess(np.random.default_rng(0).random((200, 2)), GAUSSIAN, 0.3), k=20, b=5,
+                    stream=philox_stream(0))
+    assert len(res.margins) == res.rounds and all(p >= 0 and a >= 0 for p, a in res.margins)
