@@ -60,7 +60,10 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="run the serving stream instead (prints its own JSON line)")
     ap.add_argument("--serving-jobs", type=int, default=512)
-    ap.add_argument("--serving-prec", default="bf16x3", choices=sorted(PREC_BY_NAME))
+    ap.add_argument("--serving-prec", default="bf16", choices=sorted(PREC_BY_NAME))
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave the serving stream out of the default run (it is measured after the "
+                         "factorization and reported under 'serving')")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -106,13 +109,18 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
 
 def gemm_roofline(stats, prec, workload):
     """Roofline of the dominant kernel from the HIP-event kernel times: the
-    one-kernel round product (BF16 modes) or the update-GEMM kernel.  The
-    algorithmic bytes (blocked F read once, points read, G written to F and
-    its blocked copy, row norms; the two-kernel GEMM writes C instead) against
-    8 TB/s, and the algorithmic flops (2 N k_r s_r for the GEMM, plus N s_r^2
-    for the solve when fused; counted once although the three-product mode
-    issues three BF16 products) against the matrix-core peak of the mode.
-    The binding roof (larger fraction) is reported first."""
+    one-kernel round product (BF16 modes) or the update-GEMM kernel.
+
+    Algorithmic bytes per launch: F read over its k_r columns at the
+    contraction precision, the points read, G written once to F at its
+    storage precision, the row norms written (the two-kernel GEMM writes C
+    instead).  The write of G into the panel-blocked copy that later rounds
+    contract over is reported apart (blocked_copy_bytes_per_launch), as is
+    the fraction with it counted.  Algorithmic flops: 2 N k_r s_r for the
+    GEMM, plus N s_r^2 for the solve when fused, counted once although the
+    three-product mode issues three BF16 products.  The binding roof (larger
+    fraction) is reported first; the MFMA side also states the attainable
+    fraction at the measured arithmetic intensity, min(1, AI * HBM / peak)."""
     ms = stats["ms_kernel"]["colgemm"]
     n = stats["launches"]["colgemm"]
     if ms <= 0 or n == 0:
@@ -125,41 +133,82 @@ def gemm_roofline(stats, prec, workload):
     gbs = stats["bytes_colgemm"] / sec / 1e9
     peak = {W.FP64: PEAKS["fp64_tflops"], W.FP32: PEAKS["fp32_tflops"]}.get(prec, PEAKS["bf16_tflops"])
     traffic = measured_traffic(kernel, workload, W.PREC_NAMES[prec])
+    blocked = stats["bytes_blocked"] if fused else 0.0
+    ai = flops / stats["bytes_colgemm"]
+    attainable = min(peak, ai * PEAKS["hbm_gbs"] / 1e3)   # TFLOP/s at this intensity
     common = {"kernel": kernel, "avg_launch_ms": round(ms / n, 4), "launches": n,
               "algorithmic_bytes_per_launch": round(stats["bytes_colgemm"] / n),
+              "blocked_copy_bytes_per_launch": round(blocked / n),
               "algorithmic_flops_per_launch": round(flops / n)}
     mf = {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
-          "frac": round(tflops / peak, 4), "traffic": traffic, **common}
+          "frac": round(tflops / peak, 4), "traffic": traffic,
+          "intensity_flop_per_byte": round(ai, 1), "attainable": round(attainable, 1),
+          "frac_of_attainable": round(tflops / attainable, 4), **common}
     hb = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-          "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": traffic, **common}
+          "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": traffic,
+          "frac_with_blocked_copy": round((stats["bytes_colgemm"] + blocked) / sec / 1e9 / PEAKS["hbm_gbs"], 4),
+          **common}
     return (mf, hb) if mf["frac"] >= hb["frac"] else (hb, mf)
 
 
-def cpu_baseline(X, prob, rounds):
+def cpu_baseline(X, prob, rounds, gpu_rounds):
+    """The FP64 oracle (Alg. 2 with Alg. 1 in numpy) timed on this host on the
+    first rounds of the same workload, and the full factorization's rate
+    extrapolated from them (marked as such).
+
+    Two timed samples: round 1 alone (k_r = 0: kernel columns, solve and
+    diagonal only, cost beta N s per round) and rounds 1..R.  Their
+    difference fixes alpha in the update-GEMM term alpha * 2 N k_r s_r, whose
+    sum over a run is N (k^2 - sum_r s_r^2).  The full run's cost is then
+    beta N k + alpha N (k^2 - sum s_r^2), with the GPU run's round count and
+    equal rounds for sum s_r^2."""
     from oracle import PointsAccess, philox_stream, rpc_accel
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    threads = cores
+    blas_threads = None
     try:
         from threadpoolctl import threadpool_info
         info = threadpool_info()
         if info:
-            threads = max(int(i.get("num_threads", 1)) for i in info)
+            blas_threads = max(int(i.get("num_threads", 1)) for i in info)
     except Exception:
         pass
+    if blas_threads is None:
+        blas_threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
     t = time.perf_counter()
-    r = rpc_accel(PointsAccess(X, prob.kernel, prob.sigma), prob.k, prob.b,
-                  philox_stream(prob.seed), max_rounds=rounds)
-    dt = time.perf_counter() - t
-    return {"value": round(r.k_out / dt, 3), "unit": "pivots/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"first {rounds} rounds of the same workload ({r.k_out} pivots, "
-                      f"{dt:.1f} s; later rounds cost more per pivot)"}
+    r1 = rpc_accel(acc, prob.k, prob.b, philox_stream(prob.seed), max_rounds=1)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    rr = rpc_accel(acc, prob.k, prob.b, philox_stream(prob.seed), max_rounds=rounds)
+    tr = time.perf_counter() - t
+    N, k = prob.N, prob.k
+    sizes = [int(v) for v in rr.round_sizes]
+    beta = t1 / (N * max(sizes[0], 1))
+    gemm_units, kr = 0.0, 0
+    for s_ in sizes:
+        gemm_units += 2.0 * N * kr * s_
+        kr += s_
+    rest = tr - beta * N * sum(sizes)
+    alpha = max(rest, 0.0) / gemm_units if gemm_units > 0 else 0.0
+    s_mean = k / max(gpu_rounds, 1)
+    full_s = beta * N * k + alpha * N * (k * k - gpu_rounds * s_mean * s_mean)
+    return {"value": round(k / full_s, 3), "unit": "pivots/s", "cores": int(cores),
+            "blas_threads": int(blas_threads), "kind": "oracle", "extrapolated": True,
+            "sample": f"rounds 1..{rounds} of the same workload ({rr.k_out} pivots in {tr:.1f} s, "
+                      f"{rr.k_out / tr:.2f} pivots/s) and round 1 alone ({t1:.1f} s); full run "
+                      f"extrapolated to {full_s:.0f} s with beta N k + alpha N (k^2 - sum s_r^2), "
+                      f"{gpu_rounds} rounds",
+            "sample_value": round(rr.k_out / tr, 3), "extrapolated_seconds": round(full_s, 1)}
 
 
 def run_serving(args):
+    print(json.dumps(serving_measure(args)), flush=True)
+
+
+def serving_measure(args):
     """Serving stream: jobs shaped as in workloads.serving_stream (N log-uniform
     on [1e4, 2e5], d in {3, 8, 32}, k uniform on [200, 1500], b = k/10).  A
     closed loop with a bounded number of outstanding jobs measures the
@@ -225,7 +274,9 @@ def run_serving(args):
         "closed_loop": {"pivots_per_s": round(piv_c / span_c, 1), "mean_resident_jobs": round(res_c, 3),
                         "p50_ms": round(float(np.percentile(lat_c, 50)), 3)},
     }
-    print(json.dumps(out), flush=True)
+    del Xs
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -305,7 +356,7 @@ def main():
     agg["fused"] = last.get("fused", 0)
     agg["ms_kernel"] = {c: sum(r["ms_kernel"][c] for r in runs) for c in B.KERNEL_CLASSES}
     agg["launches"] = {c: sum(r["launches"][c] for r in runs) for c in B.KERNEL_CLASSES}
-    for key in ("flops_colgemm", "bytes_colgemm", "flops_trsm", "bytes_trsm"):
+    for key in ("flops_colgemm", "bytes_colgemm", "flops_trsm", "bytes_trsm", "bytes_blocked"):
         agg[key] = sum(r[key] for r in runs)
     roof, roof_alt = gemm_roofline(agg, prec, variant)
 
@@ -333,8 +384,16 @@ def main():
         out["fp64_compare"] = {"ms": round(out64["stats"]["ms_total"], 2), "trace_error_F": te64,
                                "ratio": trace_err / te64 if te64 > 0 else None}
         del out64, F64
+    if not args.no_serving and args.workload == "mixture" and method == W.ACCEL:
+        del F, Ft, piv, ws
+        torch.cuda.empty_cache()
+        srv = serving_measure(args)
+        out["serving"] = {k: srv[k] for k in ("p50_ms", "p99_ms", "saturation_jobs_per_s",
+                                             "arrival_rate_jobs_per_s", "pivots_per_s", "mean_resident_jobs",
+                                             "dtype", "closed_loop", "peak_active")}
+        out["serving"]["workload"] = srv["config"]["workload"]
     if args.cpu_rounds > 0 and method == W.ACCEL:
-        out["cpu_baseline"] = cpu_baseline(X, prob, args.cpu_rounds)
+        out["cpu_baseline"] = cpu_baseline(X, prob, args.cpu_rounds, last["rounds"])
     print(json.dumps(out), flush=True)
 
 

@@ -107,11 +107,13 @@ typedef struct arpc_stats {
   int64_t launches[ARPC_NUM_KC];   /* launches per class (profiling on) */
   double flops_colgemm; /* algorithmic flops of the update GEMM, sum_r 2 N k_r s_r */
   double flops_trsm;    /* algorithmic flops of the triangular solve, sum_r N s_r^2 */
-  double bytes_colgemm; /* algorithmic HBM bytes of the update GEMM: blocked F read, C written,
-                           X read (fused: blocked F and X read, G written to F and to the
-                           blocked copy, row norms written) */
+  double bytes_colgemm; /* algorithmic HBM bytes of the update GEMM: F read over k_r columns at
+                           the contraction precision, C written, X read (fused: F and X read,
+                           G written once to F at its storage precision, row norms written) */
   double bytes_trsm;    /* algorithmic HBM bytes of the triangular solve: C read, G written
-                           twice, norms (0 when fused) */
+                           to F, row norms (0 when fused) */
+  double bytes_blocked; /* HBM bytes of G written into the panel-blocked copy of F that the
+                           matrix-core contraction of later rounds reads (not counted above) */
 } arpc_stats;
 
 /* Human-readable name of a status code (static storage). */

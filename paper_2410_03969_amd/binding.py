@@ -49,7 +49,7 @@ class ArpcStats(C.Structure):
                 ("trace_resid", C.c_double), ("ms_total", C.c_double),
                 ("ms_kernel", C.c_double * NUM_KC), ("launches", C.c_int64 * NUM_KC),
                 ("flops_colgemm", C.c_double), ("flops_trsm", C.c_double),
-                ("bytes_colgemm", C.c_double), ("bytes_trsm", C.c_double)]
+                ("bytes_colgemm", C.c_double), ("bytes_trsm", C.c_double), ("bytes_blocked", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("ms_kernel", "launches")}

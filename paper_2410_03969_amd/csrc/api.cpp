@@ -333,9 +333,11 @@ struct Job final : JobBase {
       stats->trace_A = h.trace_A;
       stats->trace_resid = trace_resid;
       // algorithmic traffic per round and row: the blocked copy of F read over
-      // k_r columns, the points, G stored twice (F and its blocked copy), the
-      // row norm; the two-kernel path also writes and reads C
-      double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0;
+      // k_r columns at the contraction precision, the points, G written once
+      // to F at its storage precision, the row norm; the two-kernel path also
+      // writes C (update GEMM) and reads it (solve).  The write of G into the
+      // blocked copy (which the next rounds contract over) is counted apart.
+      double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0, bb = 0.0;
       const double es = (double)sizeof(T);
       const double eb = p.prec == ARPC_FP64 ? 8.0 : (gemm_prec(p.prec) == ARPC_BF16 ? 2.0 : 4.0);
       const bool fused = l.ncbt > 0;
@@ -345,11 +347,12 @@ struct Job final : JobBase {
         ft += (double)N * sr * sr;
         if (sr > 0) {
           if (fused) {
-            bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * (es + eb) + 8.0);
+            bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * es + 8.0);
           } else {
             bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
-            bt += (double)N * (sr * (eb + es + eb) + 8.0);
+            bt += (double)N * (sr * (eb + es) + 8.0);
           }
+          if (!l.valu) bb += (double)N * sr * eb;
         }
         kr += sr;
       }
@@ -358,6 +361,7 @@ struct Job final : JobBase {
       stats->flops_trsm = ft;
       stats->bytes_colgemm = bg;
       stats->bytes_trsm = bt;
+      stats->bytes_blocked = bb;
       for (int c = 0; c < ARPC_NUM_KC; ++c) {
         stats->ms_kernel[c] = prof->ms[c];
         stats->launches[c] = prof->n[c];
@@ -388,12 +392,12 @@ arpc_status check_factor_args(const arpc_problem* p, const double* X, const void
 
 }  // namespace arpc
 
-namespace {
+namespace arpc {
 
-arpc_status run_sync(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws, const Layout& l,
-                     hipStream_t s, const Unif& un, arpc_stats* stats) {
+static arpc_status run_sync(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws,
+                            const Layout& l, hipStream_t s, const Unif& un, arpc_stats* stats, unsigned classes) {
   const auto t0 = std::chrono::steady_clock::now();
-  Profiler prof(s, g_profiling);
+  Profiler prof(s, classes);
   RoundState h{};
   auto job = make_job(p, X, F, pivots, ws, l, s, un, &h, &prof);
   arpc_status e = job->begin();
@@ -410,17 +414,17 @@ arpc_status run_sync(const arpc_problem& p, const double* X, void* F, int64_t* p
 }
 
 arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t* pivots, void* ws,
-                        size_t ws_bytes, void* stream, const Unif& un, arpc_stats* stats) {
+                        size_t ws_bytes, void* stream, const Unif& un, arpc_stats* stats, bool timed) {
   arpc_status v = check_factor_args(p, X, F, pivots);
   if (v != ARPC_OK) return v;
   if (!ws || ((uintptr_t)ws & 255)) return ARPC_EINVAL;
   Layout l = layout_of(*p);
   if (ws_bytes < l.total) return ARPC_EINVAL;
   if (l.ncbt > 0) l.grid = fused_grid();
-  return run_sync(*p, X, F, pivots, (char*)ws, l, (hipStream_t)stream, un, stats);
+  return run_sync(*p, X, F, pivots, (char*)ws, l, (hipStream_t)stream, un, stats, timed ? g_profiling : 0u);
 }
 
-}  // namespace
+}  // namespace arpc
 
 extern "C" {
 
@@ -452,7 +456,7 @@ arpc_status arpc_factor(const arpc_problem* problem, const double* X, void* F, i
                         size_t ws_bytes, void* stream, arpc_stats* stats) {
   if (!problem) return ARPC_EINVAL;
   Unif un{nullptr, 0, problem->seed};
-  return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats);
+  return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats, true);
 }
 
 arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, void* F, int64_t* pivots,
@@ -460,7 +464,7 @@ arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, v
                                  arpc_stats* stats) {
   if (!problem || !U || nU < 0 || ((uintptr_t)U & 7)) return ARPC_EINVAL;
   Unif un{U, nU, problem->seed};
-  return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats);
+  return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats, true);
 }
 
 arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out) {

@@ -96,5 +96,10 @@ arpc_status check_factor_args(const arpc_problem* p, const double* X, const void
 std::unique_ptr<JobBase> make_job(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws,
                                   const Layout& l, hipStream_t s, const Unif& un, RoundState* hstate,
                                   Profiler* prof);
+// Checks the arguments, carves the workspace and runs the factorization to
+// completion on `stream` (the host waits between batches of rounds).  timed:
+// honour the process-wide profiling switch (else no events are created).
+arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t* pivots, void* ws,
+                        size_t ws_bytes, void* stream, const Unif& un, arpc_stats* stats, bool timed);
 
 }  // namespace arpc
