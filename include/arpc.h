@@ -201,7 +201,7 @@ arpc_status arpc_qr_workspace_size(int64_t M, int64_t N, int64_t k, int64_t b, s
  * arpc_factor keyed by seed).  Output: Q with orthonormal columns and
  * F = B^* Q, B_hat = Q F^*; each round's new columns of Q are orthonormalized
  * after one extra Gram-Schmidt pass, by the QR factorization with a positive
- * diagonal in R.  FP64; plain products in rocBLAS.
+ * diagonal in R.  FP64; every product on the library's FP64 matrix-core GEMM.
  *
  *  M, N    rows and columns of B, 1 <= k <= min(M, N), 1 <= b <= 512.
  *  B       device, M x N column-major FP64 (read only).
@@ -228,8 +228,8 @@ typedef struct arpc_krr_stats {
   double rel_residual;  /* |y - (A + mu I) beta| / |y| as tracked by the recurrence */
   double ms_total;      /* host wall time of the call */
   double ms_setup;      /* forming and factoring mu I + F^* F */
-  double ms_matvec;     /* products with A + mu I (host-timed, includes the dot product) */
-  double ms_precond;    /* applications of P^{-1} */
+  double ms_matvec;     /* products with A + mu I (device time, HIP events) */
+  double ms_precond;    /* applications of P^{-1} (device time, HIP events) */
   int32_t status;       /* ARPC_OK: converged to tol; ARPC_EARLY_STOP: max_iter reached */
   int32_t reserved;
 } arpc_krr_stats;
@@ -251,7 +251,8 @@ arpc_status arpc_krr_workspace_size(int64_t N, int64_t d, int64_t k, int32_t f_p
  *          FP32 (the layout arpc_factor writes); unused when k = 0.  k <= 2048.
  *  beta    device, N FP64 output.
  *  ws      device workspace of at least arpc_krr_workspace_size bytes, 256-byte aligned.
- *  stream  hipStream_t; the host waits on it once per iteration (the PCG scalars).
+ *  stream  hipStream_t.  The PCG scalars stay on the device; the host waits on the
+ *          stream once per batch of eight iterations to read the stopping flag.
  *  stats   host, may be NULL.
  *
  * Returns ARPC_OK (converged), ARPC_EARLY_STOP (max_iter reached), ARPC_EINVAL,

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libarpc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["round_kernels.hip", "gemm_kernels.hip", "mfma_kernels.hip", "fused_kernels.hip", "lowmem.hip", "rpqr.hip", "krr.hip",
+SOURCES = ["round_kernels.hip", "gemm_kernels.hip", "mfma_kernels.hip", "fused_kernels.hip", "lowmem.hip", "rpqr.hip", "krr.hip", "dense_f64.hip",
            "api.cpp", "serving.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -43,8 +43,7 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=min(6, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-L/opt/rocm/lib", "-lrocblas",
-           "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -14,7 +14,6 @@ void launch_init_from_diag(hipStream_t s, const double* u, int64_t N, double* cs
 // In-place lower Cholesky factor of the n x n matrix G (column-major, ld n;
 // the strict upper triangle is zeroed), one workgroup; a non-positive pivot
 // is replaced by 1 and sets *bad.
-void launch_dense_chol(hipStream_t s, double* G, int n, int* bad);
 // Xq = X with every coordinate rounded to FP8 e4m3 (the FP8 mode's points), n values.
 void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n);
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,

@@ -5,14 +5,19 @@
 // The product with A + mu I regenerates the kernel entries on the fly (one
 // thread per row, the other points staged through LDS 64 at a time; FP64,
 // direct differences, the diagonal exactly kappa(0)).  P^{-1} r uses the
-// Woodbury identity, (r - F (mu I + F^* F)^{-1} F^* r) / mu, with the k x k
-// matrix formed once (rocBLAS dsyrk) and factored blockwise (the library's
-// one-workgroup Cholesky on 64 x 64 diagonal blocks, rocBLAS dtrsm and dsyrk
-// for the rest); the plain vector and matrix-vector products are rocBLAS.
+// Woodbury identity, (r - F (mu I + F^* F)^{-1} F^* r) / mu: the k x k
+// matrix mu I + F^* F = L L^* is formed and factored once and L^{-1} is formed
+// explicitly, so an application is four matrix-vector products (F^* r,
+// L^{-1} t, L^{-*} t, F t), all on the library's FP64 matrix-core GEMM with
+// contractions split over workgroups and summed in a fixed order.
 // PCG is the textbook iteration from beta = 0 (Golub and Van Loan,
-// Alg. 11.5.1); the host reads the scalars of each iteration.
+// Alg. 11.5.1) with its scalars kept on the device: dot products reduce in a
+// fixed order into device memory, one-thread kernels form alpha and the
+// direction update, and a device flag, set when |r| <= tol |y| or after
+// max_iter iterations, turns the remaining kernels of the iteration and of
+// later iterations into no-ops.  The host enqueues KRR_BATCH iterations at a
+// time and reads the flag between batches.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <chrono>
 #include <cmath>
@@ -20,6 +25,7 @@
 
 #include "../../include/arpc.h"
 #include "arpc_common.h"
+#include "arpc_dense.h"
 #include "arpc_host.h"
 #include "arpc_launch.h"
 
@@ -125,10 +131,78 @@ __global__ void k_krr_add_diag(double* __restrict__ M, int k, double mu) {
   if (i < k) M[(int64_t)i * k + i] += mu;
 }
 
+// Device state of the PCG iteration.
+struct PcgState {
+  double yy, rz, pq, rr, rz_new, alpha, ny, rel;
+  int64_t it, max_it;
+  double tol;
+  int32_t done, pad;
+};
+
+// rel and done after the initial residual r = y.
+__global__ void k_pcg_start(PcgState* ps, int64_t max_it, double tol) {
+  ps->ny = sqrt(ps->yy);
+  ps->rel = ps->ny > 0.0 ? 1.0 : 0.0;
+  ps->it = 0;
+  ps->max_it = max_it;
+  ps->tol = tol;
+  ps->done = (ps->rel > tol) ? 0 : 1;
+}
+
+__global__ void k_pcg_alpha(PcgState* ps) {
+  if (ps->done) return;
+  ps->alpha = ps->rz / ps->pq;
+}
+
+// beta += alpha p, r -= alpha q
+__global__ __launch_bounds__(256) void k_pcg_step(const PcgState* ps, const double* __restrict__ p,
+                                                  const double* __restrict__ q, double* __restrict__ beta,
+                                                  double* __restrict__ r, int64_t n) {
+  if (ps->done) return;
+  const double a = ps->alpha;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    beta[i] = fma(a, p[i], beta[i]);
+    r[i] = fma(-a, q[i], r[i]);
+  }
+}
+
+__global__ void k_pcg_check(PcgState* ps) {
+  if (ps->done) return;
+  ps->it += 1;
+  ps->rel = sqrt(ps->rr) / ps->ny;
+  if (!(ps->rel > ps->tol) || ps->it >= ps->max_it) ps->done = 1;
+}
+
+// z = (v - w) / mu  (w = F (mu I + F^* F)^{-1} F^* v), or v / mu without F
+__global__ __launch_bounds__(256) void k_pcg_precond_out(const PcgState* ps, const double* __restrict__ v,
+                                                         const double* __restrict__ w, double mu,
+                                                         double* __restrict__ z, int64_t n) {
+  if (ps && ps->done) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) z[i] = w ? (v[i] - w[i]) / mu : v[i] / mu;
+}
+
+// p = z + (rz_new / rz) p, rz = rz_new
+__global__ __launch_bounds__(256) void k_pcg_dir(PcgState* ps, const double* __restrict__ z, double* __restrict__ p,
+                                                 int64_t n) {
+  if (ps->done) return;
+  const double c = ps->rz_new / ps->rz;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = fma(c, p[i], z[i]);
+}
+
+__global__ void k_pcg_rz(PcgState* ps) {
+  if (ps->done) return;
+  ps->rz = ps->rz_new;
+}
+
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int KRR_BATCH = 8;   // iterations enqueued between host checks
+
 struct KrrLayout {
-  size_t Fd, M, D, t, r, z, p, q, part, bad, total;
+  size_t Fd, M, Li, cw, t, t2, w, r, z, p, q, part, gpart, gpe, dpart, ps, bad, total;
 };
 
 KrrLayout krr_layout(int64_t N, int64_t k, bool convert) {
@@ -141,13 +215,26 @@ KrrLayout krr_layout(int64_t N, int64_t k, bool convert) {
   };
   l.Fd = take(convert ? sizeof(double) * N * k : 0);
   l.M = take(sizeof(double) * k * k);
-  l.D = take(sizeof(double) * 64 * 64);
+  l.Li = take(sizeof(double) * k * k);
+  l.cw = take(sizeof(double) * chol_work_elems((int)k));
   l.t = take(sizeof(double) * (k > 0 ? k : 1));
+  l.t2 = take(sizeof(double) * (k > 0 ? k : 1));
+  l.w = take(sizeof(double) * N);
   l.r = take(sizeof(double) * N);
   l.z = take(sizeof(double) * N);
   l.p = take(sizeof(double) * N);
   l.q = take(sizeof(double) * N);
   l.part = take(sizeof(double) * krr_parts(N) * N);
+  size_t gpe = 1;
+  if (k > 0) {
+    const size_t c[4] = {dgemm_part_elems(k, k, N), dgemm_part_elems(k, 1, N), dgemm_part_elems(N, 1, k),
+                         dgemm_part_elems(k, 1, k)};
+    for (size_t v : c) gpe = v > gpe ? v : gpe;
+  }
+  l.gpe = gpe;
+  l.gpart = take(sizeof(double) * gpe);
+  l.dpart = take(sizeof(double) * dot_part_elems(N));
+  l.ps = take(sizeof(PcgState));
   l.bad = take(sizeof(int));
   l.total = off;
   return l;
@@ -166,18 +253,6 @@ arpc_status krr_validate(int64_t N, int64_t d, int32_t kernel, double bw, double
   do {                                        \
     if ((x) != hipSuccess) return ARPC_EDEVICE; \
   } while (0)
-#define KBCHK(x)                                        \
-  do {                                                  \
-    if ((x) != rocblas_status_success) return ARPC_EDEVICE; \
-  } while (0)
-
-struct KHandle {
-  rocblas_handle h = nullptr;
-  ~KHandle() {
-    if (h) (void)rocblas_destroy_handle(h);
-  }
-};
-
 using clk = std::chrono::steady_clock;
 inline double ms_since(clk::time_point t) { return std::chrono::duration<double, std::milli>(clk::now() - t).count(); }
 
@@ -185,75 +260,48 @@ arpc_status krr_run(int64_t N, int64_t d, int32_t kernel, double bw, double mu, 
                     const void* F, int32_t f_prec, int64_t k, double tol, int64_t max_iter, double* beta, char* ws,
                     const KrrLayout& l, hipStream_t s, arpc_krr_stats* stats) {
   const auto t0 = clk::now();
-  KHandle hb;
-  KBCHK(rocblas_create_handle(&hb.h));
-  KBCHK(rocblas_set_stream(hb.h, s));
-  rocblas_handle h = hb.h;
   arpc_problem pp{};
   pp.kernel = kernel;
   pp.bandwidth = bw;
   const KParams kp = kparams_of(pp);
+  // matrix-vector products timed as class colgemm, preconditioner applications as trsm
+  Profiler prof(s, (1u << ARPC_KC_COLGEMM) | (1u << ARPC_KC_TRSM));
   const double* Fd = (const double*)F;
   if (k > 0 && f_prec != ARPC_FP64) {
     hipLaunchKernelGGL(k_krr_to_f64, dim3(8192), dim3(256), 0, s, (const float*)F, (double*)(ws + l.Fd), N * k);
     Fd = (const double*)(ws + l.Fd);
   }
   double* M = (double*)(ws + l.M);
+  double* Li = (double*)(ws + l.Li);
   double* t = (double*)(ws + l.t);
+  double* t2 = (double*)(ws + l.t2);
+  double* w = (double*)(ws + l.w);
   double* r = (double*)(ws + l.r);
   double* z = (double*)(ws + l.z);
   double* p = (double*)(ws + l.p);
   double* q = (double*)(ws + l.q);
+  double* gpart = (double*)(ws + l.gpart);
+  double* dpart = (double*)(ws + l.dpart);
+  PcgState* ps = (PcgState*)(ws + l.ps);
   int* bad = (int*)(ws + l.bad);
-  const double one = 1.0, zero = 0.0;
   const unsigned gN = (unsigned)((N + 255) / 256);
+  const int ik = (int)k;
   KCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
-  if (k > 0) {   // M = L L^* = mu I + F^* F
-    KBCHK(rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, (rocblas_int)k, (rocblas_int)N, &one, Fd,
-                        (rocblas_int)N, &zero, M, (rocblas_int)k));
-    hipLaunchKernelGGL(k_krr_add_diag, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, M, (int)k, mu);
-    // blocked right-looking Cholesky, 64 columns at a time: the diagonal
-    // block by the one-workgroup kernel (it reads and writes only that block,
-    // which has leading dimension k here, so it is factored in a packed copy),
-    // the panel below by a triangular solve, the trailing matrix by a
-    // symmetric rank-64 update
-    constexpr int NBK = 64;
-    for (int64_t j = 0; j < k; j += NBK) {
-      const int nb = (int)(k - j < NBK ? k - j : NBK);
-      double* Ajj = M + j * k + j;
-      double* Dp = (double*)(ws + l.D);
-      KCHK(hipMemcpy2DAsync(Dp, sizeof(double) * nb, Ajj, sizeof(double) * k, sizeof(double) * nb, nb,
-                            hipMemcpyDeviceToDevice, s));
-      launch_dense_chol(s, Dp, nb, bad);
-      KCHK(hipMemcpy2DAsync(Ajj, sizeof(double) * k, Dp, sizeof(double) * nb, sizeof(double) * nb, nb,
-                            hipMemcpyDeviceToDevice, s));
-      const int64_t rest = k - j - nb;
-      if (rest > 0) {
-        double* Aij = M + j * k + j + nb;            // rows below the block, its columns
-        KBCHK(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                            rocblas_diagonal_non_unit, (rocblas_int)rest, nb, &one, Ajj, (rocblas_int)k, Aij,
-                            (rocblas_int)k));
-        const double mone = -1.0;
-        KBCHK(rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, (rocblas_int)rest, nb, &mone, Aij,
-                            (rocblas_int)k, &one, M + (j + nb) * k + j + nb, (rocblas_int)k));
-      }
-    }
+  if (k > 0) {   // M = L L^* = mu I + F^* F, then Li = L^{-1}
+    KCHK(dgemm(s, true, false, k, k, N, 1.0, Fd, N, Fd, N, 0.0, M, k, gpart, l.gpe));
+    hipLaunchKernelGGL(k_krr_add_diag, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, M, ik, mu);
+    KCHK(chol_lower(s, M, ik, k, (double*)(ws + l.cw), bad));
+    launch_trinv_lower(s, M, ik, k, Li, k);
   }
-  // z = P^{-1} v
-  auto precond = [&](const double* v, double* out) -> arpc_status {
-    if (k == 0) {
-      hipLaunchKernelGGL(k_krr_axpby, dim3(gN), dim3(256), 0, s, 1.0 / mu, v, 0.0, v, out, N);
-      return ARPC_OK;
+  // z = P^{-1} v (skipped once the iteration has stopped, when ps is given)
+  auto precond = [&](const double* v, double* out, const PcgState* gate) -> arpc_status {
+    if (k > 0) {
+      KCHK(dgemm(s, true, false, k, 1, N, 1.0, Fd, N, v, N, 0.0, t, k, gpart, l.gpe));     // t = F^* v
+      KCHK(dgemm(s, false, false, k, 1, k, 1.0, Li, k, t, k, 0.0, t2, k, gpart, l.gpe));   // L^{-1} t
+      KCHK(dgemm(s, true, false, k, 1, k, 1.0, Li, k, t2, k, 0.0, t, k, gpart, l.gpe));    // L^{-*} (L^{-1} t)
+      KCHK(dgemm(s, false, false, N, 1, k, 1.0, Fd, N, t, k, 0.0, w, N, gpart, l.gpe));    // F M^{-1} F^* v
     }
-    KBCHK(rocblas_dgemv(h, rocblas_operation_transpose, (rocblas_int)N, (rocblas_int)k, &one, Fd, (rocblas_int)N, v,
-                        1, &zero, t, 1));
-    KBCHK(rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, (rocblas_int)k, M,
-                        (rocblas_int)k, t, 1));
-    KBCHK(rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit,
-                        (rocblas_int)k, M, (rocblas_int)k, t, 1));
-    KBCHK(rocblas_dgemv(h, rocblas_operation_none, (rocblas_int)N, (rocblas_int)k, &one, Fd, (rocblas_int)N, t, 1,
-                        &zero, out, 1));
-    hipLaunchKernelGGL(k_krr_axpby, dim3(gN), dim3(256), 0, s, 1.0 / mu, v, -1.0 / mu, out, out, N);
+    hipLaunchKernelGGL(k_pcg_precond_out, dim3(gN), dim3(256), 0, s, gate, v, k > 0 ? w : nullptr, mu, out, N);
     return ARPC_OK;
   };
   const int parts = krr_parts(N);
@@ -266,59 +314,54 @@ arpc_status krr_run(int64_t N, int64_t d, int32_t kernel, double bw, double mu, 
       hipLaunchKernelGGL(k_krr_matvec<false>, dim3(gN, parts), dim3(256), 0, s, X, (int)d, kp, v, N, pw, part);
     hipLaunchKernelGGL(k_krr_sum, dim3(gN), dim3(256), 0, s, part, parts, v, mu, N, out);
   };
-  auto dot = [&](const double* a, const double* b, double* res) -> arpc_status {
-    KBCHK(rocblas_ddot(h, (rocblas_int)N, a, 1, b, 1, res));   // host result: waits for the stream
-    return ARPC_OK;
-  };
-  double tm = 0.0, tp = 0.0;
   arpc_status e;
-  // beta = 0, r = y, z = P^{-1} r, p = z
+  // beta = 0, r = y, z = P^{-1} r, p = z, rz = r.z
   KCHK(hipMemsetAsync(beta, 0, sizeof(double) * N, s));
   KCHK(hipMemcpyAsync(r, y, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-  double yy = 0.0, rz = 0.0, rr = 0.0;
-  if ((e = dot(y, y, &yy)) != ARPC_OK) return e;
-  const double setup_ms = ms_since(t0);
-  auto tq = clk::now();
-  if ((e = precond(r, z)) != ARPC_OK) return e;
+  launch_dot(s, y, y, N, dpart, &ps->yy);
+  hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(1), 0, s, ps, max_iter, tol);
+  if ((e = precond(r, z, nullptr)) != ARPC_OK) return e;
   KCHK(hipMemcpyAsync(p, z, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-  if ((e = dot(r, z, &rz)) != ARPC_OK) return e;
-  tp += ms_since(tq);
-  const double ny = std::sqrt(yy);
-  double rel = ny > 0 ? 1.0 : 0.0;
-  int64_t it = 0;
-  while (it < max_iter && rel > tol) {
-    tq = clk::now();
-    matvec(p, q);
-    double pq = 0.0;
-    if ((e = dot(p, q, &pq)) != ARPC_OK) return e;
-    tm += ms_since(tq);
-    const double alpha = rz / pq;
-    hipLaunchKernelGGL(k_krr_axpby, dim3(gN), dim3(256), 0, s, 1.0, beta, alpha, p, beta, N);
-    hipLaunchKernelGGL(k_krr_axpby, dim3(gN), dim3(256), 0, s, 1.0, r, -alpha, q, r, N);
-    if ((e = dot(r, r, &rr)) != ARPC_OK) return e;
-    ++it;
-    rel = std::sqrt(rr) / ny;
-    if (rel <= tol) break;
-    tq = clk::now();
-    if ((e = precond(r, z)) != ARPC_OK) return e;
-    double rz_new = 0.0;
-    if ((e = dot(r, z, &rz_new)) != ARPC_OK) return e;
-    tp += ms_since(tq);
-    hipLaunchKernelGGL(k_krr_axpby, dim3(gN), dim3(256), 0, s, 1.0, z, rz_new / rz, p, p, N);
-    rz = rz_new;
-  }
+  launch_dot(s, r, z, N, dpart, &ps->rz);
   KCHK(hipGetLastError());
+  PcgState h{};
+  KCHK(hipMemcpyAsync(&h, ps, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  KCHK(hipStreamSynchronize(s));
+  const double setup_ms = ms_since(t0);
+  while (!h.done) {
+    for (int b = 0; b < KRR_BATCH; ++b) {
+      prof.begin(ARPC_KC_COLGEMM);
+      matvec(p, q);
+      prof.end();
+      launch_dot(s, p, q, N, dpart, &ps->pq);
+      hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, s, ps);
+      hipLaunchKernelGGL(k_pcg_step, dim3(gN), dim3(256), 0, s, ps, p, q, beta, r, N);
+      launch_dot(s, r, r, N, dpart, &ps->rr);
+      hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, s, ps);
+      prof.begin(ARPC_KC_TRSM);
+      if ((e = precond(r, z, ps)) != ARPC_OK) return e;
+      prof.end();
+      launch_dot(s, r, z, N, dpart, &ps->rz_new);
+      hipLaunchKernelGGL(k_pcg_dir, dim3(gN), dim3(256), 0, s, ps, z, p, N);
+      hipLaunchKernelGGL(k_pcg_rz, dim3(1), dim3(1), 0, s, ps);
+    }
+    KCHK(hipGetLastError());
+    KCHK(hipMemcpyAsync(&h, ps, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    KCHK(hipStreamSynchronize(s));
+    prof.collect();
+  }
   int hbad = 0;
   KCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   KCHK(hipStreamSynchronize(s));
+  const double rel = h.rel;
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
-    stats->iterations = it;
+    stats->iterations = h.it;
     stats->rel_residual = rel;
     stats->ms_total = ms_since(t0);
     stats->ms_setup = setup_ms;
-    stats->ms_matvec = tm;
-    stats->ms_precond = tp;
+    stats->ms_matvec = prof.ms[ARPC_KC_COLGEMM];
+    stats->ms_precond = prof.ms[ARPC_KC_TRSM];
     stats->status = rel <= tol ? ARPC_OK : ARPC_EARLY_STOP;
   }
   if (hbad || !std::isfinite(rel)) return ARPC_ENUMERIC;

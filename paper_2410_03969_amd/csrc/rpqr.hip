@@ -8,17 +8,19 @@
 //   Q by Q_perp = Orth(C(:,T) - Q (Q^* C(:,T)))   (one extra Gram-Schmidt pass),
 //   F by G = B^* Q_perp,  u -= rowsqnorm(G)  (the shared diagonal kernel).
 // Orth is Cholesky QR: R^* R = Q_perp^* Q_perp, Q_perp <- Q_perp R^{-1}, the
-// QR factorization with a positive diagonal in R.  The plain products run in
-// rocBLAS (dgemm, dtrsm); the host reads s_r after each round's rejection
-// step, since those calls take their sizes on the host.
+// QR factorization with a positive diagonal in R (R^{-1} formed explicitly,
+// one workgroup per column).  Every product runs on the library's FP64
+// matrix-core GEMM (column-major operands, contractions over the M rows split
+// over workgroups and summed in a fixed order); the host reads s_r after each
+// round's rejection step, since those products take their sizes on the host.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <chrono>
 #include <cstring>
 
 #include "../../include/arpc.h"
 #include "arpc_common.h"
+#include "arpc_dense.h"
 #include "arpc_host.h"
 #include "arpc_launch.h"
 
@@ -73,37 +75,6 @@ __global__ __launch_bounds__(256) void k_qr_take(const double* __restrict__ C, i
   Qn[(int64_t)a * M + r] = C[(int64_t)acc[a] * M + r];
 }
 
-// In-place lower Cholesky factor of the s x s matrix G (column-major, ld s),
-// right-looking, one workgroup.  The Gram matrix of the accepted residual
-// columns is positive definite (every accepted proposal had a positive
-// residual); a non-positive pivot is replaced by 1 and reported in *bad.
-__global__ __launch_bounds__(256) void k_qr_chol(double* __restrict__ G, int s, int* __restrict__ bad) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < s; ++j) {
-    __syncthreads();
-    double dj = G[(int64_t)j * s + j];
-    if (!(dj > 0.0)) {
-      if (tid == 0) *bad = 1;
-      dj = 1.0;
-    }
-    const double d = sqrt(dj);
-    __syncthreads();
-    for (int i = j + 1 + tid; i < s; i += 256) G[(int64_t)j * s + i] /= d;
-    if (tid == 0) G[(int64_t)j * s + j] = d;
-    __syncthreads();
-    const int m = s - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int c = j + 1 + e / m, i = j + 1 + e % m;
-      if (i >= c) G[(int64_t)c * s + i] -= G[(int64_t)j * s + i] * G[(int64_t)j * s + c];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < s * s; e += 256) {   // zero the strict upper triangle (read by the triangular solve)
-    const int c = e / s, i = e % s;
-    if (i < c) G[(int64_t)c * s + i] = 0.0;
-  }
-}
-
 // P(j) = sum_{c < s} G(j, c)^2 (G column-major, ld N).
 __global__ __launch_bounds__(256) void k_qr_rownorms(const double* __restrict__ G, int64_t N, int s,
                                                      double* __restrict__ P) {
@@ -121,14 +92,11 @@ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-void launch_dense_chol(hipStream_t s, double* G, int n, int* bad) {
-  hipLaunchKernelGGL(k_qr_chol, dim3(1), dim3(256), 0, s, G, n, bad);
-}
-
 namespace {
 
 struct QrLayout {
-  size_t st, u, csum, cpre, props, acc, hist, Fs, C, H, Tm, Gr, P, trace, bad, total;
+  size_t st, u, csum, cpre, props, acc, hist, Fs, C, H, Tm, Gr, Li, P, part, trace, bad, total;
+  size_t part_elems;
 };
 
 QrLayout qr_layout(int64_t M, int64_t N, int64_t k, int64_t b) {
@@ -152,7 +120,13 @@ QrLayout qr_layout(int64_t M, int64_t N, int64_t k, int64_t b) {
   l.H = take(sizeof(double) * b * b);
   l.Tm = take(sizeof(double) * k * b);
   l.Gr = take(sizeof(double) * b * b);
+  l.Li = take(sizeof(double) * b * b);
   l.P = take(sizeof(double) * N);
+  // split contractions over the M rows: H = C^* C, Q^* Q_perp, Q_perp^* Q_perp
+  size_t pe = dgemm_part_elems(b, b, M);
+  if (dgemm_part_elems(k, b, M) > pe) pe = dgemm_part_elems(k, b, M);
+  l.part_elems = pe;
+  l.part = take(sizeof(double) * pe);
   l.trace = take(sizeof(double));
   l.bad = take(sizeof(int));
   l.total = off;
@@ -170,26 +144,11 @@ arpc_status qr_validate(int64_t M, int64_t N, int64_t k, int64_t b, int64_t max_
   do {                                        \
     if ((x) != hipSuccess) return ARPC_EDEVICE; \
   } while (0)
-#define BCHK(x)                                         \
-  do {                                                  \
-    if ((x) != rocblas_status_success) return ARPC_EDEVICE; \
-  } while (0)
-
-struct Handle {
-  rocblas_handle h = nullptr;
-  ~Handle() {
-    if (h) (void)rocblas_destroy_handle(h);
-  }
-};
 
 arpc_status qr_run(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t seed, int64_t max_rounds,
                    const double* B, double* Q, double* F, int64_t* pivots, char* ws, const QrLayout& l,
                    hipStream_t s, arpc_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
-  Handle hb;
-  BCHK(rocblas_create_handle(&hb.h));
-  BCHK(rocblas_set_stream(hb.h, s));
-  rocblas_handle h = hb.h;
   Profiler prof(s, g_profiling);
   const Unif un{nullptr, 0, seed};
   const int64_t nch = (N + CHUNK - 1) / CHUNK;
@@ -203,9 +162,11 @@ arpc_status qr_run(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t seed, in
   double* H = (double*)(ws + l.H);
   double* Tm = (double*)(ws + l.Tm);
   double* Gr = (double*)(ws + l.Gr);
+  double* Li = (double*)(ws + l.Li);
   double* P = (double*)(ws + l.P);
+  double* part = (double*)(ws + l.part);
+  const size_t pe = l.part_elems;
   int* bad = (int*)(ws + l.bad);
-  const double one = 1.0, zero = 0.0, mone = -1.0;
   const int ib = (int)b;
   QCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
   QCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
@@ -226,11 +187,9 @@ arpc_status qr_run(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t seed, in
     hipLaunchKernelGGL(k_qr_cols, dim3((unsigned)((M + 255) / 256), (unsigned)b), dim3(256), 0, s, B, M, props, ib, C);
     if (kr > 0) {
       hipLaunchKernelGGL(k_qr_rows, dim3((unsigned)((kr * b + 255) / 256)), dim3(256), 0, s, F, N, props, ib, kr, Fs);
-      BCHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)M, ib, (rocblas_int)kr,
-                         &mone, Q, (rocblas_int)M, Fs, ib, &one, C, (rocblas_int)M));
+      QCHK(dgemm(s, false, true, M, ib, kr, -1.0, Q, M, Fs, ib, 1.0, C, M, part, pe));   // C -= Q F(S',:)^*
     }
-    BCHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, ib, ib, (rocblas_int)M, &one, C,
-                       (rocblas_int)M, C, (rocblas_int)M, &zero, H, ib));
+    QCHK(dgemm(s, true, false, ib, ib, M, 1.0, C, M, C, M, 0.0, H, ib, part, pe));          // H = C^* C
     prof.end();
     prof.begin(ARPC_KC_REJECT);
     launch_reject(s, H, ib, props, un, st, acc, pivots, u, k, false);
@@ -246,21 +205,20 @@ arpc_status qr_run(int64_t M, int64_t N, int64_t k, int64_t b, uint64_t seed, in
       prof.begin(ARPC_KC_PREP);
       hipLaunchKernelGGL(k_qr_take, dim3((unsigned)((M + 255) / 256), (unsigned)sr), dim3(256), 0, s, C, M, acc, sr,
                          Qn);
-      if (kr > 0) {
-        BCHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)kr, sr,
-                           (rocblas_int)M, &one, Q, (rocblas_int)M, Qn, (rocblas_int)M, &zero, Tm, (rocblas_int)kr));
-        BCHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)M, sr, (rocblas_int)kr,
-                           &mone, Q, (rocblas_int)M, Tm, (rocblas_int)kr, &one, Qn, (rocblas_int)M));
+      if (kr > 0) {   // one extra Gram-Schmidt pass: Q_perp -= Q (Q^* Q_perp)
+        QCHK(dgemm(s, true, false, kr, sr, M, 1.0, Q, M, Qn, M, 0.0, Tm, kr, part, pe));
+        QCHK(dgemm(s, false, false, M, sr, kr, -1.0, Q, M, Tm, kr, 1.0, Qn, M, part, pe));
       }
-      BCHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, sr, sr, (rocblas_int)M, &one, Qn,
-                         (rocblas_int)M, Qn, (rocblas_int)M, &zero, Gr, sr));
-      launch_dense_chol(s, Gr, sr, bad);
-      BCHK(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                         rocblas_diagonal_non_unit, (rocblas_int)M, sr, &one, Gr, sr, Qn, (rocblas_int)M));
+      // Cholesky QR: R^* R = Q_perp^* Q_perp (R^* = the lower factor in Gr),
+      // Q_perp <- Q_perp R^{-1} = Q_perp (R^{-*})^*, through C as scratch
+      QCHK(dgemm(s, true, false, sr, sr, M, 1.0, Qn, M, Qn, M, 0.0, Gr, sr, part, pe));
+      launch_chol_block(s, Gr, sr, sr, bad);
+      launch_trinv_lower(s, Gr, sr, sr, Li, sr);
+      QCHK(dgemm(s, false, true, M, sr, sr, 1.0, Qn, M, Li, sr, 0.0, C, M, part, pe));
+      QCHK(hipMemcpyAsync(Qn, C, sizeof(double) * (size_t)M * (size_t)sr, hipMemcpyDeviceToDevice, s));
       prof.end();
       prof.begin(ARPC_KC_COLGEMM);
-      BCHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)N, sr, (rocblas_int)M,
-                         &one, B, (rocblas_int)M, Qn, (rocblas_int)M, &zero, F + kr * N, (rocblas_int)N));
+      QCHK(dgemm(s, true, false, N, sr, M, 1.0, B, M, Qn, M, 0.0, F + kr * N, N, part, pe));   // G = B^* Q_perp
       prof.end();
       prof.begin(ARPC_KC_DIAG);
       hipLaunchKernelGGL(k_qr_rownorms, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, F + kr * N, N, sr, P);

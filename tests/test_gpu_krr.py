@@ -47,6 +47,31 @@ def test_krr_pcg_with_rpcholesky_preconditioner(prec):
     assert abs(st["iterations"] - it_ref) <= max(3, it_ref // 10)
 
 
+def test_krr_high_dimension_and_ragged_partitions():
+    """d = 40 (coordinates read from memory in the product with A, not held in
+    registers) and N = 4133, whose column partitions end in a short one: the
+    true residual and the oracle's PCG iteration count on the same F."""
+    from paper_2410_03969_amd import binding
+    X, y, sigma, mu = problem(N=4133, d=40, seed=5)
+    N = X.shape[0]
+    prob = W.Problem(N=N, d=40, k=250, b=25, kernel=W.MATERN52, sigma=sigma, seed=4, prec=W.FP64)
+    print(f"[gpu krr] N={N} d=40", flush=True)
+    sys.stdout.flush()
+    fac = binding.factor(X, prob)
+    F = fac["F"][:, : fac["stats"]["k_out"]]
+    tol = 1e-8
+    out = binding.krr_pcg(X, y, F, W.MATERN52, sigma, mu, tol=tol, max_iter=3000)
+    beta = out["beta"].cpu().numpy()
+    st = out["stats"]
+    A = kernel_block(X, slice(None), slice(None), W.MATERN52, sigma)
+    res = np.linalg.norm(A @ beta + mu * beta - y) / np.linalg.norm(y)
+    _, it_ref, _ = pcg(lambda v: A @ v + mu * v, woodbury_apply(F.cpu().numpy(), mu), y, tol, 3000)
+    print(f"d=40: iterations {st['iterations']} (oracle {it_ref}), true residual {res:.2e}")
+    assert out["status"] == 0 and st["rel_residual"] <= tol
+    assert res <= 1e-6
+    assert abs(st["iterations"] - it_ref) <= max(3, it_ref // 10)
+
+
 def test_krr_plain_cg_needs_many_more_iterations():
     from paper_2410_03969_amd import binding
     X, y, sigma, mu = problem(N=2000, seed=3)
