@@ -283,16 +283,26 @@ void arpc_set_profiling_classes(unsigned mask);
  *    its workspace (arpc_workspace_size of its problem, about N*k elements of
  *    the blocked factor copy plus O(N + b*k) more) fits in what is left of the
  *    context's HBM budget;
- *  - every admitted job runs on a stream of its own slot, one batch of rounds
- *    after another, so the rounds of different jobs overlap on the device;
+ *  - jobs in the BF16 modes whose rounds run as one kernel (d <= 16, b <= 256)
+ *    advance together in ticks: one tick runs one round of every such job,
+ *    with one kernel launch per round step serving all of them (the round
+ *    product once per group of jobs of the same compiled shape), from a
+ *    device table of the jobs' arguments; two ticks are kept in flight, and
+ *    a job joins the next tick after its admission;
+ *  - every other job runs on a stream of its own slot, one batch of rounds
+ *    after another (each round replayed from a HIP graph recorded once), so
+ *    its rounds overlap with the ticks and with other slots;
  *  - a finished job frees its slot and memory at once and the next job is
  *    admitted.
- * A job runs exactly the kernels and launch shapes of arpc_factor on its own
- * data, so its result does not depend on the other jobs.
+ * A job runs the same kernels as arpc_factor on its own data, with the same
+ * per-job work decomposition, so its result does not depend on the other
+ * jobs.  The environment variable ARPC_SERVE_TICKS=0 turns ticks off (every
+ * job on its slot stream) and ARPC_SERVE_GRAPHS=0 the graph replay.
  * The context owns one device allocation of the budget (made by arpc_create),
- * its streams and a scheduler thread; the caller owns every job's X, F and
- * pivots and must keep them alive and untouched until the job completes.
- * Calls on one context may come from several threads. */
+ * a small device table for the ticks, its streams and a scheduler thread; the
+ * caller owns every job's X, F and pivots and must keep them alive and
+ * untouched until the job completes.  Calls on one context may come from
+ * several threads. */
 typedef struct arpc_ctx_s* arpc_ctx;
 typedef uint64_t arpc_job;
 
@@ -307,6 +317,8 @@ typedef struct arpc_serving_stats {
   int64_t peak_bytes;    /* most budget bytes held at the same time */
   int64_t budget_bytes;  /* the context's budget */
   int64_t slots;         /* the context's slot count */
+  int64_t ticks;         /* ticks launched (one round of every ticked job each) */
+  int64_t ticked_jobs;   /* jobs admitted to ticks so far */
 } arpc_serving_stats;
 
 /* Create a serving context on HIP device `device` with a budget of

@@ -62,7 +62,7 @@ class ArpcServingStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
                 ("active", C.c_int64), ("queued", C.c_int64), ("peak_active", C.c_int64),
                 ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64), ("budget_bytes", C.c_int64),
-                ("slots", C.c_int64)]
+                ("slots", C.c_int64), ("ticks", C.c_int64), ("ticked_jobs", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

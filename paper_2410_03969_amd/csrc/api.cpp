@@ -84,6 +84,7 @@ Layout layout_of(const arpc_problem& p) {
     return o;
   };
   l.st = take(sizeof(RoundState));
+  l.jd = take(sizeof(RoundJob));
   l.u = take(sizeof(double) * p.N);
   l.csum = take(sizeof(double) * nch);
   l.cpre = take(sizeof(double) * nch);
@@ -138,18 +139,65 @@ KParams kparams_of(const arpc_problem& p) {
 
 
 
+RoundJob round_job_of(const arpc_problem& p, const Layout& l, char* ws, const double* X, void* F,
+                      int64_t* pivots, const Unif& un) {
+  RoundJob j{};
+  const int b = (int)p.b;
+  const int64_t N = p.N, k = p.k;
+  j.st = (RoundState*)(ws + l.st);
+  j.u = (double*)(ws + l.u);
+  j.csum = (double*)(ws + l.csum);
+  j.cpre = (double*)(ws + l.cpre);
+  j.nchunks = nchunks_of(N);
+  j.N = N;
+  j.X = X;
+  j.d = (int)p.d;
+  j.b = b;
+  j.un = un;
+  j.kp = kparams_of(p);
+  j.props = (int64_t*)(ws + l.props);
+  j.acc = (int32_t*)(ws + l.acc);
+  j.pivots = pivots;
+  j.kmax = k;
+  j.max_rounds = p.max_rounds;
+  j.keep_all = p.method == ARPC_BLOCK ? 1 : 0;
+  j.part_cols = l.part_cols;
+  j.F = F;
+  j.Fs = (double*)(ws + l.Fs);
+  j.ldf = k;
+  j.Hp = (double*)(ws + l.Hp);
+  j.parts = gather_splits(k);
+  j.W = gather_width(k);
+  j.H = (double*)(ws + l.H);
+  j.Xp = (double*)(ws + l.Xp);
+  j.P = (const double*)(ws + l.P);
+  j.hist = (int32_t*)(ws + l.hist);
+  j.Fb = ws + l.Fb;
+  j.nkc = (k + 31) / 32;
+  j.Bm1 = (unsigned char*)(ws + l.Bm1);
+  j.Bm2 = (unsigned char*)(ws + l.Bm2);
+  if (l.ncbt > 0) {
+    j.CP = 16 * l.ncbt;
+    j.nt = (l.ncbt + 1) / 2;
+    FusedRound fr{F, ws + l.Fb, j.nkc, N, X, j.d, j.Xp, j.kp, j.Bm1, j.Bm2, (double*)(ws + l.P), b, l.ncbt, l.grid};
+    j.fa = fused_args_of(gemm_prec(p.prec), fr, j.st);
+  }
+  return j;
+}
+
+// One round of a factorization.  tab: its table row in device memory (hj:
+// the host copy, g: its grids); the steps shared by every mode go through
+// the table launchers, the two-kernel and vector-unit products take their
+// arguments directly.
 template <typename T>
-void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, const Unif& un, char* ws,
-                   const Layout& l, const double* X, T* F, int64_t* pivots, Profiler& prof) {
+void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char* ws, const Layout& l,
+                   const double* X, T* F, const RoundJob* tab, const RoundJob& hj, const RoundGrid& g,
+                   Profiler& prof) {
   const int b = (int)p.b, d = (int)p.d;
-  const int64_t N = p.N, k = p.k, nch = nchunks_of(N);
+  const int64_t N = p.N, k = p.k;
   RoundState* st = (RoundState*)(ws + l.st);
-  double* u = (double*)(ws + l.u);
-  double* csum = (double*)(ws + l.csum);
-  double* cpre = (double*)(ws + l.cpre);
   int64_t* props = (int64_t*)(ws + l.props);
   int32_t* acc = (int32_t*)(ws + l.acc);
-  int32_t* hist = (int32_t*)(ws + l.hist);
   double* Fs = (double*)(ws + l.Fs);
   double* H = (double*)(ws + l.H);
   double* Xp = (double*)(ws + l.Xp);
@@ -159,26 +207,21 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
   double* P = (double*)(ws + l.P);
 
   prof.begin(ARPC_KC_PROPOSE);
-  launch_propose(s, u, csum, cpre, nch, N, b, un, st, props);
+  launch_propose_tab(s, tab, 1, g);
   prof.end();
-  MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
-               (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k, l.dist ? (void*)(ws + l.C0) : nullptr,
-               l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr};
   prof.begin(ARPC_KC_GATHER);
-  launch_gather<T>(s, F, N, X, d, kp, props, b, Fs, k, k, (double*)(ws + l.Hp), H, st);
+  launch_gather_tab(s, tab, 1, g, sizeof(T) == sizeof(double), d > 32);
   prof.end();
   prof.begin(ARPC_KC_REJECT);
-  launch_reject(s, H, b, props, un, st, acc, pivots, u, k, p.method == ARPC_BLOCK);
+  launch_reject_tab(s, tab, 1, b);
   prof.end();
   if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
-    FusedRound fr{F, ws + l.Fb, (k + 31) / 32, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1),
-                  (unsigned char*)(ws + l.Bm2), P, b, l.ncbt, l.grid};
     prof.begin(ARPC_KC_PREP);
-    launch_prep_xp(s, acc, props, X, d, Xp, st);
-    launch_fused_prep(s, gemm_prec(p.prec), fr, props, acc, H, st);
+    launch_prep_xp_tab(s, tab, 1);
+    launch_fused_prep_tab(s, gemm_prec(p.prec), tab, 1, l.ncbt);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
-    launch_fused_round(s, gemm_prec(p.prec), fr, st);
+    launch_fused_round_tab(s, gemm_prec(p.prec), l.ncbt, d, hj.fa, tab, 1, fused_grid_of(gemm_prec(p.prec), hj.fa, l.grid));
     prof.end();
   } else if (l.valu) {  // vector-unit kernels (cross-check path)
     prof.begin(ARPC_KC_PREP);
@@ -191,8 +234,11 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
     launch_trsm<T>(s, C, N, Bt2, b, F, P, st);
     prof.end();
   } else {
+    MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
+                 (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k, l.dist ? (void*)(ws + l.C0) : nullptr,
+                 l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr};
     prof.begin(ARPC_KC_PREP);
-    launch_prep_xp(s, acc, props, X, d, Xp, st);
+    launch_prep_xp_tab(s, tab, 1);
     launch_mfma_prep(s, gemm_prec(p.prec), mr, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
@@ -204,10 +250,10 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, cons
     prof.end();
   }
   prof.begin(ARPC_KC_DIAG);
-  launch_diag(s, u, csum, P, l.part_cols, N, nch, st);
+  launch_diag_tab(s, tab, 1, g);
   prof.end();
   prof.begin(ARPC_KC_FINISH);
-  launch_finish(s, st, b, k, p.max_rounds, hist);
+  launch_finish_tab(s, tab, 1);
   prof.end();
 }
 
@@ -238,11 +284,15 @@ struct Job final : JobBase {
   hipGraphExec_t round_graph = nullptr;
 
   const double* Xin;   // the caller's points (X: the points every round reads)
+  RoundJob hj;         // the round kernels' table row (host copy; the device copy is at ws + l.jd)
+  RoundGrid g;
 
   Job(const arpc_problem& p_, const double* X_, T* F_, int64_t* piv_, char* ws_, const Layout& l_,
       hipStream_t s_, const Unif& un_, RoundState* h_, Profiler* prof_)
       : p(p_), X(p_.prec == ARPC_FP8 ? (const double*)(ws_ + l_.Xq) : X_), F(F_), pivots(piv_), ws(ws_), l(l_),
-        s(s_), un(un_), kp(kparams_of(p_)), hstate(h_), prof(prof_), Xin(X_) {}
+        s(s_), un(un_), kp(kparams_of(p_)), hstate(h_), prof(prof_), Xin(X_),
+        hj(round_job_of(p_, l_, ws_, X, F_, piv_, un_)), g(round_grid_of(hj)) {}
+  const RoundJob& row() const override { return hj; }
   ~Job() override {
     if (round_graph) (void)hipGraphExecDestroy(round_graph);
   }
@@ -251,6 +301,7 @@ struct Job final : JobBase {
     RoundState* st = (RoundState*)(ws + l.st);
     const int64_t nch = nchunks_of(p.N);
     HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
+    HIPCHK(hipMemcpyAsync(ws + l.jd, &hj, sizeof(RoundJob), hipMemcpyHostToDevice, s));
     prof->begin(ARPC_KC_INIT);
     if (p.prec == ARPC_FP8) launch_round_e4m3(s, Xin, (double*)(ws + l.Xq), p.N * p.d);
     if (l.packed)
@@ -265,13 +316,13 @@ struct Job final : JobBase {
   // device memory, so the same graph serves every round of this job).
   arpc_status capture_round() override {
     Profiler off(s, false);
-    hipGraph_t g = nullptr;
+    hipGraph_t gr = nullptr;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    enqueue_round<T>(s, p, kp, un, ws, l, X, F, pivots, off);
-    const hipError_t e = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess || !g) return ARPC_EDEVICE;
-    const hipError_t ei = hipGraphInstantiate(&round_graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
+    enqueue_round<T>(s, p, kp, ws, l, X, F, (const RoundJob*)(ws + l.jd), hj, g, off);
+    const hipError_t e = hipStreamEndCapture(s, &gr);
+    if (e != hipSuccess || !gr) return ARPC_EDEVICE;
+    const hipError_t ei = hipGraphInstantiate(&round_graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
     if (ei != hipSuccess) {
       round_graph = nullptr;
       return ARPC_EDEVICE;
@@ -287,7 +338,7 @@ struct Job final : JobBase {
     if (batch < 1) batch = 1;
     for (int64_t r = 0; r < batch; ++r) {
       if (round_graph) HIPCHK(hipGraphLaunch(round_graph, s));
-      else enqueue_round<T>(s, p, kp, un, ws, l, X, F, pivots, *prof);
+      else enqueue_round<T>(s, p, kp, ws, l, X, F, (const RoundJob*)(ws + l.jd), hj, g, *prof);
     }
     enqueued += batch;
     HIPCHK(hipGetLastError());
@@ -299,6 +350,43 @@ struct Job final : JobBase {
     if (hstate->status != ST_RUNNING) return false;
     known_k = hstate->k_r;
     return true;
+  }
+
+  // Batched form of the end of a run (serving ticks): enqueue the residual
+  // trace into *htrace and the zero tails of F and pivots for the final
+  // state h (read by the caller after the last tick that ran this job);
+  // finish_stats then fills the statistics once the stream has passed them.
+  arpc_status finish_enqueue(const RoundState& h, double* htrace) override {
+    const int64_t N = p.N, nch = nchunks_of(N);
+    double* tr = (double*)(ws + l.trace);
+    launch_trace(s, (double*)(ws + l.csum), nch, tr);
+    HIPCHK(hipMemcpyAsync(htrace, tr, sizeof(double), hipMemcpyDeviceToHost, s));
+    const int64_t k_out = h.k_r;
+    if (k_out < p.k && !h.nonfinite) {
+      HIPCHK(hipMemsetAsync(F + k_out * N, 0, sizeof(T) * (size_t)(p.k - k_out) * N, s));
+      HIPCHK(hipMemsetAsync(pivots + k_out, 0xff, sizeof(int64_t) * (size_t)(p.k - k_out), s));
+    }
+    HIPCHK(hipGetLastError());
+    return ARPC_OK;
+  }
+
+  arpc_status finish_stats(const RoundState& h, double trace_resid, arpc_stats* stats) override {
+    if (h.nonfinite) return ARPC_ENUMERIC;
+    arpc_status ret = (h.k_r == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE))
+                          ? ARPC_OK
+                          : ARPC_EARLY_STOP;
+    if (h.status == ST_NOUNIF) ret = ARPC_EINVAL;
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->k_out = h.k_r;
+      stats->rounds = h.round;
+      stats->proposals = h.proposals;
+      stats->status = ret;
+      stats->fused = l.ncbt > 0 ? 1 : 0;
+      stats->trace_A = h.trace_A;
+      stats->trace_resid = trace_resid;
+    }
+    return ret;
   }
 
   arpc_status finish(arpc_stats* stats, double ms_total) override {

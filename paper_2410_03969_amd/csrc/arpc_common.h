@@ -146,6 +146,106 @@ __device__ __attribute__((always_inline)) inline float kappa_fast(float r2, cons
   return poly * __builtin_amdgcn_exp2f(-k.q * t);
 }
 
+// Arguments of the one-kernel round product of the BF16 modes (see
+// fused_kernels.hip).
+struct FusedArgs {
+  const __bf16* Fb;         // panel-blocked BF16 planes of F
+  int64_t nkc;              // chunks per panel of Fb
+  int64_t N;
+  const unsigned char* Bm1; // F(S_r,:)^T in chunks
+  const unsigned char* Bm2; // permuted inverse factor in chunks
+  const double* X;          // N x d
+  int d;
+  const double* Xp;         // s_r x d accepted points
+  KFast kf;
+  float* Fu;                // F, column-major, ld N
+  __bf16* Fbw;              // Fb (written)
+  double* P;                // row norms of G
+  const RoundState* st;
+  int ntiles;
+};
+
+// Device pointers and sizes of one factorization that the round kernels read
+// (the proposals, the residual submatrix, RejectionSampleSubmatrix, the
+// accepted points, the diagonal update, the round control and, in the BF16
+// modes, the one-kernel round product).  Every such kernel takes a table of
+// these and serves the factorization in row blockIdx.y of the table, so one
+// launch can advance the rounds of several factorizations (serving), or of
+// one (a table of one row).  Per-round values (k_r, s_r, the round) are read
+// from the round state, so a table row does not change during a run.
+struct RoundJob {
+  RoundState* st;
+  double* u;              // residual diagonal (N)
+  double* csum;           // its chunk sums
+  double* cpre;           // their inclusive prefix
+  int64_t nchunks;
+  int64_t N;
+  const double* X;        // N x d points, row-major (the rounded copy in the FP8 mode)
+  int d;
+  int b;
+  Unif un;
+  KParams kp;
+  int64_t* props;         // b proposals
+  int32_t* acc;           // accepted local indices
+  int64_t* pivots;        // k outputs
+  int64_t kmax;           // k
+  int64_t max_rounds;
+  int keep_all;           // block RPCholesky (Alg. 7)
+  int part_cols;          // columns per partial row-norm group of P
+  const void* F;          // N x k column-major factor (FP64 or FP32)
+  double* Fs;             // F rows at the proposals, FP64, ld ldf
+  int64_t ldf;
+  double* Hp;             // partial products of F(S',:) F(S',:)^T
+  int64_t W;              // contraction columns per partition of Hp
+  int parts;
+  double* H;              // b x b residual submatrix, then L(T,T)
+  double* Xp;             // accepted points
+  const double* P;        // partial row norms of G
+  int32_t* hist;          // accepted count per round
+  const void* Fb;         // BF16 modes: panel-blocked copy of F
+  int64_t nkc;
+  unsigned char* Bm1;
+  unsigned char* Bm2;
+  int CP;                 // padded column count of the round product
+  int nt;                 // 32-column chunks of the inverse factor
+  FusedArgs fa;
+};
+
+// A table row read as kernel arguments are: through the constant address
+// space, so the compiler uses scalar loads into scalar registers (the table
+// is written before the launch and not changed by it).
+typedef const __attribute__((address_space(4))) RoundJob ConstRoundJob;
+
+__device__ __forceinline__ ConstRoundJob& table_row(const RoundJob* tab) {
+  return ((ConstRoundJob*)tab)[blockIdx.y];
+}
+
+// A copy of a member of such a row (a struct), word by word through the
+// constant address space.
+template <class T>
+__device__ __forceinline__ T ldc_any(const T& x) { return x; }
+
+template <class T>
+__device__ __forceinline__ T ldc(const __attribute__((address_space(4))) T& x) {
+  static_assert(sizeof(T) % 4 == 0, "word copy");
+  T v;
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)&x;
+  uint32_t* dst = (uint32_t*)&v;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T ldc_any(const __attribute__((address_space(4))) T& x) { return ldc(x); }
+
+// The table row of this workgroup (TAB), or the single job passed by value.
+template <bool TAB>
+__device__ __forceinline__ ConstRoundJob& job_of(const RoundJob& j0, const RoundJob* tab) {
+  if constexpr (TAB) return table_row(tab);
+  else return *(ConstRoundJob*)&j0;
+}
+
 __device__ inline double readlane_f64(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);

@@ -11,12 +11,14 @@
 
 #include "../../include/arpc.h"
 #include "arpc_common.h"
+#include "arpc_launch.h"
 
 namespace arpc {
 
 // Offsets of the buffers carved from one factorization's workspace.
 struct Layout {
-  size_t st, u, csum, cpre, props, acc, hist, Fs, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, trace, total;
+  size_t st, jd, u, csum, cpre, props, acc, hist, Fs, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, trace,
+      total;
   bool dist;  // kernel columns precomputed on the matrix cores (two-kernel path, d > 16 or FP8 mode)
   bool packed;  // FP8 mode, d % 4 == 0: the points also as e4m3 codes (X8) with their norms (xn8)
   int part_cols;
@@ -80,11 +82,14 @@ struct Profiler {
 // One factorization driven by the host (see Job in api.cpp).
 struct JobBase {
   virtual ~JobBase() {}
+  virtual const RoundJob& row() const = 0;
   virtual arpc_status begin() = 0;
   virtual arpc_status capture_round() = 0;
   virtual arpc_status enqueue_batch() = 0;
   virtual bool running() = 0;
   virtual arpc_status finish(arpc_stats* stats, double ms_total) = 0;
+  virtual arpc_status finish_enqueue(const RoundState& h, double* htrace) = 0;
+  virtual arpc_status finish_stats(const RoundState& h, double trace_resid, arpc_stats* stats) = 0;
 };
 
 extern unsigned g_profiling;   // timed kernel classes (arpc_set_profiling*)
@@ -96,6 +101,11 @@ arpc_status check_factor_args(const arpc_problem* p, const double* X, const void
 std::unique_ptr<JobBase> make_job(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws,
                                   const Layout& l, hipStream_t s, const Unif& un, RoundState* hstate,
                                   Profiler* prof);
+// The round kernels' table row of a factorization whose workspace ws has
+// layout l (X: the points the rounds read, the rounded copy in the FP8 mode).
+RoundJob round_job_of(const arpc_problem& p, const Layout& l, char* ws, const double* X, void* F,
+                      int64_t* pivots, const Unif& un);
+int gemm_prec(int prec);
 // Checks the arguments, carves the workspace and runs the factorization to
 // completion on `stream` (the host waits between batches of rounds).  timed:
 // honour the process-wide profiling switch (else no events are created).

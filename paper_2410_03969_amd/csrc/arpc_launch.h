@@ -11,9 +11,6 @@ void launch_init(hipStream_t s, double* u, double* csum, const double* X, int64_
 // (the state must have been zeroed; a set nonfinite flag stops the run).
 void launch_init_from_diag(hipStream_t s, const double* u, int64_t N, double* csum, RoundState* st,
                            int64_t nchunks);
-// In-place lower Cholesky factor of the n x n matrix G (column-major, ld n;
-// the strict upper triangle is zeroed), one workgroup; a non-positive pivot
-// is replaced by 1 and sets *bad.
 // Xq = X with every coordinate rounded to FP8 e4m3 (the FP8 mode's points), n values.
 void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n);
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
@@ -22,10 +19,8 @@ void launch_propose(hipStream_t s, const double* u, const double* csum, double* 
 // H (its partial products are summed in partition order); Hp holds
 // gather_splits(kmax) * b * b doubles.
 int gather_splits(int64_t kmax);
-template <typename T>
-void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
-                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* Hp, double* H,
-                   const RoundState* st);
+// Contraction columns per partition of Hp at this kmax.
+int64_t gather_width(int64_t kmax);
 // H = kappa(X(props), X(props)) (b x b, column-major), direct differences in FP64.
 void launch_kernel_block(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b, double* H,
                          const RoundState* st);
@@ -41,6 +36,25 @@ void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int pa
                  int64_t nchunks, const RoundState* st);
 void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist);
 void launch_trace(hipStream_t s, const double* csum, int64_t nchunks, double* out);
+
+// The same round steps over a device table of n jobs (RoundJob rows; one
+// launch per step serves them all, row blockIdx.y per workgroup).  The grid
+// of each step is the largest any row needs; rows that need fewer workgroups
+// leave the rest idle.
+struct RoundGrid {
+  unsigned propose, gather_rows, gather_hp, gather_hs, diag;
+};
+RoundGrid round_grid_of(const RoundJob& j);
+void round_grid_max(RoundGrid& g, const RoundGrid& other);
+void launch_propose_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g);
+// fdouble: F is FP64; tiled: the residual submatrix form for d > 32
+void launch_gather_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g, bool fdouble, bool tiled);
+void launch_reject_tab(hipStream_t s, const RoundJob* tab, int n, int bmax);
+void launch_prep_xp_tab(hipStream_t s, const RoundJob* tab, int n);
+void launch_diag_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g);
+void launch_finish_tab(hipStream_t s, const RoundJob* tab, int n);
+// out[i] = *tab[i].st for i < n (out: pinned host memory).
+void launch_collect_tab(hipStream_t s, const RoundJob* tab, int n, RoundState* out);
 
 // Update GEMM (Alg. 2 step 3, first factor): C = A(:,S_r) - F F(S_r,:)^T,
 // kernel columns evaluated from the points in the epilogue.

@@ -59,9 +59,17 @@ struct FusedRound {
 // path does not apply (FP64/FP32 modes, b > 256).
 int fused_ncbt(int prec, int b);
 size_t fused_operand_bytes(int prec, int64_t kmax, int b);
-void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
-                       const double* H, const RoundState* st);
-void launch_fused_round(hipStream_t s, int prec, const FusedRound& r, const RoundState* st);
+// Arguments of the round product for one job (the round state at st), and
+// its persistent grid given two workgroups per compute unit (grid2).
+FusedArgs fused_args_of(int prec, const FusedRound& r, const RoundState* st);
+int fused_grid_of(int prec, const FusedArgs& a, int grid2);
+// F(S_r,:)^T chunks and the permuted inverse factor, then the round product,
+// over a device table of n jobs with the same mode and column-block count
+// (and, for the product, the same coordinate class d <= 8 or <= 16 and the
+// same kernel form as `any`); grid: workgroups per job.
+void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, int ncbt);
+void launch_fused_round_tab(hipStream_t s, int prec, int ncbt, int d, const FusedArgs& any, const RoundJob* tab,
+                            int n, int grid);
 
 size_t mfma_operand_bytes(int prec, int64_t kmax, int b);
 size_t mfma_blocked_bytes(int prec, int64_t N, int64_t cols);

@@ -56,22 +56,6 @@ __host__ __device__ constexpr int tri_base(int mt) {
   return b;
 }
 
-struct FusedArgs {
-  const __bf16* Fb;         // panel-blocked BF16 planes of F
-  int64_t nkc;              // chunks per panel of Fb
-  int64_t N;
-  const unsigned char* Bm1; // F(S_r,:)^T in chunks
-  const unsigned char* Bm2; // permuted inverse factor in chunks
-  const double* X;          // N x d
-  int d;
-  const double* Xp;         // s_r x d accepted points
-  KFast kf;
-  float* Fu;                // F, column-major, ld N
-  __bf16* Fbw;              // Fb (written)
-  double* P;                // row norms of G
-  const RoundState* st;
-  int ntiles;
-};
 
 // Slot of contraction index t (0..31) inside a t-chunk of the solve.
 __host__ __device__ inline int solve_slot(int t) {
@@ -88,8 +72,17 @@ __device__ inline void split_hi_lo(float x, __bf16& hi, __bf16& lo) {
 // solve needs no staging; otherwise its chunks stream through the ring (two
 // 4-wavefront workgroups per CU, for the three-product mode whose two planes
 // do not fit).
-template <int PASSES, int NCBT, int DX, int FD, int FW, bool RES, bool UR>
-__global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_round(FusedArgs a) {
+// TAB: the arguments come from row blockIdx.y of a table of jobs (one launch
+// serving several factorizations), else from the kernel argument.
+template <int PASSES, int NCBT, int DX, int FD, int FW, bool RES, bool UR, bool TAB>
+__global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_round(
+    FusedArgs a0, const RoundJob* __restrict__ tab) {
+  // arguments read where they are used, as kernel arguments are (the
+  // compiler may reload them instead of holding them in registers)
+  auto&& a = [&]() -> decltype(auto) {
+    if constexpr (TAB) return (table_row(tab).fa);
+    else return (a0);
+  }();
   constexpr int SPL = PASSES == 3 ? 2 : 1;
   constexpr int CP = NCBT * 16;                 // padded column count
   constexpr int NT = (NCBT + 1) / 2;            // t-chunks of the solve
@@ -137,7 +130,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   // phi(sqrt(cr) r) with phi(t) = (1 + p1 t + p2 t^2) 2^(-q t) (use_r) or
   // phi(r^2) = 2^(-cr r^2) (Gaussian), so one scaled squared distance
   // e = cr |x - y|^2 is all a column needs.
-  const KFast kf = a.kf;
+  const KFast kf = ldc_any(a.kf);
   const float cr = UR ? kf.scale * kf.scale : kf.q * kf.scale;
   // accepted points in FP32, zero-padded to DX coordinates and CP columns.
   // Expanded form: r^2 = |x|^2 + |y|^2 - 2 x.y, the product on the matrix
@@ -601,11 +594,16 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 }
 
 // Bm1 chunk j, column c: the blocked slice of F at row S_r(c) (zero for c >= s).
-template <int SPL>
-__global__ __launch_bounds__(256) void k_fused_bm1(const __bf16* __restrict__ Fb, int64_t nkc,
-                                                   const int64_t* __restrict__ props,
-                                                   const int32_t* __restrict__ acc, int CP,
-                                                   unsigned char* __restrict__ Bm1, const RoundState* st) {
+template <int SPL, bool TAB>
+__global__ __launch_bounds__(256) void k_fused_bm1(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const __bf16* __restrict__ Fb = (const __bf16*)RJ.Fb;
+  const int64_t nkc = RJ.nkc;
+  const int64_t* __restrict__ props = RJ.props;
+  const int32_t* __restrict__ acc = RJ.acc;
+  const int CP = RJ.CP;
+  unsigned char* __restrict__ Bm1 = RJ.Bm1;
+  const RoundState* st = RJ.st;
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int64_t nk = (st->k_r + FKC - 1) / FKC;
@@ -627,9 +625,14 @@ __global__ __launch_bounds__(256) void k_fused_bm1(const __bf16* __restrict__ Fb
 // indices), one workgroup per column t: forward substitution, then Linv(i, t)
 // stored at chunk t / 32, slot
 // solve_slot(t % 32), column i (zero outside i, t < s and below the diagonal).
-template <int SPL, bool RES>
-__global__ __launch_bounds__(64) void k_fused_linv(LFactor L, int CP, unsigned char* __restrict__ Bm2,
-                                                   const RoundState* st) {
+template <int SPL, bool RES, bool TAB>
+__global__ __launch_bounds__(64) void k_fused_linv(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const LFactor L{RJ.H, RJ.acc, RJ.b};
+  const int CP = RJ.CP;
+  unsigned char* __restrict__ Bm2 = RJ.Bm2;
+  const RoundState* st = RJ.st;
+  if ((int)blockIdx.x >= RJ.nt * FKC) return;
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
@@ -682,37 +685,38 @@ struct FusedShape {
   static constexpr int FD = PASSES == 3 ? 2 : 4;
 };
 
-template <int PASSES, int NCBT, int DX>
-void launch_fused_t(hipStream_t s, const FusedRound& r, const RoundState* st) {
+template <int PASSES, int NCBT, int DX, bool TAB>
+void launch_fused_t(hipStream_t s, const FusedArgs& a, const RoundJob* tab, int n, int grid) {
   using SH = FusedShape<PASSES>;
-  constexpr int FROWS = SH::FW * FNB * 16;
-  FusedArgs a{(const __bf16*)r.Fb, r.nkc, r.N, r.Bm1, r.Bm2, r.X, r.d, r.Xp, kfast_of(r.kp), (float*)r.F,
-              (__bf16*)r.Fb, r.P, st, (int)((r.N + FROWS - 1) / FROWS)};
-  int grid = r.grid / 2 * SH::PER_CU;   // r.grid is two per CU
-  if (grid > a.ntiles) grid = a.ntiles;
   if (a.kf.use_r)
-    hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES, true>), dim3(grid),
-                       dim3(64 * SH::FW), 0, s, a);
+    hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES, true, TAB>), dim3(grid, n),
+                       dim3(64 * SH::FW), 0, s, a, tab);
   else
-    hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES, false>), dim3(grid),
-                       dim3(64 * SH::FW), 0, s, a);
+    hipLaunchKernelGGL((k_fused_round<PASSES, NCBT, DX, SH::FD, SH::FW, SH::RES, false, TAB>), dim3(grid, n),
+                       dim3(64 * SH::FW), 0, s, a, tab);
 }
 
-template <int PASSES, int NCBT>
-void launch_fused_d(hipStream_t s, const FusedRound& r, const RoundState* st) {
-  if (r.d <= 8) launch_fused_t<PASSES, NCBT, 8>(s, r, st);
-  else launch_fused_t<PASSES, NCBT, 16>(s, r, st);
+template <int PASSES, int NCBT, bool TAB>
+void launch_fused_d(hipStream_t s, int dx, const FusedArgs& a, const RoundJob* tab, int n, int grid) {
+  if (dx <= 8) launch_fused_t<PASSES, NCBT, 8, TAB>(s, a, tab, n, grid);
+  else launch_fused_t<PASSES, NCBT, 16, TAB>(s, a, tab, n, grid);
+}
+
+template <int PASSES, bool TAB>
+void launch_fused_p(hipStream_t s, int ncbt, int dx, const FusedArgs& a, const RoundJob* tab, int n, int grid) {
+  switch (ncbt) {
+    case 2: launch_fused_d<PASSES, 2, TAB>(s, dx, a, tab, n, grid); break;
+    case 4: launch_fused_d<PASSES, 4, TAB>(s, dx, a, tab, n, grid); break;
+    case 8: launch_fused_d<PASSES, 8, TAB>(s, dx, a, tab, n, grid); break;
+    case 13: launch_fused_d<PASSES, 13, TAB>(s, dx, a, tab, n, grid); break;
+    default: launch_fused_d<PASSES, 16, TAB>(s, dx, a, tab, n, grid); break;
+  }
 }
 
 template <int PASSES>
-void launch_fused_p(hipStream_t s, const FusedRound& r, const RoundState* st) {
-  switch (r.ncbt) {
-    case 2: launch_fused_d<PASSES, 2>(s, r, st); break;
-    case 4: launch_fused_d<PASSES, 4>(s, r, st); break;
-    case 8: launch_fused_d<PASSES, 8>(s, r, st); break;
-    case 13: launch_fused_d<PASSES, 13>(s, r, st); break;
-    default: launch_fused_d<PASSES, 16>(s, r, st); break;
-  }
+int fused_rows() {
+  using SH = FusedShape<PASSES>;
+  return SH::FW * FNB * 16;
 }
 
 }  // namespace
@@ -735,25 +739,33 @@ size_t fused_operand_bytes(int prec, int64_t kmax, int b) {
   return streamed > resident ? streamed : resident;
 }
 
-void launch_fused_prep(hipStream_t s, int prec, const FusedRound& r, const int64_t* props, const int32_t* acc,
-                       const double* H, const RoundState* st) {
-  const LFactor L{H, acc, r.b};
-  const int cp = 16 * r.ncbt;
-  const int nt = (r.ncbt + 1) / 2;
+FusedArgs fused_args_of(int prec, const FusedRound& r, const RoundState* st) {
+  const int rows = prec == 2 ? fused_rows<3>() : fused_rows<1>();
+  return FusedArgs{(const __bf16*)r.Fb, r.nkc, r.N, r.Bm1, r.Bm2, r.X, r.d, r.Xp, kfast_of(r.kp), (float*)r.F,
+                   (__bf16*)r.Fb, r.P, st, (int)((r.N + rows - 1) / rows)};
+}
+
+int fused_grid_of(int prec, const FusedArgs& a, int grid2) {
+  const int per_cu = prec == 2 ? FusedShape<3>::PER_CU : FusedShape<1>::PER_CU;
+  int g = grid2 / 2 * per_cu;   // grid2 is two per compute unit
+  return g > a.ntiles ? a.ntiles : (g < 1 ? 1 : g);
+}
+
+void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, int ncbt) {
+  const int nt = (ncbt + 1) / 2;
   if (prec == 2) {
-    hipLaunchKernelGGL(k_fused_bm1<2>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
-                       r.Bm1, st);
-    hipLaunchKernelGGL((k_fused_linv<2, false>), dim3(nt * FKC), dim3(64), 0, s, L, cp, r.Bm2, st);
+    hipLaunchKernelGGL((k_fused_bm1<2, true>), dim3(512, n), dim3(256), 0, s, RoundJob{}, tab);
+    hipLaunchKernelGGL((k_fused_linv<2, false, true>), dim3(nt * FKC, n), dim3(64), 0, s, RoundJob{}, tab);
   } else {
-    hipLaunchKernelGGL(k_fused_bm1<1>, dim3(512), dim3(256), 0, s, (const __bf16*)r.Fb, r.nkc, props, acc, cp,
-                       r.Bm1, st);
-    hipLaunchKernelGGL((k_fused_linv<1, true>), dim3(nt * FKC), dim3(64), 0, s, L, cp, r.Bm2, st);
+    hipLaunchKernelGGL((k_fused_bm1<1, true>), dim3(512, n), dim3(256), 0, s, RoundJob{}, tab);
+    hipLaunchKernelGGL((k_fused_linv<1, true, true>), dim3(nt * FKC, n), dim3(64), 0, s, RoundJob{}, tab);
   }
 }
 
-void launch_fused_round(hipStream_t s, int prec, const FusedRound& r, const RoundState* st) {
-  if (prec == 2) launch_fused_p<3>(s, r, st);
-  else launch_fused_p<1>(s, r, st);
+void launch_fused_round_tab(hipStream_t s, int prec, int ncbt, int d, const FusedArgs& any, const RoundJob* tab,
+                            int n, int grid) {
+  if (prec == 2) launch_fused_p<3, true>(s, ncbt, d, any, tab, n, grid);
+  else launch_fused_p<1, true>(s, ncbt, d, any, tab, n, grid);
 }
 
 }  // namespace arpc

@@ -114,9 +114,15 @@ __global__ __launch_bounds__(1024) void k_init_state(const double* __restrict__ 
 // ------------------------------------------------------------------- proposals
 // Inclusive prefix of the chunk sums in a fixed order (one workgroup), the
 // residual trace T = sum(u) as its last value, and the early stop when T <= 0.
-__global__ __launch_bounds__(1024) void k_scan_chunks(const double* __restrict__ csum, int64_t nchunks,
-                                                      double* __restrict__ cpre, int b, Unif un,
-                                                      RoundState* st) {
+template <bool TAB>
+__global__ __launch_bounds__(1024) void k_scan_chunks(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const double* __restrict__ csum = RJ.csum;
+  const int64_t nchunks = RJ.nchunks;
+  double* __restrict__ cpre = RJ.cpre;
+  const int b = RJ.b;
+  const Unif un = ldc(RJ.un);
+  RoundState* st = RJ.st;
   if (st->status != ST_RUNNING) return;
   __shared__ double wsum[16];
   __shared__ int64_t lastpos_sh[1024];
@@ -167,9 +173,16 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(const double* __restrict__
 // index with u_j > 0 (in the last positive chunk) is taken.
 constexpr int PROPOSE_WAVES = 4;
 
-__global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(
-    const double* __restrict__ u, const double* __restrict__ cpre, int64_t nchunks, int64_t N,
-    int b, Unif un, const RoundState* st, int64_t* __restrict__ props) {
+template <bool TAB>
+__global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const double* __restrict__ u = RJ.u;
+  const double* __restrict__ cpre = RJ.cpre;
+  const int64_t nchunks = RJ.nchunks, N = RJ.N;
+  const int b = RJ.b;
+  const Unif un = ldc(RJ.un);
+  const RoundState* st = RJ.st;
+  int64_t* __restrict__ props = RJ.props;
   if (st->status != ST_RUNNING) return;
   const int lane = threadIdx.x & 63;
   const int l = blockIdx.x * PROPOSE_WAVES + (threadIdx.x >> 6);
@@ -227,16 +240,22 @@ __global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(
 // ------------------------------------------------------- gathers at proposals
 typedef double rd4 __attribute__((ext_vector_type(4)));
 
-// Fs(i, c) = F(props_i, c) in FP64, row-major with leading dimension ldf.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ F, int64_t N,
-                                                     const int64_t* __restrict__ props,
-                                                     double* __restrict__ Fs, int64_t ldf,
-                                                     const RoundState* st) {
+// Fs(i, c) = F(props_i, c) in FP64, row-major with leading dimension ldf;
+// ceil(kmax / 256) workgroups per proposal.
+template <typename T, bool TAB>
+__global__ __launch_bounds__(256) void k_gather_rows(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const T* __restrict__ F = (const T*)RJ.F;
+  const int64_t N = RJ.N, ldf = RJ.ldf;
+  const int64_t* __restrict__ props = RJ.props;
+  double* __restrict__ Fs = RJ.Fs;
+  const RoundState* st = RJ.st;
+  const int64_t gx = (RJ.kmax + 255) / 256;
+  if ((int64_t)blockIdx.x >= gx * RJ.b) return;
   if (st->status != ST_RUNNING) return;
   const int64_t kr = st->k_r;
-  const int i = blockIdx.y;
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int i = (int)(blockIdx.x / gx);
+  const int64_t c = (int64_t)(blockIdx.x % gx) * 256 + threadIdx.x;
   if (c >= kr) return;
   Fs[(int64_t)i * ldf + c] = (double)F[c * N + props[i]];
 }
@@ -253,14 +272,23 @@ __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ F, in
 // the result does not depend on scheduling, and a diagonal tile takes every
 // entry from its lower half, so each Hp(p), and H, is exactly symmetric.
 // The split keeps enough workgroups busy at any k_r.
-__global__ __launch_bounds__(256) void k_gather_Hp(int b, const double* __restrict__ Fs, int64_t ldf, int64_t W,
-                                                   double* __restrict__ Hp, const RoundState* st) {
+template <bool TAB>
+__global__ __launch_bounds__(256) void k_gather_Hp(RoundJob jb0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(jb0, tab);
+  const int b = RJ.b;
+  const double* __restrict__ Fs = RJ.Fs;
+  const int64_t ldf = RJ.ldf, W = RJ.W;
+  double* __restrict__ Hp = RJ.Hp;
+  const RoundState* st = RJ.st;
+  // workgroup (x, y, z) of an nb x nb x parts grid, folded into blockIdx.x
+  const int nb = (b + 15) / 16;
+  if ((int64_t)blockIdx.x >= (int64_t)nb * nb * RJ.parts) return;
+  const int x = (int)(blockIdx.x % nb), y = (int)((blockIdx.x / nb) % nb), z = (int)(blockIdx.x / (nb * nb));
   if (st->status != ST_RUNNING) return;
-  const int x = blockIdx.x, y = blockIdx.y;
   if (x > y) return;
   const int64_t kr = st->k_r;
   const int i0 = 16 * y, j0 = 16 * x;
-  const int64_t cbeg = (int64_t)blockIdx.z * W;
+  const int64_t cbeg = (int64_t)z * W;
   const int64_t cend = (cbeg + W < kr) ? cbeg + W : kr;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const bool ai = i0 + l16 < b, bj = j0 + l16 < b;
@@ -297,7 +325,7 @@ __global__ __launch_bounds__(256) void k_gather_Hp(int b, const double* __restri
   const double v = ((red[0][rr][ck] + red[1][rr][ck]) + red[2][rr][ck]) + red[3][rr][ck];
   const int i = i0 + r, j = j0 + cc;
   if (i < b && j < b) {
-    double* hp = Hp + (int64_t)blockIdx.z * b * b;
+    double* hp = Hp + (int64_t)z * b * b;
     hp[(int64_t)j * b + i] = v;
     hp[(int64_t)i * b + j] = v;
   }
@@ -305,10 +333,16 @@ __global__ __launch_bounds__(256) void k_gather_Hp(int b, const double* __restri
 
 // Second launch: H(i, j) = kappa(x_i, x_j) - sum over the partitions, in
 // partition order.
-__global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X, int d, KParams kp,
-                                                   const int64_t* __restrict__ props, int b, int parts,
-                                                   const double* __restrict__ Hp, double* __restrict__ H,
-                                                   const RoundState* st) {
+template <bool TAB>
+__global__ __launch_bounds__(256) void k_gather_Hs(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const double* __restrict__ X = RJ.X;
+  const int d = RJ.d, b = RJ.b, parts = RJ.parts;
+  const KParams kp = ldc(RJ.kp);
+  const int64_t* __restrict__ props = RJ.props;
+  const double* __restrict__ Hp = RJ.Hp;
+  double* __restrict__ H = RJ.H;
+  const RoundState* st = RJ.st;
   if (st->status != ST_RUNNING) return;
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= (int64_t)b * b) return;
@@ -325,14 +359,23 @@ __global__ __launch_bounds__(256) void k_gather_Hs(const double* __restrict__ X,
 // is read from L2 once per block instead of once per entry); every entry sums
 // its squared differences in the same order as sqdist.
 constexpr int HS_T = 16, HS_DC = 64;
-__global__ __launch_bounds__(256) void k_gather_Hs_tiled(const double* __restrict__ X, int d, KParams kp,
-                                                         const int64_t* __restrict__ props, int b, int parts,
-                                                         const double* __restrict__ Hp, double* __restrict__ H,
-                                                         const RoundState* st) {
+template <bool TAB>
+__global__ __launch_bounds__(256) void k_gather_Hs_tiled(RoundJob jb0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(jb0, tab);
+  const double* __restrict__ X = RJ.X;
+  const int d = RJ.d, b = RJ.b, parts = RJ.parts;
+  const KParams kp = ldc(RJ.kp);
+  const int64_t* __restrict__ props = RJ.props;
+  const double* __restrict__ Hp = RJ.Hp;
+  double* __restrict__ H = RJ.H;
+  const RoundState* st = RJ.st;
+  // block (bx, by) of the ceil(b / 16)^2 blocks, folded into blockIdx.x
+  const int nbt = (b + HS_T - 1) / HS_T;
+  if ((int)blockIdx.x >= nbt * nbt) return;
   if (st->status != ST_RUNNING) return;
   __shared__ double xs[2][HS_T][HS_DC + 1];   // [0]: rows i of the block, [1]: rows j
   const int tid = threadIdx.x, ti = tid % HS_T, tj = tid / HS_T;
-  const int i0 = blockIdx.x * HS_T, j0 = blockIdx.y * HS_T;
+  const int i0 = ((int)blockIdx.x % nbt) * HS_T, j0 = ((int)blockIdx.x / nbt) * HS_T;
   const int i = i0 + ti, j = j0 + tj;
   // staging: thread tid copies dims (tid % 64) of rows (tid / 64) + 4 m, m < 8, of the 32 rows
   const int sd = tid % HS_DC, sr = tid / HS_DC;
@@ -500,13 +543,19 @@ __device__ __forceinline__ void lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <bool GT>
-__global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __restrict__ H, int b,
-                                                                   const int64_t* __restrict__ props, Unif un,
-                                                                   RoundState* st, int32_t* __restrict__ acc_out,
-                                                                   int64_t* __restrict__ pivots,
-                                                                   double* __restrict__ u, int64_t kmax,
-                                                                   int keep_all) {
+template <bool GT, bool TAB>
+__global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  double* __restrict__ H = RJ.H;
+  const int b = RJ.b;
+  const int64_t* __restrict__ props = RJ.props;
+  const Unif un = ldc(RJ.un);
+  RoundState* st = RJ.st;
+  int32_t* __restrict__ acc_out = RJ.acc;
+  int64_t* __restrict__ pivots = RJ.pivots;
+  double* __restrict__ u = RJ.u;
+  const int64_t kmax = RJ.kmax;
+  const int keep_all = RJ.keep_all;
   if (st->status != ST_RUNNING) return;
   constexpr int BM = GT ? REJECT_G_BMAX : REJECT_T_BMAX;
   __shared__ __attribute__((aligned(16))) double Q[2][BM][QS];  // block columns
@@ -941,11 +990,19 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(double* __res
   if (tid == 0) st->s_r = nacc;
 }
 
-__global__ __launch_bounds__(1024) void k_reject_global(double* __restrict__ H, int b,
-                                                        const int64_t* __restrict__ props, Unif un,
-                                                        RoundState* st, int32_t* __restrict__ acc_out,
-                                                        int64_t* __restrict__ pivots,
-                                                        double* __restrict__ u, int64_t kmax, int keep_all) {
+template <bool TAB>
+__global__ __launch_bounds__(1024) void k_reject_global(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  double* __restrict__ H = RJ.H;
+  const int b = RJ.b;
+  const int64_t* __restrict__ props = RJ.props;
+  const Unif un = ldc(RJ.un);
+  RoundState* st = RJ.st;
+  int32_t* __restrict__ acc_out = RJ.acc;
+  int64_t* __restrict__ pivots = RJ.pivots;
+  double* __restrict__ u = RJ.u;
+  const int64_t kmax = RJ.kmax;
+  const int keep_all = RJ.keep_all;
   if (st->status != ST_RUNNING) return;
   __shared__ unsigned char tk[BMAX];
   __shared__ short accl[BMAX];
@@ -1011,9 +1068,16 @@ __global__ __launch_bounds__(64) void k_trinv(LFactor L, T* __restrict__ Bt2, co
 // u <- max(u - rowsqnorm(G), 0) (Alg. 2 step 3) from the per-column-block
 // partial row norms P (nparts x N, FP64, summed in a fixed order), and the
 // new chunk sums.
-__global__ __launch_bounds__(CHUNK) void k_diag(double* __restrict__ u, double* __restrict__ csum,
-                                                const double* __restrict__ P, int part_cols, int64_t N,
-                                                const RoundState* st) {
+template <bool TAB>
+__global__ __launch_bounds__(CHUNK) void k_diag(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  double* __restrict__ u = RJ.u;
+  double* __restrict__ csum = RJ.csum;
+  const double* __restrict__ P = RJ.P;
+  const int part_cols = RJ.part_cols;
+  const int64_t N = RJ.N;
+  const RoundState* st = RJ.st;
+  if ((int64_t)blockIdx.x >= RJ.nchunks) return;
   if (st->status != ST_RUNNING || st->s_r == 0) return;
   __shared__ double sh[CHUNK];
   const int s = st->s_r;
@@ -1032,8 +1096,13 @@ __global__ __launch_bounds__(CHUNK) void k_diag(double* __restrict__ u, double* 
 
 // End of round: k_r += s_r, round counters, stop conditions (k reached, an
 // empty round, the round limit).
-__global__ void k_finish(RoundState* st, int b, int64_t kmax, int64_t max_rounds,
-                         int32_t* __restrict__ hist) {
+template <bool TAB>
+__global__ void k_finish(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  RoundState* st = RJ.st;
+  const int b = RJ.b;
+  const int64_t kmax = RJ.kmax, max_rounds = RJ.max_rounds;
+  int32_t* __restrict__ hist = RJ.hist;
   if (threadIdx.x != 0 || st->status != ST_RUNNING) return;
   const int s = st->s_r;
   hist[st->round] = s;
@@ -1079,9 +1148,19 @@ void launch_init_from_diag(hipStream_t s, const double* u, int64_t N, double* cs
 
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
                     int64_t N, int b, Unif un, RoundState* st, int64_t* props) {
-  hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, csum, nchunks, cpre, b, un, st);
-  hipLaunchKernelGGL(k_propose, dim3((b + PROPOSE_WAVES - 1) / PROPOSE_WAVES), dim3(64 * PROPOSE_WAVES), 0,
-                     s, u, cpre, nchunks, N, b, un, st, props);
+  RoundJob j{};
+  j.u = const_cast<double*>(u);
+  j.csum = const_cast<double*>(csum);
+  j.cpre = cpre;
+  j.nchunks = nchunks;
+  j.N = N;
+  j.b = b;
+  j.un = un;
+  j.st = st;
+  j.props = props;
+  hipLaunchKernelGGL(k_scan_chunks<false>, dim3(1), dim3(1024), 0, s, j, nullptr);
+  hipLaunchKernelGGL(k_propose<false>, dim3((b + PROPOSE_WAVES - 1) / PROPOSE_WAVES), dim3(64 * PROPOSE_WAVES), 0,
+                     s, j, nullptr);
 }
 
 int gather_splits(int64_t kmax) {
@@ -1089,52 +1168,105 @@ int gather_splits(int64_t kmax) {
   return (int)(p < 1 ? 1 : (p > 8 ? 8 : p));
 }
 
-template <typename T>
-void launch_gather(hipStream_t s, const T* F, int64_t N, const double* X, int d, KParams kp,
-                   const int64_t* props, int b, double* Fs, int64_t ldf, int64_t kmax, double* Hp, double* H,
-                   const RoundState* st) {
-  if (kmax > 0)
-    hipLaunchKernelGGL(k_gather_rows<T>, dim3((unsigned)((kmax + 255) / 256), b), dim3(256), 0, s, F, N,
-                       props, Fs, ldf, st);
+int64_t gather_width(int64_t kmax) {
   const int parts = gather_splits(kmax);
-  const int64_t W = ((kmax + parts - 1) / parts + 63) / 64 * 64;   // columns per partition
-  const unsigned nb = (unsigned)((b + 15) / 16);
-  hipLaunchKernelGGL(k_gather_Hp, dim3(nb, nb, parts), dim3(256), 0, s, b, Fs, ldf, W, Hp, st);
-  if (d > 32)
-    hipLaunchKernelGGL(k_gather_Hs_tiled, dim3((unsigned)((b + HS_T - 1) / HS_T), (unsigned)((b + HS_T - 1) / HS_T)),
-                       dim3(256), 0, s, X, d, kp, props, b, parts, Hp, H, st);
-  else
-    hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp,
-                       props, b, parts, Hp, H, st);
-}
-void launch_kernel_block(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b, double* H,
-                         const RoundState* st) {
-  if (d > 32)
-    hipLaunchKernelGGL(k_gather_Hs_tiled, dim3((unsigned)((b + HS_T - 1) / HS_T), (unsigned)((b + HS_T - 1) / HS_T)),
-                       dim3(256), 0, s, X, d, kp, props, b, 0, nullptr, H, st);
-  else
-    hipLaunchKernelGGL(k_gather_Hs, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, X, d, kp,
-                       props, b, 0, nullptr, H, st);
+  return ((kmax + parts - 1) / parts + 63) / 64 * 64;
 }
 
-template void launch_gather<double>(hipStream_t, const double*, int64_t, const double*, int, KParams,
-                                    const int64_t*, int, double*, int64_t, int64_t, double*, double*,
-                                    const RoundState*);
-template void launch_gather<float>(hipStream_t, const float*, int64_t, const double*, int, KParams,
-                                   const int64_t*, int, double*, int64_t, int64_t, double*, double*,
-                                   const RoundState*);
+void launch_kernel_block(hipStream_t s, const double* X, int d, KParams kp, const int64_t* props, int b, double* H,
+                         const RoundState* st) {
+  RoundJob j{};
+  j.X = X;
+  j.d = d;
+  j.kp = kp;
+  j.props = const_cast<int64_t*>(props);
+  j.b = b;
+  j.parts = 0;
+  j.Hp = nullptr;
+  j.H = H;
+  j.st = const_cast<RoundState*>(st);
+  if (d > 32)
+    hipLaunchKernelGGL(k_gather_Hs_tiled<false>, dim3((unsigned)(((b + HS_T - 1) / HS_T) * ((b + HS_T - 1) / HS_T))),
+                       dim3(256), 0, s, j, nullptr);
+  else
+    hipLaunchKernelGGL(k_gather_Hs<false>, dim3((unsigned)(((int64_t)b * b + 255) / 256)), dim3(256), 0, s, j,
+                       nullptr);
+}
 
 void launch_reject(hipStream_t s, double* H, int b, const int64_t* props, Unif un, RoundState* st,
                    int32_t* acc, int64_t* pivots, double* u, int64_t kmax, bool keep_all) {
-  const int ka = keep_all ? 1 : 0;
+  RoundJob j{};
+  j.H = H;
+  j.b = b;
+  j.props = const_cast<int64_t*>(props);
+  j.un = un;
+  j.st = st;
+  j.acc = acc;
+  j.pivots = pivots;
+  j.u = u;
+  j.kmax = kmax;
+  j.keep_all = keep_all ? 1 : 0;
   if (b <= REJECT_T_BMAX)
-    hipLaunchKernelGGL(k_reject_tiled<false>, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc,
-                       pivots, u, kmax, ka);
+    hipLaunchKernelGGL((k_reject_tiled<false, false>), dim3(1), dim3(REJECT_T_THREADS), 0, s, j, nullptr);
   else if (b <= REJECT_G_BMAX)
-    hipLaunchKernelGGL(k_reject_tiled<true>, dim3(1), dim3(REJECT_T_THREADS), 0, s, H, b, props, un, st, acc,
-                       pivots, u, kmax, ka);
+    hipLaunchKernelGGL((k_reject_tiled<true, false>), dim3(1), dim3(REJECT_T_THREADS), 0, s, j, nullptr);
   else
-    hipLaunchKernelGGL(k_reject_global, dim3(1), dim3(1024), 0, s, H, b, props, un, st, acc, pivots, u, kmax, ka);
+    hipLaunchKernelGGL(k_reject_global<false>, dim3(1), dim3(1024), 0, s, j, nullptr);
+}
+
+// ---------------------------------------------- launchers over a table of jobs
+RoundGrid round_grid_of(const RoundJob& j) {
+  RoundGrid g{};
+  g.propose = (unsigned)((j.b + PROPOSE_WAVES - 1) / PROPOSE_WAVES);
+  g.gather_rows = (unsigned)(((j.kmax + 255) / 256) * j.b);
+  const int64_t nb = (j.b + 15) / 16;
+  g.gather_hp = (unsigned)(nb * nb * j.parts);
+  g.gather_hs = j.d > 32 ? (unsigned)(((j.b + HS_T - 1) / HS_T) * ((j.b + HS_T - 1) / HS_T))
+                         : (unsigned)(((int64_t)j.b * j.b + 255) / 256);
+  g.diag = (unsigned)j.nchunks;
+  return g;
+}
+
+void round_grid_max(RoundGrid& g, const RoundGrid& o) {
+  g.propose = g.propose > o.propose ? g.propose : o.propose;
+  g.gather_rows = g.gather_rows > o.gather_rows ? g.gather_rows : o.gather_rows;
+  g.gather_hp = g.gather_hp > o.gather_hp ? g.gather_hp : o.gather_hp;
+  g.gather_hs = g.gather_hs > o.gather_hs ? g.gather_hs : o.gather_hs;
+  g.diag = g.diag > o.diag ? g.diag : o.diag;
+}
+
+void launch_propose_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g) {
+  hipLaunchKernelGGL(k_scan_chunks<true>, dim3(1, n), dim3(1024), 0, s, RoundJob{}, tab);
+  hipLaunchKernelGGL(k_propose<true>, dim3(g.propose, n), dim3(64 * PROPOSE_WAVES), 0, s, RoundJob{}, tab);
+}
+
+void launch_gather_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g, bool fdouble, bool tiled) {
+  if (g.gather_rows > 0) {
+    if (fdouble)
+      hipLaunchKernelGGL((k_gather_rows<double, true>), dim3(g.gather_rows, n), dim3(256), 0, s, RoundJob{}, tab);
+    else
+      hipLaunchKernelGGL((k_gather_rows<float, true>), dim3(g.gather_rows, n), dim3(256), 0, s, RoundJob{}, tab);
+  }
+  hipLaunchKernelGGL(k_gather_Hp<true>, dim3(g.gather_hp, n), dim3(256), 0, s, RoundJob{}, tab);
+  if (tiled) hipLaunchKernelGGL(k_gather_Hs_tiled<true>, dim3(g.gather_hs, n), dim3(256), 0, s, RoundJob{}, tab);
+  else hipLaunchKernelGGL(k_gather_Hs<true>, dim3(g.gather_hs, n), dim3(256), 0, s, RoundJob{}, tab);
+}
+
+void launch_reject_tab(hipStream_t s, const RoundJob* tab, int n, int bmax) {
+  if (bmax <= REJECT_T_BMAX)
+    hipLaunchKernelGGL((k_reject_tiled<false, true>), dim3(1, n), dim3(REJECT_T_THREADS), 0, s, RoundJob{}, tab);
+  else if (bmax <= REJECT_G_BMAX)
+    hipLaunchKernelGGL((k_reject_tiled<true, true>), dim3(1, n), dim3(REJECT_T_THREADS), 0, s, RoundJob{}, tab);
+  else
+    hipLaunchKernelGGL(k_reject_global<true>, dim3(1, n), dim3(1024), 0, s, RoundJob{}, tab);
+}
+
+void launch_diag_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g) {
+  hipLaunchKernelGGL(k_diag<true>, dim3(g.diag, n), dim3(CHUNK), 0, s, RoundJob{}, tab);
+}
+
+void launch_finish_tab(hipStream_t s, const RoundJob* tab, int n) {
+  hipLaunchKernelGGL(k_finish<true>, dim3(1, n), dim3(64), 0, s, RoundJob{}, tab);
 }
 
 template <typename T>
@@ -1154,13 +1286,27 @@ template void launch_prep<float>(hipStream_t, const double*, int64_t, const int3
 
 void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int part_cols, int64_t N,
                  int64_t nchunks, const RoundState* st) {
-  hipLaunchKernelGGL(k_diag, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, u, csum, P, part_cols, N, st);
+  RoundJob j{};
+  j.u = u;
+  j.csum = csum;
+  j.P = P;
+  j.part_cols = part_cols;
+  j.N = N;
+  j.nchunks = nchunks;
+  j.st = const_cast<RoundState*>(st);
+  hipLaunchKernelGGL(k_diag<false>, dim3((unsigned)nchunks), dim3(CHUNK), 0, s, j, nullptr);
 }
 
 // Accepted points Xp(j, :) = X(S_r(j), :).
-__global__ __launch_bounds__(256) void k_prep_xp(const int32_t* __restrict__ acc, const int64_t* __restrict__ props,
-                                                 const double* __restrict__ X, int d, double* __restrict__ Xp,
-                                                 const RoundState* st) {
+template <bool TAB>
+__global__ __launch_bounds__(256) void k_prep_xp(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const int32_t* __restrict__ acc = RJ.acc;
+  const int64_t* __restrict__ props = RJ.props;
+  const double* __restrict__ X = RJ.X;
+  const int d = RJ.d;
+  double* __restrict__ Xp = RJ.Xp;
+  const RoundState* st = RJ.st;
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   for (int q = blockIdx.x * 256 + threadIdx.x; q < s * d; q += gridDim.x * 256) {
@@ -1171,11 +1317,39 @@ __global__ __launch_bounds__(256) void k_prep_xp(const int32_t* __restrict__ acc
 
 void launch_prep_xp(hipStream_t s, const int32_t* acc, const int64_t* props, const double* X, int d, double* Xp,
                     const RoundState* st) {
-  hipLaunchKernelGGL(k_prep_xp, dim3(8), dim3(256), 0, s, acc, props, X, d, Xp, st);
+  RoundJob j{};
+  j.acc = const_cast<int32_t*>(acc);
+  j.props = const_cast<int64_t*>(props);
+  j.X = X;
+  j.d = d;
+  j.Xp = Xp;
+  j.st = const_cast<RoundState*>(st);
+  hipLaunchKernelGGL(k_prep_xp<false>, dim3(8), dim3(256), 0, s, j, nullptr);
+}
+
+void launch_prep_xp_tab(hipStream_t s, const RoundJob* tab, int n) {
+  hipLaunchKernelGGL(k_prep_xp<true>, dim3(8, n), dim3(256), 0, s, RoundJob{}, tab);
+}
+
+// out[i] = the round state of table row i (out: host memory mapped for the
+// device, so the host reads the states of a whole table after one event).
+__global__ void k_collect_states(const RoundJob* __restrict__ tab, int n, RoundState* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = *tab[i].st;
+}
+
+void launch_collect_tab(hipStream_t s, const RoundJob* tab, int n, RoundState* out) {
+  hipLaunchKernelGGL(k_collect_states, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, tab, n, out);
 }
 
 void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, b, kmax, max_rounds, hist);
+  RoundJob j{};
+  j.st = st;
+  j.b = b;
+  j.kmax = kmax;
+  j.max_rounds = max_rounds;
+  j.hist = hist;
+  hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(64), 0, s, j, nullptr);
 }
 
 }  // namespace arpc

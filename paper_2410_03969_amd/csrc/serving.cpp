@@ -1,32 +1,45 @@
 // Serving: continuous batching of factorization jobs on one device.
 //
 // A context holds one device allocation (the HBM budget), a table of slots
-// (each with its own HIP stream at the default priority, a completion event
-// and a pinned host copy of its job's round state) and a scheduler thread.
-// The scheduler admits queued jobs in submission order whenever a slot is
-// free and the job's workspace fits the unallocated part of the budget, keeps
-// one batch of rounds in flight per active job (on the job's stream, so the
-// rounds of different jobs overlap on the device), and retires a job as soon
-// as its state says it is finished, which frees its slot and memory for the
-// next one.  Each job runs the same host driver as arpc_factor (make_job), so
-// its kernels, launch shapes and results are those of a factorization alone;
-// one round of a job is recorded once as a HIP graph and replayed.
+// and a scheduler thread.  The scheduler admits queued jobs in submission
+// order whenever a slot is free and the job's workspace fits the unallocated
+// part of the budget, and retires a job as soon as it is finished, which
+// frees its slot and memory for the next one.  Each job is driven by the same
+// host driver as arpc_factor (make_job), so its kernels and results are those
+// of a factorization alone.  Jobs advance in one of two ways:
+//  - Ticks (the BF16 modes with the one-kernel round product: d <= 16,
+//    b <= 256, the library's uniform stream).  Every such job's table row
+//    (RoundJob) goes into a device table, and one tick advances all of them
+//    by one round with one launch per round step (the round product once per
+//    group of jobs with the same compiled shape), on the context's tick
+//    stream.  A tick ends by copying every row's round state to pinned host
+//    memory; up to two ticks are in flight, so the device never waits for
+//    the host between rounds.  A finished job leaves the table; its final
+//    reductions are enqueued behind the ticks and it is retired when they
+//    complete.
+//  - Rounds on the job's own slot stream (every other job): batches of
+//    rounds, recorded once as a HIP graph and replayed, as in arpc_factor,
+//    overlapping with the ticks and with other slots.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/arpc.h"
 #include "arpc_common.h"
 #include "arpc_host.h"
+#include "arpc_launch.h"
+#include "arpc_mfma.h"
 
 using namespace arpc;
 using Clock = std::chrono::steady_clock;
@@ -92,14 +105,40 @@ struct ServedJob {
   Clock::time_point t_submit;
   std::unique_ptr<JobBase> run;
   std::unique_ptr<Profiler> prof;
+  bool ticked = false;     // advanced by ticks (else on its slot stream)
+  bool finishing = false;  // ticks: final reductions enqueued, waiting for the slot event
+  RoundState last{};       // ticks: round state after the latest completed tick
 };
 
 struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   RoundState* hstate = nullptr;  // pinned
+  double* htrace = nullptr;      // pinned: residual trace of a ticked job
   ServedJob* job = nullptr;
 };
+
+// Jobs that ticks can advance: the one-kernel round product of the BF16 modes
+// with the library's uniform stream.
+bool tickable(const arpc_problem& p, const Layout& l) {
+  return l.ncbt > 0 && (p.prec == ARPC_BF16 || p.prec == ARPC_BF16X3);
+}
+
+constexpr int kTicks = 2;   // ticks in flight
+
+struct Tick {
+  hipEvent_t ev = nullptr;
+  RoundJob* htab = nullptr;     // pinned copy of the table (read by the copy at run time)
+  RoundJob* dtab = nullptr;     // device table
+  RoundState* hst = nullptr;    // pinned: states after the tick
+  std::vector<ServedJob*> jobs;
+  bool inflight = false;
+};
+
+bool ticks_enabled() {
+  const char* e = getenv("ARPC_SERVE_TICKS");
+  return !(e && strcmp(e, "0") == 0);
+}
 
 bool graphs_enabled() {
   const char* e = getenv("ARPC_SERVE_GRAPHS");
@@ -123,10 +162,129 @@ struct arpc_ctx_s {
   arpc_job next_id = 1;
   arpc_serving_stats info{};
   bool graphs = true;
+  bool use_ticks = true;
+  hipStream_t ts = nullptr;     // tick stream
+  Tick ticks[kTicks];
+  int next_tick = 0;            // tick buffer of the next launch
+  int oldest = 0;               // oldest tick in flight
+  int grid2 = 0;                // two workgroups per compute unit
+  RoundJob* dtab_base = nullptr;
 
   void run();
   void retire(ServedJob* j, arpc_status st, bool have_stats);  // with mu held
+  bool launch_tick();                                          // without mu
+  void complete_tick(Tick& t);                                 // with mu held
+  void free_resources();                                       // after the scheduler has stopped
 };
+
+void arpc_ctx_s::free_resources() {
+  if (ts) (void)hipStreamSynchronize(ts);
+  for (auto& sl : slots) {
+    if (sl.s) {
+      (void)hipStreamSynchronize(sl.s);
+      (void)hipStreamDestroy(sl.s);
+    }
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.hstate) (void)hipHostFree(sl.hstate);
+    if (sl.htrace) (void)hipHostFree(sl.htrace);
+    sl = Slot{};
+  }
+  for (auto& tk : ticks) {
+    if (tk.ev) (void)hipEventDestroy(tk.ev);
+    if (tk.htab) (void)hipHostFree(tk.htab);
+    if (tk.hst) (void)hipHostFree(tk.hst);
+    tk = Tick{};
+  }
+  if (ts) (void)hipStreamDestroy(ts);
+  ts = nullptr;
+  if (dtab_base) (void)hipFree(dtab_base);
+  dtab_base = nullptr;
+  if (base) (void)hipFree(base);
+  base = nullptr;
+}
+
+// One round of every ticked job that is still running, as one launch per
+// round step over the device table (rows grouped by compiled shape for the
+// round product), then the rows' round states into pinned memory.
+bool arpc_ctx_s::launch_tick() {
+  Tick& t = ticks[next_tick];
+  const int n = (int)t.jobs.size();
+  if (n == 0) return false;
+  // group by (mode, column blocks, coordinate class, kernel form)
+  auto key = [](ServedJob* j) {
+    const RoundJob& r = j->run->row();
+    return std::make_tuple(j->p.prec, j->l.ncbt, r.d <= 8 ? 8 : 16, r.fa.kf.use_r);
+  };
+  std::stable_sort(t.jobs.begin(), t.jobs.end(), [&](ServedJob* a, ServedJob* b) { return key(a) < key(b); });
+  RoundGrid g{};
+  int bmax = 1;
+  for (int i = 0; i < n; ++i) {
+    t.htab[i] = t.jobs[i]->run->row();
+    round_grid_max(g, round_grid_of(t.htab[i]));
+    if (t.htab[i].b > bmax) bmax = t.htab[i].b;
+  }
+  hipStream_t s = ts;
+  if (hipMemcpyAsync(t.dtab, t.htab, sizeof(RoundJob) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
+    return false;
+  launch_propose_tab(s, t.dtab, n, g);
+  launch_gather_tab(s, t.dtab, n, g, false, false);
+  launch_reject_tab(s, t.dtab, n, bmax);
+  launch_prep_xp_tab(s, t.dtab, n);
+  for (int i0 = 0; i0 < n;) {   // per mode: the inverse factor and F(S_r,:)^T chunks
+    int i1 = i0, ncbt = 0;
+    while (i1 < n && t.jobs[i1]->p.prec == t.jobs[i0]->p.prec) {
+      ncbt = std::max(ncbt, t.jobs[i1]->l.ncbt);
+      ++i1;
+    }
+    launch_fused_prep_tab(s, gemm_prec(t.jobs[i0]->p.prec), t.dtab + i0, i1 - i0, ncbt);
+    i0 = i1;
+  }
+  for (int i0 = 0; i0 < n;) {   // per compiled shape: the round product
+    int i1 = i0, tiles = 1;
+    while (i1 < n && key(t.jobs[i1]) == key(t.jobs[i0])) {
+      tiles = std::max(tiles, t.htab[i1].fa.ntiles);
+      ++i1;
+    }
+    const int prec = gemm_prec(t.jobs[i0]->p.prec);
+    FusedArgs any = t.htab[i0].fa;
+    any.ntiles = 1 << 30;
+    const int budget = fused_grid_of(prec, any, grid2);   // persistent workgroups of a lone job
+    const int per = std::max(1, (budget + (i1 - i0) - 1) / (i1 - i0));
+    launch_fused_round_tab(s, prec, t.jobs[i0]->l.ncbt, t.htab[i0].d, t.htab[i0].fa, t.dtab + i0, i1 - i0,
+                           std::min(per, tiles));
+    i0 = i1;
+  }
+  launch_diag_tab(s, t.dtab, n, g);
+  launch_finish_tab(s, t.dtab, n);
+  launch_collect_tab(s, t.dtab, n, t.hst);
+  if (hipGetLastError() != hipSuccess || hipEventRecord(t.ev, s) != hipSuccess) return false;
+  t.inflight = true;
+  next_tick = (next_tick + 1) % kTicks;
+  return true;
+}
+
+// A tick has completed: the states of its rows are in t.hst.  A job that is
+// no longer running (or was cancelled) leaves the ticks: its final
+// reductions go on the tick stream, behind every tick already launched.
+void arpc_ctx_s::complete_tick(Tick& t) {
+  for (size_t i = 0; i < t.jobs.size(); ++i) {
+    ServedJob* j = t.jobs[i];
+    if (j->finishing || j->state != ACTIVE) continue;
+    j->last = t.hst[i];
+    if (j->last.status == ST_RUNNING && !j->cancel) continue;
+    Slot& sl = slots[j->slot];
+    j->finishing = true;
+    arpc_status e = ARPC_OK;
+    if (!j->cancel) e = j->run->finish_enqueue(j->last, sl.htrace);
+    if (e == ARPC_OK && hipEventRecord(sl.ev, ts) != hipSuccess) e = ARPC_EDEVICE;
+    if (e != ARPC_OK) {
+      (void)hipStreamSynchronize(ts);
+      retire(j, e, false);
+    }
+  }
+  t.jobs.clear();
+  t.inflight = false;
+}
 
 void arpc_ctx_s::retire(ServedJob* j, arpc_status st, bool have_stats) {
   j->result = st;
@@ -168,6 +326,8 @@ void arpc_ctx_s::run() {
       j->slot = free_slot;
       j->ws_off = off;
       j->state = ACTIVE;
+      j->ticked = use_ticks && tickable(j->p, j->l);
+      if (j->ticked) info.ticked_jobs += 1;
       sl.job = j;
       info.active += 1;
       info.bytes_in_use += (int64_t)((j->l.total + 255) / 256 * 256);
@@ -177,29 +337,39 @@ void arpc_ctx_s::run() {
       // start it (the lock is released around HIP calls that may take time)
       lk.unlock();
       Unif un{nullptr, 0, j->p.seed};
-      j->prof.reset(new Profiler(sl.s, false));
-      j->run = make_job(j->p, j->X, j->F, j->pivots, base + off, j->l, sl.s, un, sl.hstate, j->prof.get());
+      hipStream_t js = j->ticked ? ts : sl.s;
+      j->prof.reset(new Profiler(js, false));
+      j->run = make_job(j->p, j->X, j->F, j->pivots, base + off, j->l, js, un, sl.hstate, j->prof.get());
       std::memset(sl.hstate, 0, sizeof(RoundState));
       arpc_status e = j->run->begin();
-      if (e == ARPC_OK && graphs) e = j->run->capture_round();
-      if (e == ARPC_OK) e = j->run->enqueue_batch();
-      if (e == ARPC_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) e = ARPC_EDEVICE;
+      if (!j->ticked) {
+        if (e == ARPC_OK && graphs) e = j->run->capture_round();
+        if (e == ARPC_OK) e = j->run->enqueue_batch();
+        if (e == ARPC_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) e = ARPC_EDEVICE;
+      }
       lk.lock();
       if (e != ARPC_OK) {
-        (void)hipStreamSynchronize(sl.s);
+        (void)hipStreamSynchronize(js);
         retire(j, e, false);
       }
     }
-    // progress of the active jobs
+    // jobs on their own slot streams, and ticked jobs whose final reductions were enqueued
     for (size_t i = 0; i < slots.size(); ++i) {
       Slot& sl = slots[i];
       ServedJob* j = sl.job;
-      if (!j) continue;
+      if (!j || (j->ticked && !j->finishing)) continue;
       const hipError_t q = hipEventQuery(sl.ev);
       if (q == hipErrorNotReady) continue;
       progress = true;
       if (q != hipSuccess) {
         retire(j, ARPC_EDEVICE, false);
+        continue;
+      }
+      if (j->ticked) {
+        arpc_stats st{};
+        const arpc_status e = j->cancel ? ARPC_ECANCELED : j->run->finish_stats(j->last, *sl.htrace, &st);
+        j->stats = st;
+        retire(j, e, !j->cancel);
         continue;
       }
       if (j->cancel) {
@@ -226,8 +396,57 @@ void arpc_ctx_s::run() {
         retire(j, e, false);
       }
     }
+    // ticks: completions in launch order, then a new tick while fewer than
+    // kTicks are in flight and some ticked job is still running
+    while (ticks[oldest].inflight) {
+      const hipError_t q = hipEventQuery(ticks[oldest].ev);
+      if (q == hipErrorNotReady) break;
+      progress = true;
+      if (q != hipSuccess) {
+        for (ServedJob* j : ticks[oldest].jobs)
+          if (j->state == ACTIVE) retire(j, ARPC_EDEVICE, false);
+        ticks[oldest].jobs.clear();
+        ticks[oldest].inflight = false;
+      } else {
+        complete_tick(ticks[oldest]);
+      }
+      oldest = (oldest + 1) % kTicks;
+    }
+    if (!ticks[next_tick].inflight) {
+      Tick& t = ticks[next_tick];
+      t.jobs.clear();
+      for (auto& sl : slots)
+        if (sl.job && sl.job->ticked && !sl.job->finishing && (sl.job->last.status == ST_RUNNING) && !sl.job->cancel)
+          t.jobs.push_back(sl.job);
+      // a cancelled ticked job that is not in flight leaves now
+      for (auto& sl : slots) {
+        ServedJob* j = sl.job;
+        if (!j || !j->ticked || j->finishing || !j->cancel) continue;
+        bool inflight = false;
+        for (auto& tk : ticks)
+          if (tk.inflight && std::find(tk.jobs.begin(), tk.jobs.end(), j) != tk.jobs.end()) inflight = true;
+        if (inflight) continue;
+        j->finishing = true;
+        if (hipEventRecord(sl.ev, ts) != hipSuccess) retire(j, ARPC_EDEVICE, false);
+        progress = true;
+      }
+      if (!t.jobs.empty()) {
+        lk.unlock();
+        const bool ok = launch_tick();
+        lk.lock();
+        progress = true;
+        if (ok) info.ticks += 1;
+        if (!ok) {
+          (void)hipStreamSynchronize(ts);
+          for (ServedJob* j : t.jobs)
+            if (j->state == ACTIVE) retire(j, ARPC_EDEVICE, false);
+          t.jobs.clear();
+          t.inflight = false;
+        }
+      }
+    }
     if (stop && info.active == 0) break;
-    if (!progress) cv_work.wait_for(lk, std::chrono::microseconds(50));
+    if (!progress) cv_work.wait_for(lk, std::chrono::microseconds(20));
   }
 }
 
@@ -243,26 +462,36 @@ arpc_status arpc_create(int device, size_t hbm_budget_bytes, int max_slots, arpc
   c->device = device;
   c->budget = hbm_budget_bytes / 256 * 256;
   c->graphs = graphs_enabled();
+  c->use_ticks = ticks_enabled();
+  c->grid2 = fused_grid();
   arpc_status ret = ARPC_OK;
   if (hipMalloc((void**)&c->base, c->budget) != hipSuccess) {
     c->base = nullptr;
     ret = ARPC_EDEVICE;
+  }
+  if (ret == ARPC_OK &&
+      (hipMalloc((void**)&c->dtab_base, sizeof(RoundJob) * (size_t)max_slots * kTicks) != hipSuccess ||
+       hipStreamCreateWithFlags(&c->ts, hipStreamNonBlocking) != hipSuccess))
+    ret = ARPC_EDEVICE;
+  for (int t = 0; t < kTicks && ret == ARPC_OK; ++t) {
+    Tick& tk = c->ticks[t];
+    tk.dtab = c->dtab_base + (size_t)t * max_slots;
+    if (hipEventCreateWithFlags(&tk.ev, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&tk.htab, sizeof(RoundJob) * (size_t)max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&tk.hst, sizeof(RoundState) * (size_t)max_slots, hipHostMallocDefault) != hipSuccess)
+      ret = ARPC_EDEVICE;
   }
   c->slots.resize((size_t)max_slots);
   for (auto& sl : c->slots) {
     if (ret != ARPC_OK) break;
     if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&sl.hstate, sizeof(RoundState), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&sl.hstate, sizeof(RoundState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sl.htrace, sizeof(double), hipHostMallocDefault) != hipSuccess)
       ret = ARPC_EDEVICE;
   }
   if (ret != ARPC_OK) {
-    for (auto& sl : c->slots) {
-      if (sl.s) (void)hipStreamDestroy(sl.s);
-      if (sl.ev) (void)hipEventDestroy(sl.ev);
-      if (sl.hstate) (void)hipHostFree(sl.hstate);
-    }
-    if (c->base) (void)hipFree(c->base);
+    c->free_resources();
     (void)hipSetDevice(prev);
     return ret;
   }
@@ -295,13 +524,7 @@ arpc_status arpc_destroy(arpc_ctx ctx) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
-  for (auto& sl : ctx->slots) {
-    (void)hipStreamSynchronize(sl.s);
-    (void)hipStreamDestroy(sl.s);
-    (void)hipEventDestroy(sl.ev);
-    (void)hipHostFree(sl.hstate);
-  }
-  (void)hipFree(ctx->base);
+  ctx->free_resources();
   (void)hipSetDevice(prev);
   delete ctx;
   return ARPC_OK;

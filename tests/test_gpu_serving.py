@@ -48,9 +48,17 @@ def _log(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("graphs", ["1", "0"])
-def test_results_same_alone_and_in_the_mix(monkeypatch, graphs):
+MODES = {"ticks": ("1", "1"), "graphs": ("0", "1"), "plain": ("0", "0")}   # (ARPC_SERVE_TICKS, ARPC_SERVE_GRAPHS)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_results_same_alone_and_in_the_mix(monkeypatch, mode):
+    """Ticks: the BF16-mode jobs with d <= 16 advance together (one launch per
+    round step over a table of jobs); graphs / plain: every job on its own
+    slot stream, with or without graph replay."""
     from paper_2410_03969_amd import binding
+    ticks, graphs = MODES[mode]
+    monkeypatch.setenv("ARPC_SERVE_TICKS", ticks)
     monkeypatch.setenv("ARPC_SERVE_GRAPHS", graphs)
     jobs = _jobs()
     alone = []
@@ -59,7 +67,7 @@ def test_results_same_alone_and_in_the_mix(monkeypatch, graphs):
         alone.append(_alone(X, prob))
     ws = [binding.arpc_workspace_size(binding.make_problem(p)) for _, p in jobs]
     budget = int(2.5 * max(ws))   # a few jobs at a time: the rest wait for memory
-    _log(f"[serving mix] budget={budget} slots=4 graphs={graphs}")
+    _log(f"[serving mix] budget={budget} slots=4 mode={mode}")
     srv = binding.Server(budget, max_slots=4)
     try:
         handles = [srv.submit(X, prob) for X, prob in jobs]
@@ -75,6 +83,107 @@ def test_results_same_alone_and_in_the_mix(monkeypatch, graphs):
     assert info["completed"] == len(jobs) and info["active"] == 0 and info["queued"] == 0
     assert info["peak_bytes"] <= budget
     assert info["peak_active"] >= 2, info     # jobs did overlap
+    n_tickable = sum(1 for _, p in jobs if p.prec in (W.BF16, W.BF16X3) and p.d <= 16)
+    if mode == "ticks":
+        assert info["ticked_jobs"] == n_tickable and info["ticks"] > 0, info
+    else:
+        assert info["ticked_jobs"] == 0 and info["ticks"] == 0, info
+
+
+def test_ticked_jobs_share_launches():
+    """Sixteen small BF16-mode jobs of three column-block shapes, all
+    submitted at once with room for all of them: fewer ticks than the jobs'
+    rounds added up (each tick ran a round of several jobs), and every result
+    equals the job's result alone."""
+    from paper_2410_03969_amd import binding
+    rng = np.random.default_rng(11)
+    jobs = []
+    for j in range(16):
+        N = int(rng.integers(3000, 9000))
+        d = int(rng.choice([3, 8, 16]))
+        k = int(rng.choice([60, 300, 1000]))
+        X = np.random.default_rng(2000 + j).random((N, d))
+        jobs.append((X, W.Problem(N=N, d=d, k=k, b=k // 10, kernel=W.GAUSSIAN, sigma=0.3, seed=j,
+                                  prec=W.BF16 if j % 3 else W.BF16X3)))
+    alone = [_alone(X, p) for X, p in jobs]
+    budget = sum(binding.arpc_workspace_size(binding.make_problem(p)) for _, p in jobs) + (1 << 24)
+    _log(f"[serving ticks] 16 jobs budget={budget}")
+    srv = binding.Server(budget, max_slots=16)
+    try:
+        hs = [srv.submit(X, p) for X, p in jobs]
+        res = [srv.wait(h) for h in hs]
+        info = srv.info()
+    finally:
+        srv.close()
+    rounds = 0
+    for (F0, p0, s0), r in zip(alone, res):
+        assert r["status"] == s0
+        assert np.array_equal(r["pivots"].cpu().numpy(), p0)
+        assert np.array_equal(r["F"].cpu().numpy(), F0)
+        rounds += r["stats"]["rounds"]
+    print(f"ticks {info['ticks']} for {rounds} job rounds, peak active {info['peak_active']}")
+    assert info["ticked_jobs"] == 16
+    assert info["ticks"] < rounds
+
+
+def test_served_fp64_jobs_match_the_oracle():
+    """Eight jobs of the serving stream's shape (the first eight with
+    N <= 20000: points uniform on [0,1]^d, Gaussian sigma = sqrt(d),
+    b = k / 10), served together in FP64, against the FP64 oracle on the same
+    uniform stream.  Pivots are compared over the rounds that start with a
+    residual trace above 1e-8 tr A; F over the same columns within 1e-10.
+    Jobs with d = 3 or 8 reach numerical rank before k: past that point the
+    residual diagonal is rounding noise on both sides, and their decisions
+    differ as ties do; there both runs must end with a residual trace at
+    that level."""
+    from oracle import PointsAccess, philox_stream, rpc_accel
+    from paper_2410_03969_amd import binding
+    stream = W.serving_stream(n_jobs=512, rate=1.0, prec=W.FP64, materialize=False)
+    picked = [j for j in stream if j.problem.N <= 20000][:8]
+    jobs = [(np.random.default_rng(1000 + j.job_id).random((j.problem.N, j.problem.d)), j.problem) for j in picked]
+    budget = sum(binding.arpc_workspace_size(binding.make_problem(p)) for _, p in jobs) + (1 << 24)
+    _log(f"[serving fp64] jobs {[j.job_id for j in picked]}")
+    srv = binding.Server(budget, max_slots=8)
+    try:
+        hs = [srv.submit(X, p) for X, p in jobs]
+        res = [srv.wait(h) for h in hs]
+    finally:
+        srv.close()
+    for (X, p), r in zip(jobs, res):
+        ref = rpc_accel(PointsAccess(X, p.kernel, p.sigma), p.k, p.b, philox_stream(p.seed), record=True)
+        starts = [ref.trace_A] + [float(h.sum()) for h in ref.u_history]
+        r_ok = next((i for i, t in enumerate(starts) if t <= 1e-8 * ref.trace_A), len(ref.round_sizes))
+        r_ok = min(r_ok, len(ref.round_sizes))
+        m = int(sum(ref.round_sizes[:r_ok]))
+        st = r["stats"]
+        k_out = st["k_out"]
+        piv = r["pivots"].cpu().numpy()
+        assert k_out >= m, (p, k_out, m)
+        assert np.array_equal(piv[:m], ref.pivots[:m]), p
+        # F: the columns of rounds that start above 1e-6 tr A within 1e-10
+        # (Frobenius).  The later compared columns belong to pivots whose
+        # residuals h went down to 1e-8 of the diagonal (kappa(0) = 1): a
+        # column of the factor is as accurate as the condition of A(S,S) so
+        # far allows, about 1 / min h, so column c is held to 1e-13 / min h
+        # over the columns up to c (h of column c = F(s_c, c)^2).
+        r_f = next((i for i, t in enumerate(starts) if t <= 1e-6 * ref.trace_A), len(ref.round_sizes))
+        mf = int(sum(ref.round_sizes[:min(r_f, r_ok)]))
+        F = r["F"].cpu().numpy()[:, :m]
+        err = np.linalg.norm(F[:, :mf] - ref.F[:, :mf]) / np.linalg.norm(ref.F[:, :mf])
+        hmin = np.minimum.accumulate(ref.F[ref.pivots[:m], np.arange(m)] ** 2)
+        col = np.linalg.norm(F - ref.F[:, :m], axis=0) / np.linalg.norm(ref.F[:, :m], axis=0)
+        ratio = (col * hmin / 1e-13)[mf:]
+        print(f"N={p.N} d={p.d} k={p.k}: k_out={k_out} (oracle {ref.k_out}), compared {m} pivots "
+              f"over {r_ok} rounds, relF={err:.2e} over {mf} columns; later columns: worst error "
+              f"{col[mf:].max() if m > mf else 0:.2e}, worst error / (1e-13 / min h) "
+              f"{ratio.max() if m > mf else 0:.2e}")
+        assert err <= 1e-10
+        assert m == mf or ratio.max() <= 1.0
+        if ref.k_out == p.k and r_ok == len(ref.round_sizes):
+            assert k_out == p.k and np.array_equal(piv, ref.pivots)
+        else:
+            assert st["trace_resid"] <= 1e-8 * st["trace_A"], st
+            assert float(np.sum(ref.u)) <= 1e-8 * ref.trace_A
 
 
 def test_admission_respects_budget():
