@@ -98,7 +98,8 @@ typedef struct arpc_stats {
   int64_t proposals;    /* b * rounds */
   int32_t status;       /* ARPC_OK or ARPC_EARLY_STOP */
   int32_t fused;        /* 1: each round's update GEMM, solve and stores ran as one
-                           kernel (ARPC_BF16X3 / ARPC_BF16 with b <= 256, d <= 16),
+                           kernel (ARPC_BF16X3 / ARPC_BF16 with b <= 256, d <= 16;
+                           ARPC_BF16 with b <= 208, d <= 32),
                            timed under the colgemm class; 0: two kernels */
   double trace_A;       /* sum of diag A */
   double trace_resid;   /* sum of the final residual diagonal */
@@ -283,7 +284,8 @@ void arpc_set_profiling_classes(unsigned mask);
  *    its workspace (arpc_workspace_size of its problem, about N*k elements of
  *    the blocked factor copy plus O(N + b*k) more) fits in what is left of the
  *    context's HBM budget;
- *  - jobs in the BF16 modes whose rounds run as one kernel (d <= 16, b <= 256)
+ *  - jobs in the BF16 modes whose rounds run as one kernel (d <= 16 and
+ *    b <= 256; in ARPC_BF16 also d <= 32 and b <= 208)
  *    advance together in ticks: one tick runs one round of every such job,
  *    with one kernel launch per round step serving all of them (the round
  *    product once per group of jobs of the same compiled shape), from a

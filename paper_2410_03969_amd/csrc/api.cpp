@@ -71,7 +71,13 @@ Layout layout_of(const arpc_problem& p) {
   const int gp = gemm_prec(p.prec);
   const bool valu = use_valu_gemm() && p.prec <= ARPC_FP32;
   l.valu = valu;
-  l.ncbt = (!valu && !fused_disabled() && p.d <= 16 && p.prec != ARPC_FP8) ? fused_ncbt(gp, (int)p.b) : -1;
+  // one kernel per round: the BF16 modes with d <= 16, and the one-product
+  // BF16 mode with d <= 32 and b <= 208 (its LDS then holds the accepted
+  // points' coordinates beside the resident inverse factor)
+  const int fn = fused_ncbt(gp, (int)p.b);
+  const bool fuse = !valu && !fused_disabled() && p.prec != ARPC_FP8 && fn > 0 &&
+                    (p.d <= 16 || (gp == ARPC_BF16 && p.d <= 32 && fn <= 13));
+  l.ncbt = fuse ? fn : -1;
   const bool fused = l.ncbt > 0;
   l.part_cols = valu ? 64 : (fused ? BMAX : mfma_part_cols(gp, (int)p.b));
   const int64_t nparts = (p.b + l.part_cols - 1) / l.part_cols;

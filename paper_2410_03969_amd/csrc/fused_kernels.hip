@@ -698,8 +698,15 @@ void launch_fused_t(hipStream_t s, const FusedArgs& a, const RoundJob* tab, int 
 
 template <int PASSES, int NCBT, bool TAB>
 void launch_fused_d(hipStream_t s, int dx, const FusedArgs& a, const RoundJob* tab, int n, int grid) {
-  if (dx <= 8) launch_fused_t<PASSES, NCBT, 8, TAB>(s, a, tab, n, grid);
-  else launch_fused_t<PASSES, NCBT, 16, TAB>(s, a, tab, n, grid);
+  if (dx <= 8) {
+    launch_fused_t<PASSES, NCBT, 8, TAB>(s, a, tab, n, grid);
+  } else if (dx <= 16) {
+    launch_fused_t<PASSES, NCBT, 16, TAB>(s, a, tab, n, grid);
+  } else {
+    // d <= 32: one-product mode with at most 13 column blocks (the LDS holds
+    // the accepted points' 32 coordinates beside the resident inverse factor)
+    if constexpr (PASSES == 1 && NCBT <= 13) launch_fused_t<PASSES, NCBT, 32, TAB>(s, a, tab, n, grid);
+  }
 }
 
 template <int PASSES, bool TAB>

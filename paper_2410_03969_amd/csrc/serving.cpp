@@ -7,8 +7,8 @@
 // frees its slot and memory for the next one.  Each job is driven by the same
 // host driver as arpc_factor (make_job), so its kernels and results are those
 // of a factorization alone.  Jobs advance in one of two ways:
-//  - Ticks (the BF16 modes with the one-kernel round product: d <= 16,
-//    b <= 256, the library's uniform stream).  Every such job's table row
+//  - Ticks (the BF16 modes with the one-kernel round product: d <= 16 and
+//    b <= 256, or one product with d <= 32 and b <= 208).  Every such job's table row
 //    (RoundJob) goes into a device table, and one tick advances all of them
 //    by one round with one launch per round step (the round product once per
 //    group of jobs with the same compiled shape), on the context's tick
@@ -213,7 +213,7 @@ bool arpc_ctx_s::launch_tick() {
   // group by (mode, column blocks, coordinate class, kernel form)
   auto key = [](ServedJob* j) {
     const RoundJob& r = j->run->row();
-    return std::make_tuple(j->p.prec, j->l.ncbt, r.d <= 8 ? 8 : 16, r.fa.kf.use_r);
+    return std::make_tuple(j->p.prec, j->l.ncbt, r.d <= 8 ? 8 : (r.d <= 16 ? 16 : 32), r.fa.kf.use_r);
   };
   std::stable_sort(t.jobs.begin(), t.jobs.end(), [&](ServedJob* a, ServedJob* b) { return key(a) < key(b); });
   RoundGrid g{};

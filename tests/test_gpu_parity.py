@@ -343,6 +343,41 @@ def test_fused_round_factor_consistent_with_its_pivots(prec, b, d):
     assert np.sum(F ** 2) <= trA * (1 + 1e-3)
 
 
+@pytest.mark.parametrize("b,d", [(20, 17), (60, 24), (120, 32), (200, 32)])
+def test_fused_round_wide_points_one_product(b, d):
+    """The one-product BF16 mode also runs one kernel per round for
+    16 < d <= 32 when b <= 208 (13 column blocks): its factor equals the FP64
+    factor of its pivots on sampled rows, as for d <= 16."""
+    rng = np.random.default_rng(2000 + b + d)
+    N = 5003
+    X = rng.uniform(0.0, 1.0, size=(N, d))
+    prob = W.Problem(N=N, d=d, k=min(3 * b, 600), b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=12, prec=W.BF16)
+    F, piv, out = gpu_factor(X, prob)
+    assert out["stats"]["fused"] == 1
+    k_out = out["stats"]["k_out"]
+    assert k_out == prob.k and len(set(piv[:k_out].tolist())) == k_out
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
+    rows = np.concatenate([np.random.default_rng(1).choice(N, 150, replace=False), np.arange(N - 40, N)])
+    ncols = min(k_out, 2 * b)
+    ref = factor_from_pivots(acc, piv[:ncols], rows=rows)
+    err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
+    print(f"fused wide b={b} d={d} cols={ncols} relF={err:.3e}")
+    assert err < FUSED_TOL[W.BF16], err
+    assert np.sum(F ** 2) <= out["stats"]["trace_A"] * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("prec,b,d", [(W.BF16X3, 60, 24), (W.BF16, 240, 32), (W.BF16, 60, 33)])
+def test_wide_points_outside_the_one_kernel_form(prec, b, d):
+    """Three products at d > 16, 14 or more column blocks at d > 16, or
+    d > 32 keep the two-kernel round product (and the same pivots rule)."""
+    rng = np.random.default_rng(3000 + b + d)
+    X = rng.uniform(0.0, 1.0, size=(3001, d))
+    prob = W.Problem(N=3001, d=d, k=2 * b, b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=13, prec=prec)
+    F, piv, out = gpu_factor(X, prob)
+    assert out["stats"]["fused"] == 0
+    assert out["stats"]["k_out"] == prob.k
+
+
 def test_fused_and_two_kernel_paths_agree_on_exact_matrix(monkeypatch):
     """On the exact cluster matrix both BF16 round products recover the same
     rank and pivots (a round-off independent answer)."""

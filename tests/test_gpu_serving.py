@@ -83,7 +83,8 @@ def test_results_same_alone_and_in_the_mix(monkeypatch, mode):
     assert info["completed"] == len(jobs) and info["active"] == 0 and info["queued"] == 0
     assert info["peak_bytes"] <= budget
     assert info["peak_active"] >= 2, info     # jobs did overlap
-    n_tickable = sum(1 for _, p in jobs if p.prec in (W.BF16, W.BF16X3) and p.d <= 16)
+    n_tickable = sum(1 for _, p in jobs if (p.prec in (W.BF16, W.BF16X3) and p.d <= 16)
+                     or (p.prec == W.BF16 and p.d <= 32 and p.b <= 208))
     if mode == "ticks":
         assert info["ticked_jobs"] == n_tickable and info["ticks"] > 0, info
     else:
