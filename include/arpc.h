@@ -28,6 +28,8 @@ typedef enum arpc_status {
   ARPC_OK = 0,           /* k pivots produced */
   ARPC_EARLY_STOP = 1,   /* informational: the residual became (numerically) zero
                             before k pivots; k_out < k, see arpc_factor */
+  ARPC_INCOMPLETE = 2,   /* informational (arpc_factor_query): the rounds enqueued so far
+                            ended before k pivots; arpc_factor_continue adds more */
   ARPC_EINVAL = -1,      /* invalid argument (sizes, pointers, alignment, workspace) */
   ARPC_ENOMEM = -2,      /* an allocation or admission could not be satisfied */
   ARPC_EBUSY = -3,       /* a queue or slot table is full */
@@ -159,6 +161,42 @@ arpc_status arpc_factor(const arpc_problem* problem, const double* X, void* F,
 arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, void* F,
                                  int64_t* pivots, void* ws, size_t ws_bytes, void* stream,
                                  const double* U, int64_t nU, arpc_stats* stats);
+
+/* Asynchronous form of arpc_factor (the same factorization, kernels and
+ * results): enqueues on `stream` the initialisation, `rounds` rounds of Alg. 2
+ * and the end of the run, and returns without waiting for the device.
+ * Every round reads the round state kept in ws, so rounds past the end of the
+ * run (k pivots held, or the residual exhausted) exit on the device at once;
+ * the end of the run writes the residual trace into ws and, after an early
+ * stop, zero columns k_out..k-1 of F and pivots[k_out..k-1] = -1.
+ *
+ *  problem, X, F, pivots, ws, ws_bytes, stream   as for arpc_factor.
+ *  rounds  rounds to enqueue; 0: problem->max_rounds if set, else
+ *          ceil(k/b) + ceil(k/b)/2 + 4 (at most k).  Every round that runs
+ *          accepts at least one pivot, so k rounds always suffice.
+ *
+ * F, pivots and the statistics (arpc_factor_query) are valid once the stream
+ * has passed the enqueued work; the caller must keep X, F, pivots and ws
+ * untouched until then.  Returns ARPC_OK when the work was enqueued,
+ * ARPC_EINVAL / ARPC_EDEVICE otherwise. */
+arpc_status arpc_factor_async(const arpc_problem* problem, const double* X, void* F, int64_t* pivots,
+                              void* ws, size_t ws_bytes, void* stream, int64_t rounds);
+
+/* Enqueue `rounds` (>= 1) more rounds and the end of the run for a
+ * factorization started by arpc_factor_async on the same problem, X, F,
+ * pivots and ws (after arpc_factor_query returned ARPC_INCOMPLETE, or without
+ * asking: rounds past the end exit at once).  Asynchronous like
+ * arpc_factor_async. */
+arpc_status arpc_factor_continue(const arpc_problem* problem, const double* X, void* F, int64_t* pivots,
+                                 void* ws, size_t ws_bytes, void* stream, int64_t rounds);
+
+/* Outcome of the work enqueued by arpc_factor_async / arpc_factor_continue,
+ * read from ws (host memory copies; call after the stream has passed that
+ * work).  Returns what arpc_factor would have returned (ARPC_OK,
+ * ARPC_EARLY_STOP, ARPC_ENUMERIC, ARPC_EINVAL for an exhausted uniform array),
+ * or ARPC_INCOMPLETE when the run needs more rounds; stats (may be NULL) as
+ * for arpc_factor, without kernel times and with ms_total = 0. */
+arpc_status arpc_factor_query(const arpc_problem* problem, const void* ws, size_t ws_bytes, arpc_stats* stats);
 
 /* Bytes of device workspace that arpc_factor_lowmem needs for *problem:
  * O(N ceil(b/64) + k (2d + 3b) + b^2) doubles, against the N k of arpc_factor's F.
@@ -336,8 +374,11 @@ arpc_status arpc_create(int device, size_t hbm_budget_bytes, int max_slots, arpc
 arpc_status arpc_destroy(arpc_ctx ctx);
 
 /* Queue a job.  Arguments as for arpc_factor (the workspace comes from the
- * context).  Returns ARPC_EINVAL for an invalid problem or pointers and
- * ARPC_ENOMEM when the job's workspace exceeds the whole budget. */
+ * context).  Returns ARPC_EINVAL for an invalid problem or pointers,
+ * ARPC_ENOMEM when the job's workspace exceeds the whole budget, and
+ * ARPC_EBUSY when the context already holds its limit of jobs submitted and
+ * not yet finished (arpc_serving_set_limit; 65536 by default): the job is not
+ * queued and may be submitted again later. */
 arpc_status arpc_submit(arpc_ctx ctx, const arpc_problem* problem, const double* X, void* F, int64_t* pivots,
                         arpc_job* job);
 
@@ -356,6 +397,11 @@ arpc_status arpc_wait(arpc_ctx ctx, arpc_job job, arpc_stats* stats);
  * batch of rounds (its F and pivots are then incomplete).  Its status becomes
  * ARPC_ECANCELED unless it had already finished. */
 arpc_status arpc_cancel(arpc_ctx ctx, arpc_job job);
+
+/* Largest number of jobs submitted to ctx and not yet finished (queued or
+ * active), 1 <= max_outstanding <= 2^31 - 1; a submission beyond it returns
+ * ARPC_EBUSY. */
+arpc_status arpc_serving_set_limit(arpc_ctx ctx, int64_t max_outstanding);
 
 /* Snapshot of the context's counters. */
 arpc_status arpc_serving_info(arpc_ctx ctx, arpc_serving_stats* out);

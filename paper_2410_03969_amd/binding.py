@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libarpc.so")
 
-ARPC_OK, ARPC_EARLY_STOP = 0, 1
+ARPC_OK, ARPC_EARLY_STOP, ARPC_INCOMPLETE = 0, 1, 2
 ARPC_EINVAL, ARPC_ENOMEM, ARPC_EBUSY, ARPC_EDEVICE, ARPC_ENUMERIC, ARPC_ECANCELED = -1, -2, -3, -4, -5, -6
 KERNEL_CLASSES = ["init", "propose", "gather", "reject", "prep", "colgemm", "trsm", "diag", "finish"]
 NUM_KC = len(KERNEL_CLASSES)
@@ -24,7 +24,8 @@ EXPORTS = ["arpc_status_str", "arpc_version", "arpc_workspace_size", "arpc_facto
            "arpc_set_profiling_classes", "arpc_lowmem_workspace_size", "arpc_factor_lowmem",
            "arpc_qr_workspace_size", "arpc_qr_factor", "arpc_krr_workspace_size", "arpc_krr_pcg",
            "arpc_create", "arpc_destroy", "arpc_submit", "arpc_poll", "arpc_wait", "arpc_cancel",
-           "arpc_serving_info"]
+           "arpc_serving_info", "arpc_factor_async", "arpc_factor_continue", "arpc_factor_query",
+           "arpc_serving_set_limit"]
 
 
 class ArpcProblem(C.Structure):
@@ -91,6 +92,15 @@ def lib():
         L.arpc_factor_uniforms.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_int64,
                                            C.POINTER(ArpcStats)]
+        for name in ("arpc_factor_async", "arpc_factor_continue"):
+            fn = getattr(L, name)
+            fn.restype = C.c_int
+            fn.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                           C.c_void_p, C.c_int64]
+        L.arpc_factor_query.restype = C.c_int
+        L.arpc_factor_query.argtypes = [C.POINTER(ArpcProblem), C.c_void_p, C.c_size_t, C.POINTER(ArpcStats)]
+        L.arpc_serving_set_limit.restype = C.c_int
+        L.arpc_serving_set_limit.argtypes = [C.c_void_p, C.c_int64]
         L.arpc_stream_uniforms_host.restype = C.c_int
         L.arpc_lowmem_workspace_size.restype = C.c_int
         L.arpc_lowmem_workspace_size.argtypes = [C.POINTER(ArpcProblem), C.POINTER(C.c_size_t)]
@@ -162,6 +172,25 @@ def arpc_factor(problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: int, ws_p
     stats = ArpcStats()
     st = lib().arpc_factor(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(F_ptr), C.c_void_p(piv_ptr),
                            C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream), C.byref(stats))
+    return st, stats
+
+
+def arpc_factor_async(problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: int, ws_ptr: int, ws_bytes: int,
+                      stream: int, rounds: int = 0) -> int:
+    return lib().arpc_factor_async(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(F_ptr), C.c_void_p(piv_ptr),
+                                   C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream), C.c_int64(rounds))
+
+
+def arpc_factor_continue(problem: ArpcProblem, X_ptr: int, F_ptr: int, piv_ptr: int, ws_ptr: int, ws_bytes: int,
+                         stream: int, rounds: int) -> int:
+    return lib().arpc_factor_continue(C.byref(problem), C.c_void_p(X_ptr), C.c_void_p(F_ptr), C.c_void_p(piv_ptr),
+                                      C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream),
+                                      C.c_int64(rounds))
+
+
+def arpc_factor_query(problem: ArpcProblem, ws_ptr: int, ws_bytes: int):
+    stats = ArpcStats()
+    st = lib().arpc_factor_query(C.byref(problem), C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.byref(stats))
     return st, stats
 
 
@@ -383,6 +412,10 @@ def arpc_wait(ctx, job: int):
 
 def arpc_cancel(ctx, job: int) -> int:
     return lib().arpc_cancel(ctx, C.c_uint64(job))
+
+
+def arpc_serving_set_limit(ctx, max_outstanding: int) -> int:
+    return lib().arpc_serving_set_limit(ctx, C.c_int64(max_outstanding))
 
 
 def arpc_serving_info(ctx) -> dict:

@@ -145,6 +145,61 @@ KParams kparams_of(const arpc_problem& p) {
 
 
 
+// Status of a finished run from its final round state.
+arpc_status status_of(const arpc_problem& p, const RoundState& h) {
+  if (h.nonfinite) return ARPC_ENUMERIC;
+  if (h.status == ST_NOUNIF) return ARPC_EINVAL;
+  if (h.status == ST_RUNNING) return ARPC_INCOMPLETE;
+  return (h.k_r == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE)) ? ARPC_OK
+                                                                                            : ARPC_EARLY_STOP;
+}
+
+// Statistics of a run from its final round state, the accepted count of
+// each round (hist, h.round entries) and the residual trace.
+void fill_stats(const arpc_problem& p, const Layout& l, const RoundState& h, const int32_t* hist, double trace_resid,
+                arpc_stats* stats) {
+  if (!stats) return;
+  std::memset(stats, 0, sizeof(*stats));
+  const arpc_status ret = status_of(p, h);
+  const int64_t N = p.N;
+  stats->k_out = h.k_r;
+  stats->rounds = h.round;
+  stats->proposals = h.proposals;
+  stats->status = ret;
+  stats->trace_A = h.trace_A;
+  stats->trace_resid = trace_resid;
+  // algorithmic traffic per round and row: the blocked copy of F read over
+  // k_r columns at the contraction precision, the points, G written once to
+  // F at its storage precision, the row norm; the two-kernel path also writes
+  // C (update GEMM) and reads it (solve).  The write of G into the blocked
+  // copy (which the next rounds contract over) is counted apart.
+  double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0, bb = 0.0;
+  const double es = (double)elem_size(p.prec);
+  const double eb = p.prec == ARPC_FP64 ? 8.0 : (gemm_prec(p.prec) == ARPC_BF16 ? 2.0 : 4.0);
+  const bool fused = l.ncbt > 0;
+  for (int64_t r = 0; r < h.round; ++r) {
+    const double sr = hist[r];
+    fg += 2.0 * (double)N * kr * sr;
+    ft += (double)N * sr * sr;
+    if (sr > 0) {
+      if (fused) {
+        bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * es + 8.0);
+      } else {
+        bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
+        bt += (double)N * (sr * (eb + es) + 8.0);
+      }
+      if (!l.valu) bb += (double)N * sr * eb;
+    }
+    kr += sr;
+  }
+  stats->fused = fused ? 1 : 0;
+  stats->flops_colgemm = fg;
+  stats->flops_trsm = ft;
+  stats->bytes_colgemm = bg;
+  stats->bytes_trsm = bt;
+  stats->bytes_blocked = bb;
+}
+
 RoundJob round_job_of(const arpc_problem& p, const Layout& l, char* ws, const double* X, void* F,
                       int64_t* pivots, const Unif& un) {
   RoundJob j{};
@@ -307,7 +362,7 @@ struct Job final : JobBase {
     RoundState* st = (RoundState*)(ws + l.st);
     const int64_t nch = nchunks_of(p.N);
     HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
-    HIPCHK(hipMemcpyAsync(ws + l.jd, &hj, sizeof(RoundJob), hipMemcpyHostToDevice, s));
+    launch_store_job(s, hj, (RoundJob*)(ws + l.jd));
     prof->begin(ARPC_KC_INIT);
     if (p.prec == ARPC_FP8) launch_round_e4m3(s, Xin, (double*)(ws + l.Xq), p.N * p.d);
     if (l.packed)
@@ -352,6 +407,22 @@ struct Job final : JobBase {
     return ARPC_OK;
   }
 
+  // Rounds and the end of the run enqueued without reading anything back
+  // (the asynchronous entry points): rounds past the end exit on the device.
+  arpc_status enqueue_rounds(int64_t rounds) override {
+    for (int64_t r = 0; r < rounds; ++r)
+      enqueue_round<T>(s, p, kp, ws, l, X, F, (const RoundJob*)(ws + l.jd), hj, g, *prof);
+    HIPCHK(hipGetLastError());
+    return ARPC_OK;
+  }
+
+  arpc_status enqueue_end() override {
+    launch_trace(s, (double*)(ws + l.csum), nchunks_of(p.N), (double*)(ws + l.trace));
+    launch_zero_tail(s, (const RoundState*)(ws + l.st), p.k, p.N, (int)sizeof(T), F, pivots);
+    HIPCHK(hipGetLastError());
+    return ARPC_OK;
+  }
+
   bool running() override {
     if (hstate->status != ST_RUNNING) return false;
     known_k = hstate->k_r;
@@ -377,11 +448,8 @@ struct Job final : JobBase {
   }
 
   arpc_status finish_stats(const RoundState& h, double trace_resid, arpc_stats* stats) override {
-    if (h.nonfinite) return ARPC_ENUMERIC;
-    arpc_status ret = (h.k_r == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE))
-                          ? ARPC_OK
-                          : ARPC_EARLY_STOP;
-    if (h.status == ST_NOUNIF) ret = ARPC_EINVAL;
+    const arpc_status ret = status_of(p, h);
+    if (ret == ARPC_ENUMERIC) return ret;
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
       stats->k_out = h.k_r;
@@ -414,48 +482,9 @@ struct Job final : JobBase {
     }
     HIPCHK(hipStreamSynchronize(s));
 
-    arpc_status ret = (k_out == p.k || (p.max_rounds > 0 && h.round >= p.max_rounds && h.status == ST_DONE))
-                          ? ARPC_OK
-                          : ARPC_EARLY_STOP;
-    if (h.status == ST_NOUNIF) ret = ARPC_EINVAL;
+    const arpc_status ret = status_of(p, h);
+    fill_stats(p, l, h, hist.data(), trace_resid, stats);
     if (stats) {
-      std::memset(stats, 0, sizeof(*stats));
-      stats->k_out = k_out;
-      stats->rounds = h.round;
-      stats->proposals = h.proposals;
-      stats->status = (ret == ARPC_EINVAL) ? ARPC_EINVAL : ret;
-      stats->trace_A = h.trace_A;
-      stats->trace_resid = trace_resid;
-      // algorithmic traffic per round and row: the blocked copy of F read over
-      // k_r columns at the contraction precision, the points, G written once
-      // to F at its storage precision, the row norm; the two-kernel path also
-      // writes C (update GEMM) and reads it (solve).  The write of G into the
-      // blocked copy (which the next rounds contract over) is counted apart.
-      double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0, bb = 0.0;
-      const double es = (double)sizeof(T);
-      const double eb = p.prec == ARPC_FP64 ? 8.0 : (gemm_prec(p.prec) == ARPC_BF16 ? 2.0 : 4.0);
-      const bool fused = l.ncbt > 0;
-      for (int64_t r = 0; r < h.round; ++r) {
-        const double sr = hist[r];
-        fg += 2.0 * (double)N * kr * sr;
-        ft += (double)N * sr * sr;
-        if (sr > 0) {
-          if (fused) {
-            bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * es + 8.0);
-          } else {
-            bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
-            bt += (double)N * (sr * (eb + es) + 8.0);
-          }
-          if (!l.valu) bb += (double)N * sr * eb;
-        }
-        kr += sr;
-      }
-      stats->fused = fused ? 1 : 0;
-      stats->flops_colgemm = fg;
-      stats->flops_trsm = ft;
-      stats->bytes_colgemm = bg;
-      stats->bytes_trsm = bt;
-      stats->bytes_blocked = bb;
       for (int c = 0; c < ARPC_NUM_KC; ++c) {
         stats->ms_kernel[c] = prof->ms[c];
         stats->launches[c] = prof->n[c];
@@ -526,6 +555,7 @@ const char* arpc_status_str(int status) {
   switch (status) {
     case ARPC_OK: return "ok";
     case ARPC_EARLY_STOP: return "early stop: residual reached zero before k pivots";
+    case ARPC_INCOMPLETE: return "incomplete: the enqueued rounds ended before k pivots";
     case ARPC_EINVAL: return "invalid argument";
     case ARPC_ENOMEM: return "out of memory";
     case ARPC_EBUSY: return "busy";
@@ -559,6 +589,73 @@ arpc_status arpc_factor_uniforms(const arpc_problem* problem, const double* X, v
   if (!problem || !U || nU < 0 || ((uintptr_t)U & 7)) return ARPC_EINVAL;
   Unif un{U, nU, problem->seed};
   return factor_impl(problem, X, F, pivots, ws, ws_bytes, stream, un, stats, true);
+}
+
+// Rounds enqueued by arpc_factor_async when the problem sets no round limit:
+// the fewest that could suffice, plus half as many again and four.
+static int64_t default_async_rounds(const arpc_problem& p) {
+  const int64_t need = (p.k + p.b - 1) / p.b;
+  int64_t r = need + need / 2 + 4;
+  return r < p.k ? r : p.k;
+}
+
+arpc_status arpc_factor_async(const arpc_problem* problem, const double* X, void* F, int64_t* pivots, void* ws,
+                              size_t ws_bytes, void* stream, int64_t rounds) {
+  if (!problem) return ARPC_EINVAL;
+  arpc_status v = check_factor_args(problem, X, F, pivots);
+  if (v != ARPC_OK) return v;
+  if (!ws || ((uintptr_t)ws & 255) || rounds < 0) return ARPC_EINVAL;
+  Layout l = layout_of(*problem);
+  if (ws_bytes < l.total) return ARPC_EINVAL;
+  if (l.ncbt > 0) l.grid = fused_grid();
+  if (rounds == 0) rounds = problem->max_rounds > 0 ? problem->max_rounds : default_async_rounds(*problem);
+  const Unif un{nullptr, 0, problem->seed};
+  hipStream_t s = (hipStream_t)stream;
+  Profiler prof(s, 0u);
+  auto job = make_job(*problem, X, F, pivots, (char*)ws, l, s, un, nullptr, &prof);
+  arpc_status e = job->begin();
+  if (e == ARPC_OK) e = job->enqueue_rounds(rounds);
+  if (e == ARPC_OK) e = job->enqueue_end();
+  return e;
+}
+
+arpc_status arpc_factor_continue(const arpc_problem* problem, const double* X, void* F, int64_t* pivots, void* ws,
+                                 size_t ws_bytes, void* stream, int64_t rounds) {
+  if (!problem) return ARPC_EINVAL;
+  arpc_status v = check_factor_args(problem, X, F, pivots);
+  if (v != ARPC_OK) return v;
+  if (!ws || ((uintptr_t)ws & 255) || rounds < 1) return ARPC_EINVAL;
+  Layout l = layout_of(*problem);
+  if (ws_bytes < l.total) return ARPC_EINVAL;
+  if (l.ncbt > 0) l.grid = fused_grid();
+  const Unif un{nullptr, 0, problem->seed};
+  hipStream_t s = (hipStream_t)stream;
+  Profiler prof(s, 0u);
+  auto job = make_job(*problem, X, F, pivots, (char*)ws, l, s, un, nullptr, &prof);
+  arpc_status e = job->enqueue_rounds(rounds);
+  if (e == ARPC_OK) e = job->enqueue_end();
+  return e;
+}
+
+arpc_status arpc_factor_query(const arpc_problem* problem, const void* ws, size_t ws_bytes, arpc_stats* stats) {
+  arpc_status v = validate(problem);
+  if (v != ARPC_OK) return v;
+  if (!ws || ((uintptr_t)ws & 255)) return ARPC_EINVAL;
+  const Layout l = layout_of(*problem);
+  if (ws_bytes < l.total) return ARPC_EINVAL;
+  const char* w = (const char*)ws;
+  RoundState h{};
+  double trace = 0.0;
+  if (hipMemcpy(&h, w + l.st, sizeof(RoundState), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&trace, w + l.trace, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return ARPC_EDEVICE;
+  if (h.round < 0 || h.round > problem->k) return ARPC_EINVAL;   // not a state this library wrote
+  std::vector<int32_t> hist((size_t)h.round + 1, 0);
+  if (h.round > 0 &&
+      hipMemcpy(hist.data(), w + l.hist, sizeof(int32_t) * (size_t)h.round, hipMemcpyDeviceToHost) != hipSuccess)
+    return ARPC_EDEVICE;
+  fill_stats(*problem, l, h, hist.data(), trace, stats);
+  return status_of(*problem, h);
 }
 
 arpc_status arpc_stream_uniforms_host(uint64_t seed, int64_t start, int64_t n, double* out) {

@@ -86,6 +86,8 @@ struct JobBase {
   virtual arpc_status begin() = 0;
   virtual arpc_status capture_round() = 0;
   virtual arpc_status enqueue_batch() = 0;
+  virtual arpc_status enqueue_rounds(int64_t rounds) = 0;
+  virtual arpc_status enqueue_end() = 0;
   virtual bool running() = 0;
   virtual arpc_status finish(arpc_stats* stats, double ms_total) = 0;
   virtual arpc_status finish_enqueue(const RoundState& h, double* htrace) = 0;

@@ -53,6 +53,11 @@ void launch_reject_tab(hipStream_t s, const RoundJob* tab, int n, int bmax);
 void launch_prep_xp_tab(hipStream_t s, const RoundJob* tab, int n);
 void launch_diag_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g);
 void launch_finish_tab(hipStream_t s, const RoundJob* tab, int n);
+// *dst = j by a kernel (graph-capturable; j need not outlive the call).
+void launch_store_job(hipStream_t s, const RoundJob& j, RoundJob* dst);
+// Zero columns k_r .. k-1 of F (es-byte elements, N rows) and set pivots
+// k_r .. k-1 to -1, k_r read from the round state on the device.
+void launch_zero_tail(hipStream_t s, const RoundState* st, int64_t k, int64_t N, int es, void* F, int64_t* pivots);
 // out[i] = *tab[i].st for i < n (out: pinned host memory).
 void launch_collect_tab(hipStream_t s, const RoundJob* tab, int n, RoundState* out);
 

@@ -1342,6 +1342,39 @@ void launch_collect_tab(hipStream_t s, const RoundJob* tab, int n, RoundState* o
   hipLaunchKernelGGL(k_collect_states, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, tab, n, out);
 }
 
+// *dst = j: a job's table row written by a kernel (its argument is captured
+// at launch, so the host copy need not outlive the call).
+__global__ void k_store_job(RoundJob j, RoundJob* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = j;
+}
+
+void launch_store_job(hipStream_t s, const RoundJob& j, RoundJob* dst) {
+  hipLaunchKernelGGL(k_store_job, dim3(1), dim3(64), 0, s, j, dst);
+}
+
+// End of a run enqueued without the host: columns k_r .. k-1 of F (element
+// size es bytes, N rows) and pivots k_r .. k-1 (-1) as left by an early stop,
+// read from the round state (nothing to do when k pivots are held).
+__global__ __launch_bounds__(256) void k_zero_tail(const RoundState* __restrict__ st, int64_t k, int64_t N, int es,
+                                                   void* __restrict__ F, int64_t* __restrict__ pivots) {
+  const int64_t kr = st->k_r;
+  if (kr >= k || st->nonfinite) return;
+  const int64_t n = (k - kr) * N;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x, step = (int64_t)gridDim.x * 256;
+  if (es == 8) {
+    double* f = (double*)F + kr * N;
+    for (int64_t i = i0; i < n; i += step) f[i] = 0.0;
+  } else {
+    float* f = (float*)F + kr * N;
+    for (int64_t i = i0; i < n; i += step) f[i] = 0.f;
+  }
+  for (int64_t i = i0; i < k - kr; i += step) pivots[kr + i] = -1;
+}
+
+void launch_zero_tail(hipStream_t s, const RoundState* st, int64_t k, int64_t N, int es, void* F, int64_t* pivots) {
+  hipLaunchKernelGGL(k_zero_tail, dim3(2048), dim3(256), 0, s, st, k, N, es, F, pivots);
+}
+
 void launch_finish(hipStream_t s, RoundState* st, int b, int64_t kmax, int64_t max_rounds, int32_t* hist) {
   RoundJob j{};
   j.st = st;

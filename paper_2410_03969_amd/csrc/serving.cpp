@@ -163,6 +163,7 @@ struct arpc_ctx_s {
   arpc_serving_stats info{};
   bool graphs = true;
   bool use_ticks = true;
+  int64_t max_outstanding = 65536;   // submitted and not yet finished
   hipStream_t ts = nullptr;     // tick stream
   Tick ticks[kTicks];
   int next_tick = 0;            // tick buffer of the next launch
@@ -553,6 +554,7 @@ arpc_status arpc_submit(arpc_ctx ctx, const arpc_problem* problem, const double*
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->stop) return ARPC_ECANCELED;
+    if (ctx->info.queued + ctx->info.active >= ctx->max_outstanding) return ARPC_EBUSY;
     j->id = ctx->next_id++;
     *job = j->id;
     ctx->queue.push_back(j.get());
@@ -614,6 +616,13 @@ arpc_status arpc_cancel(arpc_ctx ctx, arpc_job job) {
     }
   }
   ctx->cv_work.notify_all();
+  return ARPC_OK;
+}
+
+arpc_status arpc_serving_set_limit(arpc_ctx ctx, int64_t max_outstanding) {
+  if (!ctx || max_outstanding < 1 || max_outstanding > 2147483647LL) return ARPC_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->max_outstanding = max_outstanding;
   return ARPC_OK;
 }
 
