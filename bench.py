@@ -271,6 +271,7 @@ def serving_measure(args):
         "pivots_per_s": round(piv / span, 1), "mean_resident_jobs": round(res, 3),
         "mean_pivots_per_job": round(piv / len(jobs), 1),
         "peak_active": info["peak_active"], "peak_bytes": info["peak_bytes"],
+        "ticks": info["ticks"], "ticked_jobs": info["ticked_jobs"],
         "closed_loop": {"pivots_per_s": round(piv_c / span_c, 1), "mean_resident_jobs": round(res_c, 3),
                         "p50_ms": round(float(np.percentile(lat_c, 50)), 3)},
     }
@@ -389,8 +390,9 @@ def main():
         torch.cuda.empty_cache()
         srv = serving_measure(args)
         out["serving"] = {k: srv[k] for k in ("p50_ms", "p99_ms", "saturation_jobs_per_s",
-                                             "arrival_rate_jobs_per_s", "pivots_per_s", "mean_resident_jobs",
-                                             "dtype", "closed_loop", "peak_active")}
+                                             "arrival_rate_jobs_per_s", "pivots_per_s", "mean_pivots_per_job",
+                                             "mean_resident_jobs", "dtype", "closed_loop", "peak_active",
+                                             "ticks", "ticked_jobs")}
         out["serving"]["workload"] = srv["config"]["workload"]
     if args.cpu_rounds > 0 and method == W.ACCEL:
         out["cpu_baseline"] = cpu_baseline(X, prob, args.cpu_rounds, last["rounds"])

@@ -715,8 +715,10 @@ void launch_fused_d(hipStream_t s, int dx, const FusedArgs& a, const RoundJob* t
   } else if (dx <= 16) {
     launch_fused_t<PASSES, NCBT, 16, TAB>(s, a, tab, n, grid);
   } else {
-    // d <= 32: one-product mode with at most 13 column blocks (the LDS holds
-    // the accepted points' 32 coordinates beside the resident inverse factor)
+    // d <= 32: the one-product mode with at most 13 column blocks (its LDS
+    // holds the accepted points' 32 coordinates beside the resident inverse
+    // factor).  The three-product mode differences coordinates directly and
+    // keeps the two-kernel round product there.
     if constexpr (PASSES == 1 && NCBT <= 13) launch_fused_t<PASSES, NCBT, 32, TAB>(s, a, tab, n, grid);
   }
 }

@@ -343,15 +343,15 @@ def test_fused_round_factor_consistent_with_its_pivots(prec, b, d):
     assert np.sum(F ** 2) <= trA * (1 + 1e-3)
 
 
-@pytest.mark.parametrize("b,d", [(20, 17), (60, 24), (120, 32), (200, 32)])
-def test_fused_round_wide_points_one_product(b, d):
+@pytest.mark.parametrize("prec,b,d", [(W.BF16, 20, 17), (W.BF16, 60, 24), (W.BF16, 120, 32), (W.BF16, 200, 32)])
+def test_fused_round_wide_points(prec, b, d):
     """The one-product BF16 mode also runs one kernel per round for
-    16 < d <= 32 when b <= 208 (13 column blocks): its factor equals the FP64
+    16 < d <= 32 when b <= 208 (13 column blocks): the factor equals the FP64
     factor of its pivots on sampled rows, as for d <= 16."""
     rng = np.random.default_rng(2000 + b + d)
     N = 5003
     X = rng.uniform(0.0, 1.0, size=(N, d))
-    prob = W.Problem(N=N, d=d, k=min(3 * b, 600), b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=12, prec=W.BF16)
+    prob = W.Problem(N=N, d=d, k=min(3 * b, 600), b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=12, prec=prec)
     F, piv, out = gpu_factor(X, prob)
     assert out["stats"]["fused"] == 1
     k_out = out["stats"]["k_out"]
@@ -361,15 +361,16 @@ def test_fused_round_wide_points_one_product(b, d):
     ncols = min(k_out, 2 * b)
     ref = factor_from_pivots(acc, piv[:ncols], rows=rows)
     err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
-    print(f"fused wide b={b} d={d} cols={ncols} relF={err:.3e}")
-    assert err < FUSED_TOL[W.BF16], err
+    print(f"fused wide prec={prec} b={b} d={d} cols={ncols} relF={err:.3e}")
+    assert err < FUSED_TOL[prec], err
     assert np.sum(F ** 2) <= out["stats"]["trace_A"] * (1 + 1e-3)
 
 
-@pytest.mark.parametrize("prec,b,d", [(W.BF16X3, 60, 24), (W.BF16, 240, 32), (W.BF16, 60, 33)])
+@pytest.mark.parametrize("prec,b,d", [(W.BF16X3, 60, 17), (W.BF16, 240, 32), (W.BF16, 60, 33)])
 def test_wide_points_outside_the_one_kernel_form(prec, b, d):
-    """Three products at d > 16, 14 or more column blocks at d > 16, or
-    d > 32 keep the two-kernel round product (and the same pivots rule)."""
+    """Three products at d > 16, one product with 14 or more column blocks
+    at d > 16, and d > 32 keep the two-kernel round product (where the
+    expanded distances fall back to direct differences as they cancel)."""
     rng = np.random.default_rng(3000 + b + d)
     X = rng.uniform(0.0, 1.0, size=(3001, d))
     prob = W.Problem(N=3001, d=d, k=2 * b, b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=13, prec=prec)
