@@ -122,16 +122,8 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const int64_t kr = st->k_r;
   const int64_t nk = (kr + FKC - 1) / FKC;      // contraction chunks of the update GEMM
   const int64_t N = a.N;
-  // Rows: 32-row units, one per wavefront and tile; workgroup x owns the
-  // contiguous units [u0, u1) (the ranges differ by at most one unit) and
-  // walks them FW at a time, so every workgroup ends within one partial tile
-  // of the others.  In a partial tile a wavefront past u1 repeats the last
-  // unit's loads and stores nothing.
-  const int64_t units = (N + FNB * 16 - 1) / (FNB * 16);
-  const int64_t u0 = (int64_t)blockIdx.x * units / gridDim.x;
-  const int64_t u1 = (int64_t)(blockIdx.x + 1) * units / gridDim.x;
-  const int64_t rlim = (FNB * 16 * u1 < N) ? FNB * 16 * u1 : N;   // rows this workgroup stores
-  const int ntl = (int)((u1 - u0 + FW - 1) / FW);                  // its tiles
+  constexpr int FROWS = FW * FNB * 16;           // rows per workgroup tile
+  const int ntiles = (int)((N + FROWS - 1) / FROWS);
   const int d = a.d;
   const int tid0 = threadIdx.x, w = tid0 >> 6;
 
@@ -228,8 +220,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   };
   auto prologue_early = [&](int tile_) {
     const int lane_ = tid & 63, l16_ = lane_ & 15, g_ = lane_ >> 4;
-    const int64_t unit_ = u0 + (int64_t)tile_ * FW + w;
-    const int64_t row_w_ = (unit_ < u1 ? unit_ : u1 - 1) * (FNB * 16);
+    const int64_t row_w_ = (int64_t)tile_ * FROWS + w * (FNB * 16);
     // this lane's rows (tiles nb = 0, 1): row_w + 16 nb + l16.  Expanded
     // form: coordinates 4 ks + g only, the B operand of the distance product
     // (lane (g, n) holds B(k = g, n)); direct form: all coordinates, scaled.
@@ -250,21 +241,20 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
     for (int u = 0; u < FD - 1; ++u) loadF(fr[u], rb_, u < nkl ? u : nkl);
   };
-  if (PRE && ntl > 0) {
+  if (PRE && (int)blockIdx.x < ntiles) {
     tid = tid0;
     asm volatile("" : "+v"(tid));
-    prologue_early(0);
+    prologue_early(blockIdx.x);
   }
 
-  for (int tile = 0; tile < ntl; ++tile) {
+  // tiles are dealt to the persistent workgroups in turn
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     // Lane-dependent values are re-derived in every tile: hoisted out of the
     // loop they would stay live across it and spill.
     tid = tid0;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, l16 = lane & 15, g = lane >> 4;
-    const int64_t unit = u0 + (int64_t)tile * FW + w;
-    const int64_t row_w = (unit < u1 ? unit : u1 - 1) * (FNB * 16);
-    const int64_t wlim = unit < u1 ? rlim : 0;   // rows this wavefront stores: < wlim
+    const int64_t row_w = (int64_t)tile * FROWS + w * (FNB * 16);
 
     f4 acc[FNB][NCBT];
 #pragma unroll
@@ -504,9 +494,9 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       g2 += __shfl_xor(g2, 16, 64);
       g2 += __shfl_xor(g2, 32, 64);
       const int64_t row = row_w + nb * 16 + l16;
-      if (row < wlim && g == 0) a.P[row] = (double)g2;
+      if (row < N && g == 0) a.P[row] = (double)g2;
     }
-    if (PRE && tile + 1 < ntl) prologue_early(tile + 1);
+    if (PRE && tile + (int)gridDim.x < ntiles) prologue_early(tile + gridDim.x);
     // Blocked BF16 copy, 8-byte stores straight from the accumulators.  Its
     // columns kr - m .. are cut into groups of four (m = kr mod 4, so a group
     // never crosses a 32-column chunk): lane (g, l16) of group mt writes
@@ -534,7 +524,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         for (int mt = 0; mt < NCBT + 3; ++mt) {
           const int64_t a0 = kr - m + 16 * mt + 4 * g;
           __bf16* p = prow + (a0 / FKC) * (int64_t)CHUNK_E + a0 % FKC;
-          const bool ok = row < wlim && a0 < zend;
+          const bool ok = row < N && a0 < zend;
           const bool first = mt == 0 && g == 0 && m != 0;
 #pragma unroll
           for (int pl = 0; pl < SPL; ++pl) {
@@ -575,7 +565,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // SEPW, else the ring area: no wavefront reads the ring after the last
     // barrier of the contraction)
     float* E = (float*)(lds + (SEPW ? WINOFF : 0)) + w * (WC * EROW);
-    const int nrows = (wlim - row_w) < (FNB * 16) ? (int)(wlim - row_w) : FNB * 16;
+    const int nrows = (N - row_w) < (FNB * 16) ? (int)(N - row_w) : FNB * 16;
     const bool vec_cols = (N & 3) == 0;          // 16-byte aligned columns of F
 #pragma unroll
     for (int w0 = 0; w0 < CP; w0 += WC) {
