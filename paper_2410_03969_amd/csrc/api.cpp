@@ -108,12 +108,15 @@ Layout layout_of(const arpc_problem& p) {
   l.Fb = take(valu ? 0 : mfma_blocked_bytes(gp, p.N, p.k));
   l.C = take(valu ? es * p.N * p.b : (fused ? 0 : mfma_blocked_bytes(gp, p.N, p.b)));
   l.dist = !valu && !fused && (mfma_dist_contraction((int)p.d) || p.prec == ARPC_FP8);
-  l.C0 = take(l.dist ? es * p.N * p.b : 0);
+  l.dist8 = l.dist && p.prec == ARPC_FP8 && p.d % 4 == 0 && mfma_dist_in_epilogue((int)p.d);
+  l.C0 = take(l.dist && !l.dist8 ? es * p.N * p.b : 0);
   l.P = take(sizeof(double) * nparts * p.N);
   l.Xq = take(p.prec == ARPC_FP8 ? sizeof(double) * p.N * p.d : 0);
   l.packed = p.prec == ARPC_FP8 && l.dist && p.d % 4 == 0;   // e4m3 codes for the distance kernel
   l.X8 = take(l.packed ? (size_t)p.N * p.d : 0);
   l.xn8 = take(l.packed ? sizeof(float) * p.N : 0);
+  l.Xp8 = take(l.dist8 ? (size_t)p.b * p.d : 0);
+  l.ypn = take(l.dist8 ? sizeof(float) * p.b : 0);
   l.trace = take(sizeof(double));
   l.total = off;
   return l;
@@ -296,10 +299,15 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
     prof.end();
   } else {
     MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
-                 (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k, l.dist ? (void*)(ws + l.C0) : nullptr,
-                 l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr};
+                 (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k,
+                 l.dist && !l.dist8 ? (void*)(ws + l.C0) : nullptr,
+                 l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr,
+                 l.dist8 ? (const unsigned char*)(ws + l.Xp8) : nullptr,
+                 l.dist8 ? (const float*)(ws + l.ypn) : nullptr};
     prof.begin(ARPC_KC_PREP);
     launch_prep_xp_tab(s, tab, 1);
+    if (l.dist8)   // the accepted points as e4m3 codes for the update GEMM's epilogue
+      launch_pack_e4m3(s, Xp, b, d, (unsigned*)(ws + l.Xp8), (float*)(ws + l.ypn));
     launch_mfma_prep(s, gemm_prec(p.prec), mr, st);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);

@@ -17,10 +17,12 @@ namespace arpc {
 
 // Offsets of the buffers carved from one factorization's workspace.
 struct Layout {
-  size_t st, jd, u, csum, cpre, props, acc, hist, Fs, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, trace,
-      total;
+  size_t st, jd, u, csum, cpre, props, acc, hist, Fs, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, Xp8,
+      ypn, trace, total;
   bool dist;  // kernel columns precomputed on the matrix cores (two-kernel path, d > 16 or FP8 mode)
   bool packed;  // FP8 mode, d % 4 == 0: the points also as e4m3 codes (X8) with their norms (xn8)
+  bool dist8;   // packed, d <= 256, d % 16 == 0: kernel columns in the update GEMM's epilogue
+                // (the accepted points as codes in Xp8 with norms ypn; no C0)
   int part_cols;
   bool valu;  // vector-unit GEMM kernels instead of the matrix-core ones
   int ncbt;   // > 0: one-kernel round product with this column-block count

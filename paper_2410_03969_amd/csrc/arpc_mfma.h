@@ -34,6 +34,9 @@ struct MfmaRound {
   const unsigned* X8;      // FP8 mode with d % 4 == 0: the rounded points as e4m3 codes (N x d
                            // bytes, row-major), or null
   const float* xn8;        // their squared norms (FP32), or null
+  const unsigned char* Xp8;  // FP8 mode with the distances in the update GEMM's epilogue: the
+                             // accepted points as e4m3 codes (b x d bytes), else null
+  const float* ypn;        // their squared norms (FP32)
 };
 
 // Device pointers and sizes of the one-kernel round product of the BF16
@@ -79,6 +82,8 @@ void launch_mfma_colgemm(hipStream_t s, int prec, const MfmaRound& r, const Roun
 // Kernel columns on the matrix cores for d > 16 (into r.C0, read by the
 // update GEMM's epilogue).
 bool mfma_dist_contraction(int d);
+// FP8 mode: the kernel columns formed in the update GEMM's epilogue (no C0).
+bool mfma_dist_in_epilogue(int d);
 // X8 = e4m3 codes of the (already rounded) points Xq, xn = their squared
 // norms in FP32; d % 4 == 0.
 void launch_pack_e4m3(hipStream_t s, const double* Xq, int64_t N, int d, unsigned* X8, float* xn);

@@ -117,6 +117,12 @@ struct PanelArgs {
   int npanels;         // row panels of this kernel
   int ngroups;         // column groups
   const void* C0;      // colgemm: kernel columns precomputed by k_dist (T, column-major, ld N), or null
+  // colgemm in the FP8 mode with the distances in the epilogue (see k_panel):
+  const unsigned char* X8;   // the rounded points as e4m3 codes, N x d bytes
+  const float* xn8;          // their squared norms
+  const unsigned char* Xp8;  // the accepted points as e4m3 codes, b x d bytes
+  const float* ypn;          // their squared norms
+  KFast kf;
 };
 
 // Byte offset of element (k, c) of the chunked small operand.
@@ -173,7 +179,17 @@ constexpr int panel_lds_bytes() {
   return stage > epi ? stage : epi;
 }
 
-template <class Pol, int NCB, int MODE, int PASSES>
+// DIST8 (update GEMM of the FP8 mode, d <= 256, d % 16 == 0): the kernel
+// columns are formed in the epilogue from the e4m3 codes instead of being read
+// from C0.  Each wavefront stages its 64 rows' codes into its own part of the
+// LDS (row stride d + 4 bytes, so the sixteen rows a product reads fall in
+// distinct banks) and, per column block, forms x.y on the FP8 matrix cores
+// (16x16x32, FP32 accumulation, products exact), with the accepted points'
+// codes as the A operand: the result lands in the accumulator layout of the
+// update GEMM, so C = kappa - F F(S_r,:)^T is formed in the registers.  r^2 =
+// |x|^2 + |y|^2 - 2 x.y, with the direct-difference fallback where it cancels
+// (as in k_dist).
+template <class Pol, int NCB, int MODE, int PASSES, bool DIST8 = false>
 __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
   using T = typename Pol::T;
   using S = typename Pol::S;
@@ -367,6 +383,69 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
     }
   }
 
+  if constexpr (DIST8) {
+    // the staging ring is free (the loop ended with a barrier); wavefront w's
+    // rows (64 RS <= 16640 bytes) go to the start of its own epilogue window
+    // E (the same offset as E below), which only it touches from here on
+    const int dd = a.d, RS = dd + 4, parts = dd / 16;
+    constexpr size_t EBYTES = (size_t)(WROWS + 1) * EPI_CB * 16 * sizeof(T);
+    static_assert(64 * (256 + 4) <= EBYTES, "staged rows fit the epilogue window");
+    unsigned* rowsL = (unsigned*)(lds + (size_t)w * EBYTES);
+    for (int q = lane; q < 64 * parts; q += 64) {
+      const int r = q / parts, pc = q % parts;
+      int64_t rr = row_w + r;
+      if (rr >= N) rr = N - 1;
+      const u4 v = *(const u4*)(a.X8 + (size_t)rr * dd + 16 * pc);
+      unsigned* dst = rowsL + (r * RS + 16 * pc) / 4;
+      dst[0] = v[0];
+      dst[1] = v[1];
+      dst[2] = v[2];
+      dst[3] = v[3];
+    }
+    float xn[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      int64_t rr = row_w + 16 * nb + l16;
+      xn[nb] = a.xn8[rr < N ? rr : N - 1];
+    }
+    const float frac = 0x1p-6f;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      if (cb < ncb) {   // uniform
+        const int cl = 16 * (cb0 + cb) + l16;                 // A operand: column of this lane
+        const unsigned char* xa = a.Xp8 + (size_t)(cl < s ? cl : s - 1) * dd + 8 * g;
+        f4 dp[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) dp[nb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < dd; k0 += 32) {
+          // a lane's 8 dims are all inside d or all past it (d % 16 == 0);
+          // past it both operands are zero
+          const bool in = k0 + 8 * g < dd;
+          const long ap = in ? *(const long*)(xa + k0) : 0l;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const unsigned* src = rowsL + ((16 * nb + l16) * RS + k0 + 8 * g) / 4;
+            const long bp = in ? (long)((unsigned long)src[0] | ((unsigned long)src[1] << 32)) : 0l;
+            dp[nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ap, bp, dp[nb], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 16 * (cb0 + cb) + 4 * g + i;
+          const float y = a.ypn[c < s ? c : s - 1];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int64_t rr = row_w + 16 * nb + l16;
+            float r2 = xn[nb] + y - 2.f * dp[nb][i];
+            if (__builtin_expect(r2 < frac * (xn[nb] + y), 0))   // cancellation: direct differences
+              r2 = (float)sqdist(a.X + (rr < N ? rr : N - 1) * dd, a.Xp + (int64_t)(c < s ? c : s - 1) * dd, dd);
+            acc[nb][cb][i] = kappa_fast(r2 > 0.f ? r2 : 0.f, a.kf) - acc[nb][cb][i];
+          }
+        }
+      }
+    }
+  }
+
   // ------------------------------------------------------------- epilogue
   // Windows of 64 columns:
   //  A. accumulator tiles -> LDS tile E[col][row] of this wavefront;
@@ -421,7 +500,9 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
       for (int cc = my_part; cc < wv; cc += LPR) {
         const int c = w0 + cc;
         T& v = E[cc * EROW + my_row];
-        if (MODE == MODE_COLGEMM && a.C0) {
+        if (MODE == MODE_COLGEMM && DIST8) {
+          // C formed in the registers before the window
+        } else if (MODE == MODE_COLGEMM && a.C0) {
           v = (T)((double)((const T*)a.C0)[(int64_t)c * N + row] - (double)v);
         } else if (MODE == MODE_COLGEMM) {
           const double* xp = a.Xp + (int64_t)c * d;
@@ -987,11 +1068,18 @@ static void launch_panel(hipStream_t s, const MfmaRound& r, const RoundState* st
   const int64_t nkcF = (r.kmax + Pol::KC - 1) / Pol::KC, nkcC = (r.b + Pol::KC - 1) / Pol::KC;
   if (which == 0) {
     PanelArgs a1{r.Fb, nkcF, r.N, r.Bm1, r.Ctot, r.X, r.d, r.Xp, r.kp, nullptr, r.C, nkcC, nullptr, st,
-                 npanels, ngroups, r.C0};
+                 npanels, ngroups, r.C0, (const unsigned char*)r.X8, r.xn8, r.Xp8, r.ypn, kfast_of(r.kp)};
+    if constexpr (std::is_same<Pol, PolBF<1>>::value) {
+      if (r.Xp8) {
+        hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_COLGEMM, PASSES, true>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0,
+                           s, a1);
+        return;
+      }
+    }
     hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_COLGEMM, PASSES>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0, s, a1);
   } else {
     PanelArgs a2{r.C, nkcC, r.N, r.Bm2, r.Ctot, nullptr, 0, nullptr, r.kp, r.F, r.Fb, nkcF, r.P, st,
-                 npanels, ngroups, nullptr};
+                 npanels, ngroups, nullptr, nullptr, nullptr, nullptr, nullptr, KFast{}};
     hipLaunchKernelGGL((k_panel<Pol, NCB, MODE_TRSM, PASSES>), dim3(nblocks), dim3(64 * PANEL_WAVES), 0, s, a2);
   }
 }
@@ -1078,6 +1166,8 @@ void launch_mfma_prep(hipStream_t s, int prec, const MfmaRound& r, const RoundSt
 }
 
 bool mfma_dist_contraction(int d) { return d > XREG; }
+
+bool mfma_dist_in_epilogue(int d) { return d <= 256 && d % 16 == 0; }
 
 void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st) {
   const int64_t nrb = (r.N + 255) / 256;

@@ -412,18 +412,19 @@ def test_reduced_precision_trace_error(prec):
     assert tem <= 1.05 * te64 and nym <= 1.05 * ny64
 
 
-@pytest.mark.parametrize("d", [24, 30, 40])
+@pytest.mark.parametrize("d", [24, 30, 40, 32, 48, 256])
 def test_fp8_mode_factors_the_rounded_points(d):
     """The FP8 mode factors the kernel matrix of the points rounded to e4m3:
     its factor matches the FP64 factor of its pivots on round_e4m3(X) to the
     BF16 update's accuracy, and is clearly further from that of the unrounded
     points.  Coordinates reach (240, 448] (OCP e4m3 only) and beyond 448
     (saturation); d = 24 and 40 leave a ragged 32-wide contraction step (packed
-    e4m3 rows), d = 30 takes the unpacked path (d not a multiple of 4).
-    N = 4001 at d = 24: the stored kernel columns end in a run short of four
-    rows."""
+    e4m3 rows, kernel columns stored by the distance kernel), d = 30 takes the
+    unpacked path (d not a multiple of 4); d = 32, 48 and 256 form the kernel
+    columns in the update GEMM's epilogue (d % 16 == 0, d <= 256; 48 leaves a
+    ragged step there).  N = 4001 at d = 24 and 48: the last tile is ragged."""
     rng = np.random.default_rng(d)
-    N = 4001 if d == 24 else 4000
+    N = 4001 if d in (24, 48) else 4000
     X = 100.0 * rng.standard_normal((N, d))
     X[0, 0], X[1, 1], X[2, 2] = 1000.0, -460.0, 300.0
     prob = W.Problem(N=N, d=d, k=300, b=60, kernel=W.GAUSSIAN, sigma=60.0 * np.sqrt(d), seed=d, prec=W.FP8)
