@@ -487,34 +487,35 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
 
 // Tiled form for b <= 256, one workgroup of eight wavefronts.  Wavefront 0
 // runs the tests; the other seven hold the trailing submatrix as 16 x 16
-// tiles in FP64 matrix-core accumulators (tile t = J (J + 1) / 2 + L of the
-// lower triangle, J >= L, belongs to tile wavefront t mod 7; entry i of lane
-// (g, n) is row 16 J + g + 4 i, column 16 L + n: the layout of the FP64
-// 16x16x4 product's accumulator).  The proposals are taken 16 at a time
-// (block column I), in this order in the GT form below:
-//  1. the tile wavefronts finish the previous block's update on block column
-//     I and copy it to LDS;
-//  2. wavefront 0 runs the tests of Alg. 1 on the diagonal block while the
-//     tile wavefronts apply the previous block's update to the rest of the
-//     trailing tiles;
-//  3. the panel below the block is solved against the accepted columns as a
-//     product with the inverse of their factor, X (formed by wavefront 0 with
-//     the tests), four matrix-core products per tile;
-//  4. (at the next block) the trailing tiles receive the rank-16 update on
-//     the matrix cores, four products per tile (rejected columns are zero).
-// The register-resident form defers 3 and 4 of block I - 1 into block I
+// tiles in FP64 matrix-core accumulators.  The tiles of the lower triangle
+// are numbered down the block columns, t = T0(L) + J - L for tile (J, L),
+// J >= L, T0(L) = L nbk - L (L - 1) / 2, and tile t belongs to tile wavefront
+// t mod 7 (its slot t / 7), so the tiles of block columns L >= I are a range
+// of each wavefront's slots.  Entry i of lane (g, n) of a tile is row
+// 16 J + g + 4 i, column 16 L + n: the layout of the FP64 16x16x4 product's
+// accumulator.  The proposals are taken 16 at a time (block column I):
+//  1. wavefront 0 runs the tests of Alg. 1 on the diagonal block and forms
+//     the block's columns of the factor and the inverse X of their factor;
+//  2. the panel below the block is solved against the accepted columns as a
+//     product with X, four matrix-core products per tile;
+//  3. the trailing tiles receive the rank-16 update on the matrix cores, four
+//     products per tile (rejected columns are zero).
+// The register-resident form defers 2 and 3 of block I - 1 into block I
 // (look-ahead): before block I's tests only the panel row P_I and the
-// diagonal tile (I, I) are computed; the rest of the panel runs beside the
-// first half of the tests and the rest of the update beside the second half
-// (X double-buffered, barriers on LDS only).  The block-column buffer is
-// double-buffered so a block's copy does not overwrite the previous panel
-// while it is still being applied.  The scaled column of proposal i goes to
-// column i of H (no longer read once in registers), where the solve's
-// preparation reads it.
+// diagonal tile (I, I) are computed (by that tile's owner); the rest of the
+// panel runs beside the first half of the tests and the rest of the update
+// beside the second half (X double-buffered, barriers on LDS only).  The
+// block-column buffer is double-buffered so a block's copy does not
+// overwrite the previous panel while it is still being applied.  Block 0's
+// diagonal block is read from H itself, so its tests start while the tile
+// wavefronts are still loading.
 // For 256 < b <= 512 the triangle (up to 528 tiles, 1 MiB) does not fit the
 // register file; the GT form keeps the trailing tiles in H and streams them
-// through steps 1-4 (three full barriers per block; there the trailing
+// through the steps (three full barriers per block; there the trailing
 // update, not the tests, sets the pace, so the look-ahead gains nothing).
+// Duplicates: the latest earlier proposal of the same point is found through
+// chained hash buckets in LDS (the chains are short; each is walked in full,
+// so the answer does not depend on the order of the insertions).
 constexpr int RT = 16;                  // tile edge
 constexpr int REJECT_T_THREADS = 512;
 constexpr int REJECT_T_BMAX = 256;
@@ -522,21 +523,38 @@ constexpr int REJECT_G_BMAX = 512;      // the form with the trailing tiles in g
 constexpr int REJECT_T_TW = 7;          // tile wavefronts
 constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
+constexpr int DUP_HBITS = 12;           // 4096 hash buckets
 
-// (J, L) of lower-triangular tile index t, given those of t - step (L may
-// start past J: it is carried into the following rows).
-__device__ inline void tile_advance(int& J, int& L) {
-  while (L > J) {
-    L -= J + 1;
-    ++J;
-  }
+// LDS of the tiled form.  The small arrays come first, at addresses that fit
+// the offset field of the LDS instructions.
+template <int BM>
+struct RejectLds {
+  double BC[RT][RT];       // BC[ii][r]: column ii of the diagonal block (unscaled) when its test runs
+  double XB[2][RT * RT];   // X of the last two blocks, X(r, c) at [r * RT + c]
+  double rsq[RT];          // 1/sqrt(h) of the block's accepted proposals (0: rejected)
+  double uv[BM];           // u_i V_i of the test
+  short prv[BM], accl[BM];
+  unsigned char tk[BM];
+  int bmask;
+  alignas(16) double Q[2][BM][QS];   // block columns
+};
+// The duplicate search's scratch, in the block-column buffer before the first block.
+struct DupScratch {
+  int64_t pr[REJECT_G_BMAX];
+  int nxt[REJECT_G_BMAX];
+  int head[1 << DUP_HBITS];
+};
+static_assert(sizeof(DupScratch) <= sizeof(double) * 2 * REJECT_T_BMAX * QS, "duplicate scratch exceeds the block buffer");
+
+__device__ __forceinline__ int dup_bucket(int64_t p) {
+  return (int)(((uint64_t)p * 0x9E3779B97F4A7C15ull) >> (64 - DUP_HBITS));
 }
 
 // Workgroup barrier for LDS traffic only (it does not wait for global stores
-// in flight): the register-resident form exchanges data between its waves
-// only through LDS (the factor columns stored to H are read by later
-// kernels, and every tile load from a column block of H has been consumed
-// before that block's columns are written).
+// in flight): the tiled forms exchange data between their waves only through
+// LDS (the factor columns stored to H are read by later kernels, and every
+// tile load from a column block of H has been consumed before that block's
+// columns are written).
 __device__ __forceinline__ void lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -558,19 +576,9 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
   const int keep_all = RJ.keep_all;
   if (st->status != ST_RUNNING) return;
   constexpr int BM = GT ? REJECT_G_BMAX : REJECT_T_BMAX;
-  __shared__ __attribute__((aligned(16))) double Q[2][BM][QS];  // block columns
-  __shared__ double LD[RT][RT];            // LD[ii][r]: scaled accepted column ii at row r of the block
-  __shared__ double BC[RT][RT];            // BC[ii][r]: column ii of the block when its test runs;
-                                           // then X = L^{-1} of the block's accepted part, X(r, c) at BC[r][c]
-  __shared__ double rsq[RT];               // 1/sqrt(h) of the accepted proposals (0: rejected)
-  // register form (look-ahead): X of the last two blocks, XB[I & 1] for block I
   constexpr bool LA = !GT;
-  __shared__ double XB[LA ? 2 * RT * RT : 1];
-  __shared__ double uv[BM];     // u_i V_i of the test
-  __shared__ int64_t pr[BM];
-  __shared__ short prv[BM], accl[BM];
-  __shared__ unsigned char tk[BM];
-  __shared__ int bmask;
+  __shared__ RejectLds<BM> sm;
+  DupScratch& dsc = *reinterpret_cast<DupScratch*>(&sm.Q[0][0][0]);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: tile coordinates stay scalar
   const int g = lane >> 4, l16 = lane & 15;
@@ -579,144 +587,191 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
   const int nbk = (b + RT - 1) / RT;
   const int ntile = nbk * (nbk + 1) / 2;
 
-  if (tid < b) {
-    uv[tid] = keep_all ? 0.0 : H[(int64_t)tid * b + tid] * stream_uniform(un, 2 * (int64_t)b * round + b + tid);
-    pr[tid] = props[tid];
-    tk[tid] = 0;
-  }
-  __syncthreads();
-  // the latest earlier proposal of the same point, eight LDS reads in flight
-  if (tid < b) {
-    const int64_t me = pr[tid];
-    int p = -1;
-    for (int q0 = tid - 1; q0 >= 0 && p < 0; q0 -= 8) {
-      int64_t v[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = (q0 - k >= 0) ? pr[q0 - k] : -1;
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (p < 0 && v[k] == me) p = q0 - k;
-    }
-    prv[tid] = (short)p;
-  }
-
   int nacc = 0;
   if (w == 0) {
+    // ---- per-proposal state (proposals lane, lane + 64, ...) and the
+    // duplicate chains.  This wavefront's loads are issued before the start
+    // barrier (P), the tile wavefronts' tile loads after it, so these do not
+    // queue behind them.
+    constexpr int PW = BM / 64;
+    // block 0's diagonal block, row l16 (no update is pending there), kept in
+    // rows 0..15 of the second block buffer, which no block column reaches
+    double dr0[RT], hv[PW], uu[PW];
+    int64_t pv[PW];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) dr0[c] = (l16 < b && c < b) ? H[(int64_t)c * b + l16] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int i = lane + 64 * q;
+      pv[q] = i < b ? props[i] : 0;
+      hv[q] = i < b ? H[(int64_t)i * b + i] : 0.0;
+      uu[q] = (i < b && un.U) ? un.U[2 * (int64_t)b * round + b + i] : 0.0;
+    }
+    lds_sync();   // (P)
+    for (int q = lane; q < (1 << DUP_HBITS) / 4; q += 64)
+      reinterpret_cast<int4*>(dsc.head)[q] = make_int4(-1, -1, -1, -1);
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int i = lane + 64 * q;
+      if (i < b) {
+        sm.tk[i] = 0;
+        dsc.pr[i] = pv[q];
+        dsc.nxt[i] = atomicExch(&dsc.head[dup_bucket(pv[q])], i);
+      }
+    }
+    for (int i = lane; i < b; i += 64) {
+      const int64_t p = dsc.pr[i];
+      int best = -1;
+      int q = dsc.head[dup_bucket(p)];
+      for (int n = 0; q >= 0 && n < b; ++n) {   // a chain holds each proposal once
+        if (q < i && q > best && dsc.pr[q] == p) best = q;
+        q = dsc.nxt[q];
+      }
+      sm.prv[i] = (short)best;
+    }
+    if (LA && g == 0)
+#pragma unroll
+      for (int c = 0; c < RT; ++c) sm.Q[1][l16][c] = dr0[c];
+    lds_sync();   // (0) the scratch is free for the block columns; the uniforms are in uv
+    // u_i V_i of the tests (keep_all: V = 0)
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int i = lane + 64 * q;
+      if (i < b) sm.uv[i] = keep_all ? 0.0 : hv[q] * (un.U ? uu[q] : sm.uv[i]);
+    }
+
     // ---- the tests.  Lane r (mod 16) keeps row 16 I + r of the (symmetric)
     // diagonal block.  The update after an accepted proposal ii is written as
     // T(r, c) -= (T(r, ii) / h) T(c, ii), the same rank-one update as with the
     // scaled column, so the chain from one test to the next holds a
     // reciprocal but no square root; the scaled columns, 1/sqrt(h) and the
-    // outputs are formed for the whole block afterwards, one lane per column.
-    // Straight-line code: a rejected proposal has a zero multiplier.  Column
-    // ii is broadcast through LDS at the start of its step, off the chain.
-    // Lane ii also holds what the test of proposal 16 I + ii needs: u V, and
-    // whether an earlier proposal of the same point was taken (before this
-    // block: from tk; inside it: the scalar mask).
-    int pm = 0;   // accepted columns of the previous block (register form: its panel is pending)
+    // outputs are formed for the whole block afterwards.  Straight-line code:
+    // a rejected proposal has a zero multiplier.  Column ii is written to BC
+    // at the start of its step (the row of the next test by readlane, the
+    // rest through LDS, needed no earlier than the test after next); BC then
+    // holds every unscaled column of the block's factor.
     for (int I = 0; I < nbk && nacc < cap; ++I) {
-      double(*Qb)[QS] = Q[I & 1];
-      if constexpr (LA) {
-        lds_sync();   // (1) the diagonal block of block column I is in LDS
-      } else {
-        __syncthreads();   // (1) block column I is in LDS
+      if (!LA || I > 0) {
+        if constexpr (LA) lds_sync();       // (1) the diagonal block of block column I is in LDS
+        else __syncthreads();                // (1) block column I is in LDS
       }
+      const double* src = (LA && I == 0) ? &sm.Q[1][l16][0] : &sm.Q[I & 1][RT * I + l16][0];
       double dr[RT];
 #pragma unroll
-      for (int c = 0; c < RT; ++c) dr[c] = Qb[RT * I + l16][c];
+      for (int c = 0; c < RT; ++c) dr[c] = src[c];
       const int iL = RT * I + l16;
       double uvL = 0.0;
       int pL = -1;
       bool dupL = false;
       if (iL < b) {
-        uvL = uv[iL];
-        const int p = prv[iL];
+        uvL = sm.uv[iL];
+        const int p = sm.prv[iL];
         if (p >= RT * I) pL = p - RT * I;
-        else if (p >= 0) dupL = tk[p] != 0;
+        else if (p >= 0) dupL = sm.tk[p] != 0;
       }
       const unsigned dup_before = (unsigned)__ballot(dupL) & 0xffffu;
-      int mask = 0, taken = 0, cnt = 0;
-      double hL = 1.0;   // lane ii: h of proposal 16 I + ii
+      const int bl = b - RT * I;
+      const unsigned okm = bl >= RT ? 0xffffu : ((1u << bl) - 1u);
+      const int capL = cap - nacc;
+      unsigned mask = 0, taken = 0;
+      int cnt = 0;
+      // column ii goes to BC, and its entries below the next row are read
+      // back, at the end of step ii - 1, so that the LDS round trip overlaps
+      // the next test
+      double bcn[RT];
+      sm.BC[0][l16] = dr[0];
+#pragma unroll
+      for (int c = 2; c < RT; ++c) bcn[c] = sm.BC[0][c];
 #pragma unroll
       for (int ii = 0; ii < RT; ++ii) {
-        const int i = RT * I + ii;
         if constexpr (LA) {
-          if (ii == RT / 2 && pm) lds_sync();   // (m)
+          if (ii == RT / 2) lds_sync();   // (m) the panel of the previous block is complete
         }
-        // column ii is final: T(ii + 1, ii), needed by the next test, by
-        // readlane; the rest through LDS (lanes r and r + 16 k write the same
-        // value), needed no earlier than the test after next
-        BC[ii][l16] = dr[ii];
         const double bn = readlane_f64(dr[ii], ii + 1 < RT ? ii + 1 : ii);
         double bc[RT];
 #pragma unroll
-        for (int c = ii + 2; c < RT; ++c) bc[c] = BC[ii][c];
-        // the test, evaluated on lane ii (which holds h = its diagonal entry)
-        const int dupl = (int)((dup_before >> l16) & 1u) | ((pL >= 0) & (int)((taken >> (pL & 15)) & 1));
-        const int al = (dupl ^ 1) & (uvL < dr[ii] ? 1 : 0);
-        const int bits = __builtin_amdgcn_readlane(al | (dupl << 1), ii);
-        const bool dup = (bits & 2) != 0;
-        const bool a = (bits & 1) && i < b && nacc + cnt < cap;
+        for (int c = ii + 2; c < RT; ++c) bc[c] = bcn[c];
+        // the test of proposal 16 I + ii, from lane ii's values: its u V
+        // against h = its diagonal entry, and whether an earlier proposal of
+        // the same point was taken (before this block: dup_before; in it:
+        // the taken mask at its local index)
+        // 1/h: hardware reciprocal and two Newton steps (exact for h = 1),
+        // formed beside the decision; where the proposal is not accepted
+        // (h may then be zero or negative) the multiplier is selected away
         const double h = readlane_f64(dr[ii], ii);
-        taken |= (a || dup) ? (1 << ii) : 0;
-        // 1/h: hardware reciprocal and two Newton steps (exact for h = 1)
-        const double ha = a ? h : 1.0;
-        double inv = __builtin_amdgcn_rcp(ha);
-        inv = fma(inv, fma(-ha, inv, 1.0), inv);
-        inv = fma(inv, fma(-ha, inv, 1.0), inv);
-        const double t = a ? dr[ii] * inv : 0.0;
-        if (ii + 1 < RT) dr[ii + 1] = fma(-t, bn, dr[ii + 1]);
+        double inv = __builtin_amdgcn_rcp(h);
+        inv = fma(inv, fma(-h, inv, 1.0), inv);
+        inv = fma(inv, fma(-h, inv, 1.0), inv);
+        const double tv = dr[ii] * inv;
+        const unsigned long long lt = __ballot(uvL < dr[ii]);
+        const int pq = __builtin_amdgcn_readlane(pL, ii);
+        const unsigned dup = ((dup_before >> ii) | ((taken >> (pq & 15)) & (unsigned)(pq >= 0))) & 1u;
+        const unsigned below_cap = (unsigned)(cnt - capL) >> 31;
+        const unsigned av = ~dup & (unsigned)(lt >> ii) & (okm >> ii) & below_cap & 1u;
+        taken |= (av | dup) << ii;
+        mask |= av << ii;
+        cnt += (int)av;
+        const double t = av ? tv : 0.0;
+        if (ii + 1 < RT) {
+          dr[ii + 1] = fma(-t, bn, dr[ii + 1]);
+          sm.BC[ii + 1][l16] = dr[ii + 1];
+        }
 #pragma unroll
         for (int c = ii + 2; c < RT; ++c) dr[c] = fma(-t, bc[c], dr[c]);
-        hL = (l16 == ii) ? h : hL;
-        mask |= a ? (1 << ii) : 0;
-        cnt += a ? 1 : 0;
-      }
-      // the block's outputs: lane c forms 1/sqrt(h_c); row r keeps the
-      // unscaled entries T(r, ii) of the steps, which scale into column ii
-      const double rsL = ((mask >> l16) & 1) ? 1.0 / sqrt(hL) : 0.0;
-      if (lane < RT) {
-        rsq[lane] = rsL;
-        if (iL < b) tk[iL] = (taken >> lane) & 1;
-        if ((mask >> lane) & 1) accl[nacc + __popc(mask & ((1 << lane) - 1))] = (short)iL;
-      }
-      double rs[RT];
 #pragma unroll
-      for (int ii = 0; ii < RT; ++ii) rs[ii] = rsq[ii];
-      // column ii of the factor (zero for a rejected proposal) into column
-      // 16 I + ii of H, rows of the block at and below ii
+        for (int c = ii + 3; c < RT; ++c) bcn[c] = sm.BC[ii + 1][c];
+      }
+      // ---- the block's outputs.  Lane c forms 1/sqrt(h_c) from its diagonal
+      // entry BC[c][c]; column ii of the factor (zero for a rejected
+      // proposal) is BC[ii][r] / sqrt(h_ii), rows r >= ii, stored to column
+      // 16 I + ii of H by lanes (g, r) for ii = g, g + 4, g + 8, g + 12.
+      {
+        const double hL = sm.BC[l16][l16];
+        const double rsL = ((mask >> l16) & 1u) ? 1.0 / sqrt(hL) : 0.0;
+        if (lane < RT) {
+          sm.rsq[lane] = rsL;
+          if (iL < b) sm.tk[iL] = (taken >> lane) & 1u;
+          if ((mask >> lane) & 1u) sm.accl[nacc + __popc(mask & ((1u << lane) - 1u))] = (short)iL;
+        }
 #pragma unroll
-      for (int ii = 0; ii < RT; ++ii) {
-        const double col = (l16 >= ii) ? dr[ii] * rs[ii] : 0.0;
-        if (lane < RT) LD[ii][lane] = col;
-        if (lane < RT && lane >= ii && iL < b && RT * I + ii < b) H[(int64_t)(RT * I + ii) * b + iL] = col;
+        for (int i = 0; i < 4; ++i) {
+          const int ii = g + 4 * i;
+          if (l16 >= ii && iL < b && RT * I + ii < b)
+            H[(int64_t)(RT * I + ii) * b + iL] = sm.BC[ii][l16] * sm.rsq[ii];
+        }
       }
       // X = L^{-1} restricted to the accepted proposals (rejected rows and
       // columns come out zero): lane c forms column c by forward
-      // substitution, into XS(r, c) (the broadcast area, free again)
+      // substitution on the unscaled columns, L(r, k) = BC[k][r] rs_k:
+      // x_k = y_k rs_k, then y_r -= BC[k][r] (x_k rs_k) for r > k
       {
         double y[RT];
+        // the right-hand side e_c, from a value of this block (a
+        // loop-invariant one would be hoisted out of the block loop and held
+        // in registers through it)
+        const double one = (double)(mask | 1u) / (double)(mask | 1u);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) y[r] = (r == l16) ? 1.0 : 0.0;
+        for (int r = 0; r < RT; ++r) y[r] = (r == l16) ? one : 0.0;
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
-          const double xk = y[k] * rsq[k];
+          const double rk = sm.rsq[k];
+          const double xk = y[k] * rk;
+          const double zk = xk * rk;
           y[k] = xk;
 #pragma unroll
-          for (int r = k + 1; r < RT; ++r) y[r] = fma(-LD[k][r], xk, y[r]);
+          for (int r = k + 1; r < RT; ++r) y[r] = fma(-sm.BC[k][r], zk, y[r]);
         }
-        double* xo = LA ? XB + (I & 1) * RT * RT : &BC[0][0];
+        double* xo = sm.XB[I & 1];
         if (lane < RT)
 #pragma unroll
           for (int r = 0; r < RT; ++r) xo[r * RT + lane] = y[r];
       }
-      if (lane == 0) bmask = mask;
+      if (lane == 0) sm.bmask = (int)mask;
       if constexpr (LA) {
-        lds_sync();   // (2) decisions, LD, rsq and X are in LDS
-        pm = mask;
+        lds_sync();   // (2) decisions, rsq and X are in LDS
         if (mask == 0) continue;
       } else {
-        __syncthreads();   // (2) decisions, LD, rsq and X are in LDS
+        __syncthreads();   // (2) decisions, rsq and X are in LDS
         if (mask == 0) continue;
         __syncthreads();   // (3) the panel is solved
       }
@@ -724,26 +779,33 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
     }
   } else if constexpr (!GT) {
     const int wt = w - 1;
+    const int nslot = ntile > wt ? (ntile - wt + REJECT_T_TW - 1) / REJECT_T_TW : 0;
     rd4 tr[REJECT_T_TPW];
-    // coordinates of this wavefront's tiles, four bits each of J and L, four
-    // tiles per word (scalar registers)
+    // (J, L) of this wavefront's slots, four bits each, four slots per word
+    // (scalar registers); slots past the last tile name tile (0, 0)
     unsigned pk[(REJECT_T_TPW + 3) / 4];
     {
 #pragma unroll
       for (int q = 0; q < (REJECT_T_TPW + 3) / 4; ++q) pk[q] = 0;
-      int J = 0, L = wt;
+      int L = 0, off = wt;   // tile wt + 7 k: (L + off, L)
 #pragma unroll
       for (int k = 0; k < REJECT_T_TPW; ++k) {
-        tile_advance(J, L);
-        pk[k / 4] |= (unsigned)((J & 15) | ((L & 15) << 4)) << (8 * (k % 4));
-        L += REJECT_T_TW;
+        while (L < nbk && off >= nbk - L) {
+          off -= nbk - L;
+          ++L;
+        }
+        if (k < nslot) pk[k / 4] |= (unsigned)(((L + off) & 15) | ((L & 15) << 4)) << (8 * (k % 4));
+        off += REJECT_T_TW;
       }
     }
-    // f(k, J, L) for each tile k of this wavefront
-    auto for_tiles = [&](auto f) __attribute__((always_inline)) {
+    // f(k, J, L) for the slots k in [lo, hi), lo <= hi (a bit mask of the
+    // range: a comparison with a single slot index would let the compiler
+    // index the tile registers dynamically, which puts them in scratch)
+    auto for_slots = [&](int lo, int hi, auto f) __attribute__((always_inline)) {
+      const unsigned sel = ((1u << hi) - 1u) ^ ((1u << lo) - 1u);
 #pragma unroll
       for (int k = 0; k < REJECT_T_TPW; ++k) {
-        if (wt + REJECT_T_TW * k < ntile) {
+        if ((sel >> k) & 1u) {
           const unsigned e = pk[k / 4] >> (8 * (k % 4));
           f(k, (int)(e & 15), (int)((e >> 4) & 15));
         }
@@ -752,58 +814,67 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
     // this wavefront's tiles of H (zero padding), read along rows of the
     // symmetric H so that a load instruction covers four 128-byte runs; the
     // loads are unconditional (clamped indices) so that all stay in flight
+    lds_sync();   // (P)
 #pragma unroll
-    for (int k = 0; k < REJECT_T_TPW; ++k) tr[k] = rd4{0.0, 0.0, 0.0, 0.0};
-    for_tiles([&](int k, int J, int L) {
+    for (int k = 0; k < REJECT_T_TPW; ++k) {
+      const unsigned e = pk[k / 4] >> (8 * (k % 4));
+      const int J = (int)(e & 15), L = (int)((e >> 4) & 15);
       const int col = RT * L + l16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = RT * J + g + 4 * i;
         tr[k][i] = H[(int64_t)(row < b ? row : b - 1) * b + (col < b ? col : b - 1)];
       }
-    });
-    for_tiles([&](int k, int J, int L) {
+    }
+    // the counter-based uniforms V_i of the tests, while the loads are in flight
+    if (!keep_all && !un.U)
+      for (int i = tid - 64; i < b; i += REJECT_T_THREADS - 64)
+        sm.uv[i] = philox_uniform(un.seed, (uint64_t)(2 * (int64_t)b * round + b + i));
+    lds_sync();   // (0)
+    // zero padding (after (0): block 0's tests need no tile, so they start
+    // while these loads are in flight)
+    for_slots(0, nslot, [&](int k, int J, int L) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         if (RT * J + g + 4 * i >= b || RT * L + l16 >= b) tr[k][i] = 0.0;
     });
-    // T(J, L) -= P_J P_L^T for the tiles selected by pick(J, L), four k-steps
-    // of four columns (rejected columns of P are zero), P the previous block's
-    // solved panel; a tile's eight operands are read before its products
-    auto update2 = [&](double(*P)[QS], auto pick) __attribute__((always_inline)) {
-      for_tiles([&](int k, int J, int L) {
-        if (__builtin_expect(pick(J, L), 0)) {
-          double av[4], bv[4];
+    // T(J, L) -= P_J P_L^T for the slots in [lo, hi), four k-steps of four
+    // columns (rejected columns of P are zero), P the previous block's solved
+    // panel; a tile's eight operands are read before its products
+    auto update = [&](double(*P)[QS], int lo, int hi) __attribute__((always_inline)) {
+      for_slots(lo, hi, [&](int k, int J, int L) {
+        double av[4], bv[4];
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            av[ks] = P[RT * J + l16][4 * ks + g];
-            bv[ks] = P[RT * L + l16][4 * ks + g];
-          }
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) tr[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ks], bv[ks], tr[k], 0, 0, 0);
+        for (int ks = 0; ks < 4; ++ks) {
+          av[ks] = P[RT * J + l16][4 * ks + g];
+          bv[ks] = P[RT * L + l16][4 * ks + g];
         }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) tr[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ks], bv[ks], tr[k], 0, 0, 0);
       });
     };
-    // tiles selected by pick(J, L) into the rows of block J of the buffer
-    auto copy_to = [&](double(*Qd)[QS], auto pick) __attribute__((always_inline)) {
-      for_tiles([&](int k, int J, int L) {
-        if (__builtin_expect(pick(J, L), 0))
+    // the slots in [lo, hi) into the rows of their block J of the buffer
+    auto copy_to = [&](double(*Qd)[QS], int lo, int hi) __attribute__((always_inline)) {
+      for_slots(lo, hi, [&](int k, int J, int L) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) Qd[RT * J + g + 4 * i][l16] = tr[k][i];
+        for (int i = 0; i < 4; ++i) Qd[RT * J + g + 4 * i][l16] = tr[k][i];
       });
     };
     // panel rows J >= Jlo of block Ip (spread: row J to tile wavefront
-    // (J - Jlo) mod 7; else row Jlo only, by the caller): P_J = Q_J X^T from the copy of block column Ip, in place, and the
-    // accepted columns into H.  A loop over J, not over this wavefront's tiles
-    // (it touches no tile registers).
+    // (J - Jlo) mod 7; else row Jlo only, by the caller): P_J = Q_J X^T from
+    // the copy of block column Ip, in place, and the accepted columns into H
     auto panel = [&](double(*Qs)[QS], const double* X, int Ip, int Jlo, bool spread) __attribute__((always_inline)) {
-      const int j0 = spread ? Jlo + wt : Jlo, je = spread ? nbk : Jlo + 1;
-      for (int J = j0; J < je; J += REJECT_T_TW) {
+      const int jb = spread ? Jlo + wt : Jlo, je = spread ? nbk : Jlo + 1;
+      for (int J = jb; J < je; J += REJECT_T_TW) {
+        double av[4], xv[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          av[ks] = Qs[RT * J + l16][4 * ks + g];
+          xv[ks] = X[l16 * RT + 4 * ks + g];
+        }
         rd4 pj = rd4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-          pj = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[RT * J + l16][4 * ks + g], X[l16 * RT + 4 * ks + g], pj, 0,
-                                                    0, 0);
+        for (int ks = 0; ks < 4; ++ks) pj = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], xv[ks], pj, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) Qs[RT * J + g + 4 * i][l16] = pj[i];
         if (RT * Ip + l16 < b)
@@ -816,36 +887,51 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
     };
     // Look-ahead: the panel and the rank-16 update of block I - 1 run during
     // block I.  Before the tests of block I only the panel row P_I and the
-    // diagonal tile (I, I) are computed (by that tile's owner); the rest of
-    // the panel runs beside the first half of the tests and the rest of the
-    // update beside the second half, the block's outputs and its inverse
-    // factor (wavefront 0 takes the barrier (m) between them inside its test
-    // loop).
+    // diagonal tile (I, I) are computed, by that tile's owner (the first
+    // tile of block column I); the rest of the panel runs beside the first
+    // half of the tests and the rest of the update beside the second half,
+    // the block's outputs and its inverse factor (wavefront 0 takes the
+    // barrier (m) between them inside its test loop).
     int pmask = 0;   // accepted columns of the previous block (panel and update pending)
     for (int I = 0; I < nbk && nacc < cap; ++I) {
-      double(*Qb)[QS] = Q[I & 1];
-      double(*Qp)[QS] = Q[(I + 1) & 1];         // block column I - 1, becoming its panel
-      const double* Xp = XB + ((I + 1) & 1) * RT * RT;   // X of block I - 1
-      if (pmask) {
-        // panel row I of block I - 1 (P_I = Q_I X^T), by the owner of the
-        // diagonal tile (I, I), which then updates that tile with it (its own
-        // LDS writes are ordered before its reads); the other waves read P_I
-        // only after (m)
-        if ((I * (I + 1) / 2 + I) % REJECT_T_TW == wt) {
-          panel(Qp, Xp, I - 1, I, false);
-          update2(Qp, [&](int J, int L) { return J == I && L == I; });
+      double(*Qb)[QS] = sm.Q[I & 1];
+      double(*Qp)[QS] = sm.Q[(I + 1) & 1];         // block column I - 1, becoming its panel
+      const double* Xp = sm.XB[(I + 1) & 1];       // X of block I - 1
+      // slots of block columns >= I start at k0, those of block column I end
+      // before k2; the diagonal tile (I, I) is tile T0(I)
+      const int T0 = I * nbk - I * (I - 1) / 2, T1 = T0 + nbk - I;
+      const int k0 = T0 > wt ? (T0 - wt + REJECT_T_TW - 1) / REJECT_T_TW : 0;
+      const int k2 = T1 > wt ? (T1 - wt + REJECT_T_TW - 1) / REJECT_T_TW : 0;
+      const bool own = T0 % REJECT_T_TW == wt;
+      const int k1 = own ? k0 + 1 : k0;
+      if (I > 0) {
+        if (own) {
+          // panel row I of block I - 1 and the diagonal tile's update with
+          // it (this wavefront's own LDS writes are ordered before its
+          // reads); the other waves read P_I only after (m)
+          if (pmask) panel(Qp, Xp, I - 1, I, false);
+          // update and copy in one pass over the slot (two separate
+          // conditional passes over the same tile spill the tile registers)
+          for_slots(k0, k0 + 1, [&](int k, int J, int L) {
+            if (pmask) {
+              double av[4];
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) av[ks] = Qp[RT * I + l16][4 * ks + g];
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) tr[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ks], av[ks], tr[k], 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Qb[RT * I + g + 4 * i][l16] = tr[k][i];
+          });
         }
+        lds_sync();   // (1)
       }
-      copy_to(Qb, [&](int J, int L) { return J == I && L == I; });
-      lds_sync();   // (1)
-      if (pmask) {
-        panel(Qp, Xp, I - 1, I + 1, true);
-        lds_sync();   // (m)
-        update2(Qp, [&](int J, int L) { return L >= I && !(J == I && L == I); });
-      }
-      copy_to(Qb, [&](int J, int L) { return L == I && J > I; });
+      if (pmask) panel(Qp, Xp, I - 1, I + 1, true);
+      lds_sync();   // (m)
+      if (pmask) update(Qp, k1, nslot);
+      copy_to(Qb, k1, k2);
       lds_sync();   // (2)
-      const int mask = bmask;
+      const int mask = sm.bmask;
       pmask = mask;
       if (mask == 0) continue;
       nacc += __popc(mask);
@@ -899,10 +985,15 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
     };
     constexpr int NB1 = (REJECT_G_BMAX / RT + REJECT_T_TW - 1) / REJECT_T_TW;   // tiles of a block column per wavefront
     constexpr int NB = 8;                                                       // tiles in flight in the update
+    lds_sync();   // (P)
+    if (!keep_all && !un.U)
+      for (int i = tid - 64; i < b; i += REJECT_T_THREADS - 64)
+        sm.uv[i] = philox_uniform(un.seed, (uint64_t)(2 * (int64_t)b * round + b + i));
+    lds_sync();   // (0)
     int pmask = 0;
     for (int I = 0; I < nbk && nacc < cap; ++I) {
-      double(*Qb)[QS] = Q[I & 1];
-      double(*Qp)[QS] = Q[(I + 1) & 1];
+      double(*Qb)[QS] = sm.Q[I & 1];
+      double(*Qp)[QS] = sm.Q[(I + 1) & 1];
       // 1. block column I (tiles (J, I), J >= I) with the pending update, to LDS
       {
         rd4 t[NB1];
@@ -925,44 +1016,64 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
       __syncthreads();   // (1)
       // 2. the rest of the pending update, beside the tests: the trailing
       // tiles (J, L), J >= L > I, numbered down the block columns, tile q to
-      // tile wavefront q mod 7, eight loads in flight
+      // tile wavefront q mod 7, in batches of NB; the loads of the next batch
+      // are issued before the products and stores of this one (two register
+      // sets; loads past the last tile are clamped into the matrix and their
+      // values dropped)
       if (pmask) {
         const int nt = nbk - I - 1, m = nt * (nt + 1) / 2;
-        int L = I + 1, off = wt;   // tile q: (L + off, L)
-        for (int q = wt; q < m; q += REJECT_T_TW * NB) {
-          int Js[NB], Ls[NB];
-          rd4 t[NB];
+        int L = I + 1, off = wt;   // the next tile: (L + off, L)
+        // (J, L) of the next tile, packed J | L << 8
+        auto next = [&]() __attribute__((always_inline)) {
+          while (off >= nbk - L && L < nbk - 1) {
+            off -= nbk - L;
+            ++L;
+          }
+          const int J = L + off < nbk ? L + off : nbk - 1;
+          off += REJECT_T_TW;
+          return J | (L << 8);
+        };
+        auto load_batch = [&](rd4 (&t)[NB], int (&jl)[NB]) __attribute__((always_inline)) {
 #pragma unroll
           for (int n = 0; n < NB; ++n) {
-            while (off >= nbk - L && L < nbk - 1) {
-              off -= nbk - L;
-              ++L;
-            }
-            Js[n] = L + off < nbk ? L + off : nbk - 1;
-            Ls[n] = L;
-            t[n] = tload(Js[n], Ls[n]);
-            off += REJECT_T_TW;
+            jl[n] = next();
+            t[n] = tload(jl[n] & 255, jl[n] >> 8);
           }
+        };
+        auto apply_batch = [&](rd4 (&t)[NB], const int (&jl)[NB], int q0) __attribute__((always_inline)) {
 #pragma unroll
           for (int n = 0; n < NB; ++n) {
-            if (q + REJECT_T_TW * n < m) {
-              tpad(t[n], Js[n], Ls[n]);
-              tstore(tupd(t[n], Qp, Js[n], Ls[n]), Js[n], Ls[n]);
+            if (q0 + REJECT_T_TW * n < m) {
+              const int J = jl[n] & 255, L2 = jl[n] >> 8;
+              tpad(t[n], J, L2);
+              tstore(tupd(t[n], Qp, J, L2), J, L2);
             }
           }
+        };
+        rd4 ta[NB], tb[NB];
+        int ja[NB], jb[NB];
+        if (wt < m) load_batch(ta, ja);
+        for (int q = wt; q < m; q += 2 * REJECT_T_TW * NB) {
+          const bool more = q + REJECT_T_TW * NB < m;
+          if (more) load_batch(tb, jb);
+          apply_batch(ta, ja, q);
+          if (!more) break;
+          if (q + 2 * REJECT_T_TW * NB < m) load_batch(ta, ja);
+          apply_batch(tb, jb, q + REJECT_T_TW * NB);
         }
       }
       __syncthreads();   // (2)
-      const int mask = bmask;
+      const int mask = sm.bmask;
       pmask = mask;
       if (mask == 0) continue;
       // 3. the panel below the block, as in the register-resident form
+      const double* X = sm.XB[I & 1];
       for (int J = I + 1 + wt; J < nbk; J += REJECT_T_TW) {
         double av[4], bv[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           av[ks] = Qb[RT * J + l16][4 * ks + g];
-          bv[ks] = BC[l16][4 * ks + g];
+          bv[ks] = X[l16 * RT + 4 * ks + g];
         }
         rd4 pj = rd4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -982,8 +1093,8 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
   }
   __syncthreads();
   for (int a = tid; a < nacc; a += REJECT_T_THREADS) {
-    const int64_t pv = props[accl[a]];
-    acc_out[a] = accl[a];
+    const int64_t pv = props[sm.accl[a]];
+    acc_out[a] = sm.accl[a];
     pivots[kr + a] = pv;
     u[pv] = 0.0;
   }
