@@ -175,7 +175,11 @@ void fill_stats(const arpc_problem& p, const Layout& l, const RoundState& h, con
   // k_r columns at the contraction precision, the points, G written once to
   // F at its storage precision, the row norm; the two-kernel path also writes
   // C (update GEMM) and reads it (solve).  The write of G into the blocked
-  // copy (which the next rounds contract over) is counted apart.
+  // copy (which the next rounds contract over) is counted apart.  What the
+  // two-kernel update GEMM reads for the kernel columns: the points in FP64
+  // (epilogue from the coordinates), the e4m3 codes and a squared norm
+  // (epilogue on the FP8 matrix cores), or the precomputed columns (s_r
+  // values per row at the storage precision).
   double kr = 0.0, fg = 0.0, ft = 0.0, bg = 0.0, bt = 0.0, bb = 0.0;
   const double es = (double)elem_size(p.prec);
   const double eb = p.prec == ARPC_FP64 ? 8.0 : (gemm_prec(p.prec) == ARPC_BF16 ? 2.0 : 4.0);
@@ -188,7 +192,8 @@ void fill_stats(const arpc_problem& p, const Layout& l, const RoundState& h, con
       if (fused) {
         bg += (double)N * (kr * eb + 8.0 * (double)p.d + sr * es + 8.0);
       } else {
-        bg += (double)N * (kr * eb + sr * eb + 8.0 * (double)p.d);
+        const double kc = l.dist8 ? (double)p.d + 4.0 : (l.dist ? sr * es : 8.0 * (double)p.d);
+        bg += (double)N * (kr * eb + sr * eb + kc);
         bt += (double)N * (sr * (eb + es) + 8.0);
       }
       if (!l.valu) bb += (double)N * sr * eb;

@@ -148,6 +148,35 @@ __device__ inline void store_blk(typename Pol::S* __restrict__ base, int64_t row
   }
 }
 
+// Store 16 bytes' worth of consecutive columns k .. k + 16 / sizeof(S) - 1
+// of one row into the blocked layout (k a multiple of that count, so the piece
+// lies in one chunk and is 16-byte aligned), split into BF16 planes if needed.
+template <class Pol>
+__device__ inline void store_piece(typename Pol::S* __restrict__ base, int64_t row, int64_t k, int64_t nkc,
+                                   const typename Pol::T* v) {
+  using S = typename Pol::S;
+  if constexpr (sizeof(S) == 2) {
+    bf8 hi, lo;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if constexpr (Pol::SPLANES == 2) {
+        __bf16 h, l;
+        split_bf16((float)v[j], h, l);
+        hi[j] = h;
+        lo[j] = l;
+      } else {
+        hi[j] = (__bf16)v[j];
+      }
+    }
+    *(bf8*)(base + blk_offset<Pol>(row, k, nkc, 0)) = hi;
+    if constexpr (Pol::SPLANES == 2) *(bf8*)(base + blk_offset<Pol>(row, k, nkc, 1)) = lo;
+  } else {
+    u4 w;
+    __builtin_memcpy(&w, v, 16);
+    *(u4*)(base + blk_offset<Pol>(row, k, nkc, 0)) = w;
+  }
+}
+
 // One lane's slice of the N-row operand for one chunk and one 16-row tile.
 template <class Pol>
 struct Frag;
@@ -391,16 +420,31 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
     constexpr size_t EBYTES = (size_t)(WROWS + 1) * EPI_CB * 16 * sizeof(T);
     static_assert(64 * (256 + 4) <= EBYTES, "staged rows fit the epilogue window");
     unsigned* rowsL = (unsigned*)(lds + (size_t)w * EBYTES);
-    for (int q = lane; q < 64 * parts; q += 64) {
-      const int r = q / parts, pc = q % parts;
-      int64_t rr = row_w + r;
-      if (rr >= N) rr = N - 1;
-      const u4 v = *(const u4*)(a.X8 + (size_t)rr * dd + 16 * pc);
-      unsigned* dst = rowsL + (r * RS + 16 * pc) / 4;
-      dst[0] = v[0];
-      dst[1] = v[1];
-      dst[2] = v[2];
-      dst[3] = v[3];
+    // 16-byte pieces, eight loads in flight per lane (a loop with one load
+    // per iteration would wait out the latency of each)
+    for (int q0 = 0; q0 < 64 * parts; q0 += 64 * 8) {
+      u4 v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int q = q0 + 64 * j + lane;
+        const int qc = q < 64 * parts ? q : 64 * parts - 1;
+        const int r = qc / parts, pc = qc % parts;
+        int64_t rr = row_w + r;
+        if (rr >= N) rr = N - 1;
+        v[j] = *(const u4*)(a.X8 + (size_t)rr * dd + 16 * pc);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int q = q0 + 64 * j + lane;
+        if (q < 64 * parts) {
+          const int r = q / parts, pc = q % parts;
+          unsigned* dst = rowsL + (r * RS + 16 * pc) / 4;
+          dst[0] = v[j][0];
+          dst[1] = v[j][1];
+          dst[2] = v[j][2];
+          dst[3] = v[j][3];
+        }
+      }
     }
     float xn[NB];
 #pragma unroll
@@ -409,30 +453,56 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
       xn[nb] = a.xn8[rr < N ? rr : N - 1];
     }
     const float frac = 0x1p-6f;
+    // The A operand (accepted points' codes) of a column block for all its
+    // 32-wide steps (at most 8 at d <= 256) in registers, the next block's
+    // loaded while this one's products run.  A lane's 8 dims are all inside
+    // d or all past it (d % 16 == 0); past it both operands are zero.
+    constexpr int KS = 8;
+    auto load_ap = [&](long (&ap)[KS], int cb) __attribute__((always_inline)) {
+      const int cl = 16 * (cb0 + cb) + l16;                   // A operand: column of this lane
+      const unsigned char* xa = a.Xp8 + (size_t)(cl < s ? cl : s - 1) * dd + 8 * g;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) ap[kk] = (32 * kk + 8 * g < dd) ? *(const long*)(xa + 32 * kk) : 0l;
+    };
+    constexpr bool APN = NCB <= 5;   // registers for the next block's operand
+    // squared norms of this lane's four columns of a block
+    auto load_y = [&](float (&y)[4], int cb) __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * (cb0 + cb) + 4 * g + i;
+        y[i] = a.ypn[c < s ? c : s - 1];
+      }
+    };
+    long apc[KS], apn[KS];
+    float yc[4];
+    load_ap(apc, 0);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       if (cb < ncb) {   // uniform
-        const int cl = 16 * (cb0 + cb) + l16;                 // A operand: column of this lane
-        const unsigned char* xa = a.Xp8 + (size_t)(cl < s ? cl : s - 1) * dd + 8 * g;
+        // this block's norms, their latency covered by its products
+        load_y(yc, cb);
+        if (!APN && cb > 0) load_ap(apc, cb);
+        if (APN && cb + 1 < ncb) load_ap(apn, cb + 1);
         f4 dp[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) dp[nb] = f4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < dd; k0 += 32) {
-          // a lane's 8 dims are all inside d or all past it (d % 16 == 0);
-          // past it both operands are zero
-          const bool in = k0 + 8 * g < dd;
-          const long ap = in ? *(const long*)(xa + k0) : 0l;
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const unsigned* src = rowsL + ((16 * nb + l16) * RS + k0 + 8 * g) / 4;
-            const long bp = in ? (long)((unsigned long)src[0] | ((unsigned long)src[1] << 32)) : 0l;
-            dp[nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ap, bp, dp[nb], 0, 0, 0);
+        for (int kk = 0; kk < KS; ++kk) {
+          const int k0 = 32 * kk;
+          if (k0 < dd) {   // uniform
+            const bool in = k0 + 8 * g < dd;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              const unsigned* src = rowsL + ((16 * nb + l16) * RS + k0 + 8 * g) / 4;
+              const long bp = in ? (long)((unsigned long)src[0] | ((unsigned long)src[1] << 32)) : 0l;
+              dp[nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(apc[kk], bp, dp[nb], 0, 0, 0);
+            }
           }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int c = 16 * (cb0 + cb) + 4 * g + i;
-          const float y = a.ypn[c < s ? c : s - 1];
+          const float y = yc[i];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int64_t rr = row_w + 16 * nb + l16;
@@ -441,6 +511,11 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
               r2 = (float)sqdist(a.X + (rr < N ? rr : N - 1) * dd, a.Xp + (int64_t)(c < s ? c : s - 1) * dd, dd);
             acc[nb][cb][i] = kappa_fast(r2 > 0.f ? r2 : 0.f, a.kf) - acc[nb][cb][i];
           }
+        }
+        // the next block's operands become the current ones (after their last use)
+        if constexpr (APN) {
+#pragma unroll
+          for (int kk = 0; kk < KS; ++kk) apc[kk] = apn[kk];
         }
       }
     }
@@ -535,14 +610,37 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
       }
     }
     __syncthreads();
-    // C
+    // C: 16-byte pieces on the piece grid of the blocked layout (a lane
+    // per piece, several pieces in flight); a piece that the window covers
+    // only in part is written element by element, since its other columns
+    // belong to another window or workgroup
     int wend = chi - w0;
     if (wend > 16 * EPI_CB) wend = 16 * EPI_CB;
-    if (lane < wend) {
-      for (int rl = 0; rl < WROWS; ++rl) {
-        if (row_w + rl >= N) break;
-        const T v = (lane < wv) ? E[lane * EROW + rl] : (T)0;
-        store_blk<Pol>(ob, row_w + rl, cshift + w0 + lane, a.nkc_out, v);
+    {
+      constexpr int PE = 16 / (int)sizeof(S);
+      const int64_t a0 = cshift + w0;                    // blocked column of window column 0
+      const int64_t p0 = a0 / PE * PE;                   // first piece
+      const int npc = (int)((a0 + wend - p0 + PE - 1) / PE);
+#pragma unroll 4
+      for (int q = lane; q < WROWS * npc; q += 64) {
+        const int rl = q / npc, pc = q % npc;
+        const int64_t rw = row_w + rl;
+        if (rw < N) {
+          const int c0 = (int)(p0 + (int64_t)pc * PE - a0);   // window column of the piece's first element
+          T v[PE];
+#pragma unroll
+          for (int j = 0; j < PE; ++j) {
+            const int cc = c0 + j;
+            v[j] = (cc >= 0 && cc < wv) ? E[cc * EROW + rl] : (T)0;
+          }
+          if (c0 >= 0 && c0 + PE <= wend) {
+            store_piece<Pol>(ob, rw, a0 + c0, a.nkc_out, v);
+          } else {
+#pragma unroll
+            for (int j = 0; j < PE; ++j)
+              if (c0 + j >= 0 && c0 + j < wend) store_blk<Pol>(ob, rw, a0 + c0 + j, a.nkc_out, v[j]);
+          }
+        }
       }
     }
     __syncthreads();

@@ -147,6 +147,21 @@ def test_identity_matrix_exact_large_block(b):
     assert np.array_equal(F, np.eye(N)[:, want])
 
 
+@pytest.mark.parametrize("b", [200, 256])
+def test_identity_matrix_exact_register_block(b):
+    """A = I on 512 points with blocks of the register-resident form: most
+    rounds propose some point twice inside one 16-proposal block and across
+    blocks, and the last rounds draw from a few remaining points, so the
+    duplicate search sees long runs of repeats."""
+    X = W.grid(3, levels=8)
+    N = X.shape[0]
+    prob = W.Problem(N=N, d=3, k=480, b=b, kernel=W.GAUSSIAN, sigma=1.0, seed=17)
+    F, piv, out = gpu_factor(X, prob)
+    want = simulate_identity(N, prob.k, prob.b, philox_stream(prob.seed))
+    assert list(piv) == want
+    assert np.array_equal(F, np.eye(N)[:, want])
+
+
 def test_lds_limit_block_size():
     rng = np.random.default_rng(3)
     X = rng.standard_normal((3000, 4))
