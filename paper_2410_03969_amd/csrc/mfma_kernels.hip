@@ -446,6 +446,13 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
         }
       }
     }
+    // zero codes in each row's pad and (d < 256) in the 256 bytes after the
+    // last row: the steps below read up to 256 bytes from a row's start in
+    // every lane and zero the A operand past d, so what a lane reads past d
+    // must be a finite code (a NaN code would survive the zero operand);
+    // 64 (d + 4) + 256 <= 16640 bytes for d <= 248
+    rowsL[(lane * RS + dd) / 4] = 0u;
+    if (dd < 256) rowsL[(64 * RS) / 4 + lane] = 0u;
     float xn[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -465,6 +472,11 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
       for (int kk = 0; kk < KS; ++kk) ap[kk] = (32 * kk + 8 * g < dd) ? *(const long*)(xa + 32 * kk) : 0l;
     };
     constexpr bool APN = NCB <= 5;   // registers for the next block's operand
+    // this lane's staged bytes 8 g .. of its rows 16 nb + l16 (a 32-wide step
+    // is a constant offset from here)
+    const unsigned* rowp[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) rowp[nb] = rowsL + ((16 * nb + l16) * RS + 8 * g) / 4;
     // squared norms of this lane's four columns of a block
     auto load_y = [&](float (&y)[4], int cb) __attribute__((always_inline)) {
 #pragma unroll
@@ -486,17 +498,16 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
         f4 dp[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) dp[nb] = f4{0.f, 0.f, 0.f, 0.f};
+        // all eight steps, straight-line (a guard per step would split the
+        // accumulators across blocks); past d the A operand is zero and the
+        // B bytes are finite codes, so those products add exactly zero
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
-          const int k0 = 32 * kk;
-          if (k0 < dd) {   // uniform
-            const bool in = k0 + 8 * g < dd;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-              const unsigned* src = rowsL + ((16 * nb + l16) * RS + k0 + 8 * g) / 4;
-              const long bp = in ? (long)((unsigned long)src[0] | ((unsigned long)src[1] << 32)) : 0l;
-              dp[nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(apc[kk], bp, dp[nb], 0, 0, 0);
-            }
+          for (int nb = 0; nb < NB; ++nb) {
+            const unsigned* src = rowp[nb] + 8 * kk;
+            const long bp = (long)((unsigned long)src[0] | ((unsigned long)src[1] << 32));
+            dp[nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(apc[kk], bp, dp[nb], 0, 0, 0);
           }
         }
 #pragma unroll
