@@ -105,7 +105,9 @@ Layout layout_of(const arpc_problem& p) {
   l.Bt2 = take(valu ? es * p.b * p.b : 0);
   l.Bm1 = take(mb);
   l.Bm2 = take(mb);
-  l.Fb = take(valu ? 0 : mfma_blocked_bytes(gp, p.N, p.k));
+  // the blocked copy of F: the BF16 modes contract over it; FP64 and FP32 read F itself
+  l.fblk = !valu && gp != ARPC_FP64 && gp != ARPC_FP32;
+  l.Fb = take(l.fblk ? mfma_blocked_bytes(gp, p.N, p.k) : 0);
   l.C = take(valu ? es * p.N * p.b : (fused ? 0 : mfma_blocked_bytes(gp, p.N, p.b)));
   l.dist = !valu && !fused && (mfma_dist_contraction((int)p.d) || p.prec == ARPC_FP8);
   l.dist8 = l.dist && p.prec == ARPC_FP8 && p.d % 4 == 0 && mfma_dist_in_epilogue((int)p.d);
@@ -196,7 +198,7 @@ void fill_stats(const arpc_problem& p, const Layout& l, const RoundState& h, con
         bg += (double)N * (kr * eb + sr * eb + kc);
         bt += (double)N * (sr * (eb + es) + 8.0);
       }
-      if (!l.valu) bb += (double)N * sr * eb;
+      if (l.fblk) bb += (double)N * sr * eb;
     }
     kr += sr;
   }
@@ -303,7 +305,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
     launch_trsm<T>(s, C, N, Bt2, b, F, P, st);
     prof.end();
   } else {
-    MfmaRound mr{F, ws + l.Fb, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
+    MfmaRound mr{F, l.fblk ? (void*)(ws + l.Fb) : nullptr, C, N, X, d, Xp, kp, (unsigned char*)(ws + l.Bm1), (unsigned char*)(ws + l.Bm2),
                  (int)((b + 15) / 16 * 16), P, Fs, k, acc, H, b, k,
                  l.dist && !l.dist8 ? (void*)(ws + l.C0) : nullptr,
                  l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr,

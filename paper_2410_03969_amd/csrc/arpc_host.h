@@ -25,6 +25,7 @@ struct Layout {
                 // (the accepted points as codes in Xp8 with norms ypn; no C0)
   int part_cols;
   bool valu;  // vector-unit GEMM kernels instead of the matrix-core ones
+  bool fblk;  // a panel-blocked copy of F (BF16 modes; FP64 and FP32 read F itself)
   int ncbt;   // > 0: one-kernel round product with this column-block count
   int grid;   // persistent workgroups of that kernel (set per call)
 };

@@ -12,7 +12,7 @@ constexpr int PH = 256;
 // update GEMM and triangular solve.
 struct MfmaRound {
   void* F;                 // N x k column-major output factor (storage per mode)
-  void* Fb;                // the same factor in the panel-blocked layout
+  void* Fb;                // the same factor in the panel-blocked layout (BF16 modes), or null
   void* C;                 // panel-blocked scratch for A(:,S_r) - F F(S_r,:)^T (N x b)
   int64_t N;
   const double* X;         // N x d points

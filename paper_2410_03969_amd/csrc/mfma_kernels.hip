@@ -6,10 +6,12 @@
 //
 // Both are computed transposed, C^T = Bm * F^T: the N-row operand (F, or C)
 // is the MFMA B operand and the small per-round operand Bm (F(S_r,:)^T, or
-// Linv) the A operand.  The N-row operands are kept in a panel-blocked copy
-// (see blk_offset) in which a lane's contraction values for one row are
-// adjacent, so each lane fetches them with 16-byte loads straight from HBM
-// into registers, double-buffered one chunk ahead.  Bm is pre-arranged in
+// Linv) the A operand.  The BF16 modes keep the N-row operands in a
+// panel-blocked copy (see blk_offset) in which a lane's contraction values for
+// one row are adjacent, so each lane fetches them with 16-byte loads straight
+// from HBM into registers, double-buffered one chunk ahead.  The FP64 and FP32
+// products, bound by the matrix cores, read F itself (column-major): a load
+// then covers 16 rows of four columns, and no second copy of F is kept.  Bm is pre-arranged in
 // contraction chunks and staged through LDS once per workgroup, double-
 // buffered and shared by the four wavefronts.  Each wavefront owns 16*NB rows
 // and all columns of its column group, so F is read from HBM once per round
@@ -100,7 +102,8 @@ __host__ __device__ inline size_t blk_offset(int64_t row, int64_t k, int64_t nkc
 
 // Arguments of one panel product.
 struct PanelArgs {
-  const void* Bsrc;    // F (colgemm) or C (trsm), panel-blocked
+  const void* Bsrc;    // colgemm: F itself (FP64, FP32; column-major, ld N) or its panel-blocked
+                       // copy (BF16 modes); trsm: C, panel-blocked
   int64_t nkc_src;     // contraction chunks per panel of Bsrc
   int64_t N;
   const unsigned char* Bm;  // chunked small operand (see chunk_offset)
@@ -110,7 +113,7 @@ struct PanelArgs {
   const double* Xp;    // accepted points, s x d
   KParams kp;
   void* out_user;      // F, column-major, ld N (trsm only)
-  void* out_blk;       // C (colgemm) or F (trsm), panel-blocked
+  void* out_blk;       // C (colgemm) or the blocked copy of F (trsm; null in FP64 and FP32), panel-blocked
   int64_t nkc_out;     // contraction chunks per panel of out_blk
   double* P;           // partial row norms (trsm), groups x N
   const RoundState* st;
@@ -305,6 +308,25 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
   constexpr size_t PLANE_ELEMS = (size_t)PH * Pol::KC;
   using F = Frag<Pol>;
   auto load = [&](F (&f)[NB], int64_t ch) {
+    if constexpr (Pol::KC == 16 && MODE == MODE_COLGEMM) {
+      // FP64 and FP32: F itself, column-major (ld N).  Lane (g, l16) takes
+      // columns 16 ch + 4 g .. + 3 of its rows: each load covers 16
+      // consecutive rows of four columns (four 128-byte runs in FP64).
+      // Columns past k_r are zero (the caller's F holds anything there);
+      // rows past N read row N - 1 and feed only outputs that are never stored.
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        int64_t r = myrow + 16 * nb;
+        if (r >= N) r = N - 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t k = ch * Pol::KC + 4 * g + i;
+          const T v = Bsrc[(size_t)(k < K ? k : K - 1) * N + r];
+          f[nb].v[i] = k < K ? v : (T)0;
+        }
+      }
+      return;
+    }
     const S* p = rowbase + (size_t)ch * CHUNK_ELEMS;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -627,7 +649,7 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
     // belong to another window or workgroup
     int wend = chi - w0;
     if (wend > 16 * EPI_CB) wend = 16 * EPI_CB;
-    {
+    if (ob) {   // the solve of the FP64 and FP32 modes keeps no blocked copy of F
       constexpr int PE = 16 / (int)sizeof(S);
       const int64_t a0 = cshift + w0;                    // blocked column of window column 0
       const int64_t p0 = a0 / PE * PE;                   // first piece
@@ -1176,7 +1198,8 @@ static void launch_panel(hipStream_t s, const MfmaRound& r, const RoundState* st
   const unsigned nblocks = (unsigned)((npanels + 7) / 8) * 8u * (unsigned)ngroups;
   const int64_t nkcF = (r.kmax + Pol::KC - 1) / Pol::KC, nkcC = (r.b + Pol::KC - 1) / Pol::KC;
   if (which == 0) {
-    PanelArgs a1{r.Fb, nkcF, r.N, r.Bm1, r.Ctot, r.X, r.d, r.Xp, r.kp, nullptr, r.C, nkcC, nullptr, st,
+    // FP64 and FP32 contract over F itself (column-major), the BF16 modes over its blocked copy
+    PanelArgs a1{Pol::KC == 16 ? r.F : r.Fb, nkcF, r.N, r.Bm1, r.Ctot, r.X, r.d, r.Xp, r.kp, nullptr, r.C, nkcC, nullptr, st,
                  npanels, ngroups, r.C0, (const unsigned char*)r.X8, r.xn8, r.Xp8, r.ypn, kfast_of(r.kp)};
     if constexpr (std::is_same<Pol, PolBF<1>>::value) {
       if (r.Xp8) {
