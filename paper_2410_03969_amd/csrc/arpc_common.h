@@ -328,6 +328,70 @@ __device__ inline void linv_column(const LFactor& L, int s, int c, int lane, dou
   }
 }
 
+// Largest b whose RejectionSampleSubmatrix runs in the tiled form, which also
+// leaves the inverses of its 16 x 16 diagonal blocks in H (see linv_blocks).
+constexpr int REJECT_TILED_BMAX = 512;
+
+// Column c of the inverse of the accepted factor L(T,T) (s x s), in proposal
+// indexing: x[q] = (L(T,T)^{-1})(i, c) at q = acc[i], zero at every proposal
+// that was not accepted.  Block forward substitution over the 16-proposal
+// blocks of the tiled RejectionSampleSubmatrix, which leaves in H the factor
+// columns (lower triangle, proposal indexing, columns of rejected proposals
+// zero) and, in the upper triangle of each diagonal block J, the strictly
+// lower part of the inverse X_J of that block's accepted factor (X_J(r, q) at
+// H[(16 J + r) b + 16 J + q], r > q; its diagonal is 1 / H(p, p), zero where
+// that column is zero).  With p = acc[c] and e = e_p,
+//   x_J = X_J (e_J - sum_{K < J} L_JK x_K),  J = block(p) .. block(acc[s - 1]),
+// so the chain is one step per block, not per proposal.  One wavefront: lane
+// (g, r) takes row r of a block and a quarter of each sum.  x: b doubles in
+// LDS, written by this wavefront only.
+__device__ inline void linv_blocks(const double* __restrict__ H, const int32_t* __restrict__ acc, int b, int s,
+                                   int c, int lane, double* x) {
+  const int g = lane >> 4, r = lane & 15;
+  const int p = acc[c];
+  const int J0 = p >> 4, J1 = acc[s - 1] >> 4;
+  for (int i = lane; i < b; i += 64) x[i] = 0.0;
+  for (int J = J0; J <= J1; ++J) {
+    const int row = 16 * J + r;
+    const int rowc = row < b ? row : b - 1;
+    // e_J(r) - sum over the earlier blocks (K = J0 + g, J0 + g + 4, ...)
+    double y = 0.0;
+    for (int K = J0 + g; K < J; K += 4) {
+      const double* hc = H + (int64_t)(16 * K) * b + rowc;   // column 16 K, row `row`
+      double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; q += 2) {
+        t0 = fma(hc[(int64_t)q * b], x[16 * K + q], t0);
+        t1 = fma(hc[(int64_t)(q + 1) * b], x[16 * K + q + 1], t1);
+      }
+      y += t0 + t1;
+    }
+    y += __shfl_xor(y, 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    y = (row == p ? 1.0 : 0.0) - y;
+    // x_J(r) = sum_q X_J(r, q) y(q), lane (g, r) taking q = 4 g .. 4 g + 3
+    double xr = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * g + j;
+      const double yq = __shfl(y, q, 64);   // lane q holds y(q)
+      double xq = 0.0;
+      if (row < b && 16 * J + q < b) {
+        if (q < r) {
+          xq = H[(int64_t)row * b + 16 * J + q];
+        } else if (q == r) {
+          const double dg = H[(int64_t)row * b + row];
+          xq = dg > 0.0 ? 1.0 / dg : 0.0;
+        }
+      }
+      xr = fma(xq, yq, xr);
+    }
+    xr += __shfl_xor(xr, 16, 64);
+    xr += __shfl_xor(xr, 32, 64);
+    if (g == 0 && row < b) x[row] = xr;
+  }
+}
+
 // Squared distance by direct differences (a point paired with itself gives 0).
 __device__ __attribute__((always_inline)) inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
   double s = 0.0;

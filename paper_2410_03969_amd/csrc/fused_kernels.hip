@@ -640,10 +640,18 @@ __global__ __launch_bounds__(64) void k_fused_linv(RoundJob j0, const RoundJob* 
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   __shared__ double x[256];
-  double r[4];
-  linv_column(L, s, c, lane, r);
+  __shared__ double xp[256];   // proposal-indexed column (block solve)
+  if (L.b <= REJECT_TILED_BMAX) {
+    if (c < s) {
+      linv_blocks(L.H, L.acc, L.b, s, c, lane, xp);
+      for (int i = lane; i < s; i += 64) x[i] = xp[L.acc[i]];
+    }
+  } else {
+    double r[4];
+    linv_column(L, s, c, lane, r);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
+    for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
+  }
   __syncthreads();
   const int tc = c / FKC, slot = solve_slot(c % FKC);
   if constexpr (RES) {

@@ -1150,7 +1150,14 @@ __global__ __launch_bounds__(64) void k_trinv_bm(LFactor L, int Ctot, unsigned c
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   __shared__ double x[BMAX];
-  if (s <= 256) {
+  __shared__ double xp[REJECT_TILED_BMAX];   // proposal-indexed column (block solve)
+  if (L.b <= REJECT_TILED_BMAX) {
+    if (c < s) {
+      linv_blocks(L.H, L.acc, L.b, s, c, lane, xp);
+      for (int i = lane; i < s; i += 64) x[i] = xp[L.acc[i]];
+    }
+    __syncthreads();
+  } else if (s <= 256) {
     double r[4];
     linv_column(L, s, c, lane, r);
 #pragma unroll

@@ -519,7 +519,7 @@ __device__ void reject_body(Store S, int b, const int64_t* __restrict__ props, U
 constexpr int RT = 16;                  // tile edge
 constexpr int REJECT_T_THREADS = 512;
 constexpr int REJECT_T_BMAX = 256;
-constexpr int REJECT_G_BMAX = 512;      // the form with the trailing tiles in global memory
+constexpr int REJECT_G_BMAX = REJECT_TILED_BMAX;   // the form with the trailing tiles in global memory
 constexpr int REJECT_T_TW = 7;          // tile wavefronts
 constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
@@ -765,6 +765,16 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
         if (lane < RT)
 #pragma unroll
           for (int r = 0; r < RT; ++r) xo[r * RT + lane] = y[r];
+      }
+      // X's strictly lower part into the upper triangle of the block's
+      // diagonal block of H, no longer read here (the inverse-factor kernels
+      // solve by blocks with it; see linv_blocks): lane (g, c) stores rows
+      // g, g + 4, g + 8, g + 12 of column c, read back from LDS
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = g + 4 * i;
+        if (r > l16 && RT * I + r < b)
+          H[(int64_t)(RT * I + r) * b + RT * I + l16] = sm.XB[I & 1][r * RT + l16];
       }
       if (lane == 0) sm.bmask = (int)mask;
       if constexpr (LA) {
