@@ -523,6 +523,8 @@ constexpr int REJECT_G_BMAX = REJECT_TILED_BMAX;   // the form with the trailing
 constexpr int REJECT_T_TW = 7;          // tile wavefronts
 constexpr int REJECT_T_TPW = 20;        // tiles per tile wavefront: 136 / 7, rounded up
 constexpr int QS = 18;                  // LDS row stride (doubles) of the block-column buffer
+constexpr int GT_RC = 13;               // b > 256: block columns whose tiles stay in registers
+constexpr int GT_TPW = 13;              // their tiles per tile wavefront: 91 / 7
 constexpr int DUP_HBITS = 12;           // 4096 hash buckets
 
 // LDS of the tiled form.  The small arrays come first, at addresses that fit
@@ -947,14 +949,62 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
       nacc += __popc(mask);
     }
   } else {
-    // Trailing tiles in H itself: tile (J, L), J >= L, element (r, c) (row
-    // 16 J + r, column 16 L + c of the residual) at H[(16 J + r) b + 16 L + c],
-    // which is the upper triangle of the column-major H for J > L and the
-    // whole diagonal block for J = L.  The factor goes to the lower triangle
-    // of block columns already consumed, so the two never overlap.  At most
-    // 2 MiB, held in the L2 of the workgroup's XCD; each update is a load,
-    // four matrix-core products and a store per tile.
+    // 256 < b <= 512: the trailing triangle (up to 528 tiles, 1 MiB) does
+    // not fit the register file.  The tiles of the last GT_RC block columns
+    // (L >= L0) are held in registers as in the form above (numbered down
+    // those columns, tile t of that sub-triangle to tile wavefront t mod 7).
+    // The tiles of the earlier block columns stay in H itself: tile (J, L),
+    // J >= L, element (r, c) (row 16 J + r, column 16 L + c of the residual)
+    // at H[(16 J + r) b + 16 L + c], the upper triangle of the column-major H
+    // for J > L and the whole diagonal block for J = L (the factor goes to the
+    // lower triangle of block columns already consumed, so the two never
+    // overlap); each of their updates is a load, four matrix-core products
+    // and a store, out of the XCD's L2.  Per block I: 1. block column I with
+    // the pending update (of block I - 1) to LDS; 2. the rest of the pending
+    // update, beside the tests; 3. the panel below the block.
     const int wt = w - 1;
+    const int L0 = nbk > GT_RC ? nbk - GT_RC : 0;   // first register-resident block column
+    const int mr = nbk - L0;
+    const int ntr = mr * (mr + 1) / 2;
+    const int nslot = ntr > wt ? (ntr - wt + REJECT_T_TW - 1) / REJECT_T_TW : 0;
+    // first tile of sub-triangle column L (L0 <= L <= nbk), and this
+    // wavefront's first slot at or after sub-triangle tile T
+    auto t0r = [&](int L) __attribute__((always_inline)) {
+      const int q = L - L0;
+      return q * mr - q * (q - 1) / 2;
+    };
+    auto kfirst = [&](int T) __attribute__((always_inline)) {
+      return T > wt ? (T - wt + REJECT_T_TW - 1) / REJECT_T_TW : 0;
+    };
+    rd4 tr[GT_TPW];
+    // (J, L) of this wavefront's slots, eight bits each, two slots per word
+    // (scalar registers); slots past the last tile name tile (0, 0)
+    unsigned pk[(GT_TPW + 1) / 2];
+    {
+#pragma unroll
+      for (int q = 0; q < (GT_TPW + 1) / 2; ++q) pk[q] = 0;
+      int L = L0, off = wt;   // tile wt + 7 k of the sub-triangle: (L + off, L)
+#pragma unroll
+      for (int k = 0; k < GT_TPW; ++k) {
+        while (L < nbk && off >= nbk - L) {
+          off -= nbk - L;
+          ++L;
+        }
+        if (k < nslot) pk[k / 2] |= (unsigned)(((L + off) & 255) | ((L & 255) << 8)) << (16 * (k % 2));
+        off += REJECT_T_TW;
+      }
+    }
+    // f(k, J, L) for the slots k in [lo, hi), lo <= hi (a bit mask, as above)
+    auto for_slots = [&](int lo, int hi, auto f) __attribute__((always_inline)) {
+      const unsigned sel = ((1u << hi) - 1u) ^ ((1u << lo) - 1u);
+#pragma unroll
+      for (int k = 0; k < GT_TPW; ++k) {
+        if ((sel >> k) & 1u) {
+          const unsigned e = pk[k / 2] >> (16 * (k % 2));
+          f(k, (int)(e & 255), (int)((e >> 8) & 255));
+        }
+      }
+    };
     // tile (J, L) from H (indices clamped into the matrix; see tpad)
     auto tload = [&](int J, int L) __attribute__((always_inline)) {
       rd4 t;
@@ -994,18 +1044,25 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
       return t;
     };
     constexpr int NB1 = (REJECT_G_BMAX / RT + REJECT_T_TW - 1) / REJECT_T_TW;   // tiles of a block column per wavefront
-    constexpr int NB = 8;                                                       // tiles in flight in the update
+    constexpr int NB = 4;   // tiles of H in flight in the update (the register tiles leave room for four)
     lds_sync();   // (P)
+    // the register-resident tiles, all loads in flight (clamped indices)
+#pragma unroll
+    for (int k = 0; k < GT_TPW; ++k) {
+      const unsigned e = pk[k / 2] >> (16 * (k % 2));
+      tr[k] = tload((int)(e & 255), (int)((e >> 8) & 255));
+    }
     if (!keep_all && !un.U)
       for (int i = tid - 64; i < b; i += REJECT_T_THREADS - 64)
         sm.uv[i] = philox_uniform(un.seed, (uint64_t)(2 * (int64_t)b * round + b + i));
     lds_sync();   // (0)
+    for_slots(0, nslot, [&](int k, int J, int L) { tpad(tr[k], J, L); });
     int pmask = 0;
     for (int I = 0; I < nbk && nacc < cap; ++I) {
       double(*Qb)[QS] = sm.Q[I & 1];
       double(*Qp)[QS] = sm.Q[(I + 1) & 1];
       // 1. block column I (tiles (J, I), J >= I) with the pending update, to LDS
-      {
+      if (I < L0) {
         rd4 t[NB1];
 #pragma unroll
         for (int n = 0; n < NB1; ++n) {
@@ -1022,55 +1079,49 @@ __global__ __launch_bounds__(REJECT_T_THREADS) void k_reject_tiled(RoundJob j0, 
             for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = t[n][i];
           }
         }
+      } else {
+        // register tiles of block column I: update and copy in one pass
+        for_slots(kfirst(t0r(I)), kfirst(t0r(I + 1)), [&](int k, int J, int L) {
+          if (pmask) tr[k] = tupd(tr[k], Qp, J, L);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Qb[RT * J + g + 4 * i][l16] = tr[k][i];
+        });
       }
       __syncthreads();   // (1)
-      // 2. the rest of the pending update, beside the tests: the trailing
-      // tiles (J, L), J >= L > I, numbered down the block columns, tile q to
-      // tile wavefront q mod 7, in batches of NB; the loads of the next batch
-      // are issued before the products and stores of this one (two register
-      // sets; loads past the last tile are clamped into the matrix and their
-      // values dropped)
+      // 2. the rest of the pending update, beside the tests
       if (pmask) {
-        const int nt = nbk - I - 1, m = nt * (nt + 1) / 2;
-        int L = I + 1, off = wt;   // the next tile: (L + off, L)
-        // (J, L) of the next tile, packed J | L << 8
-        auto next = [&]() __attribute__((always_inline)) {
-          while (off >= nbk - L && L < nbk - 1) {
-            off -= nbk - L;
-            ++L;
-          }
-          const int J = L + off < nbk ? L + off : nbk - 1;
-          off += REJECT_T_TW;
-          return J | (L << 8);
-        };
-        auto load_batch = [&](rd4 (&t)[NB], int (&jl)[NB]) __attribute__((always_inline)) {
+        // tiles in H: (J, L), I < L < L0, numbered down the block columns,
+        // tile q to tile wavefront q mod 7, NB loads in flight
+        if (I + 1 < L0) {
+          const int m = (L0 - I - 1) * nbk - ((L0 - 1) * L0 / 2 - I * (I + 1) / 2);
+          int L = I + 1, off = wt;   // tile q: (L + off, L)
+          for (int q = wt; q < m; q += REJECT_T_TW * NB) {
+            int Js[NB], Ls[NB];
+            rd4 t[NB];
 #pragma unroll
-          for (int n = 0; n < NB; ++n) {
-            jl[n] = next();
-            t[n] = tload(jl[n] & 255, jl[n] >> 8);
-          }
-        };
-        auto apply_batch = [&](rd4 (&t)[NB], const int (&jl)[NB], int q0) __attribute__((always_inline)) {
+            for (int n = 0; n < NB; ++n) {
+              while (off >= nbk - L && L < nbk - 1) {
+                off -= nbk - L;
+                ++L;
+              }
+              Js[n] = L + off < nbk ? L + off : nbk - 1;
+              Ls[n] = L;
+              t[n] = tload(Js[n], Ls[n]);
+              off += REJECT_T_TW;
+            }
 #pragma unroll
-          for (int n = 0; n < NB; ++n) {
-            if (q0 + REJECT_T_TW * n < m) {
-              const int J = jl[n] & 255, L2 = jl[n] >> 8;
-              tpad(t[n], J, L2);
-              tstore(tupd(t[n], Qp, J, L2), J, L2);
+            for (int n = 0; n < NB; ++n) {
+              if (q + REJECT_T_TW * n < m) {
+                tpad(t[n], Js[n], Ls[n]);
+                tstore(tupd(t[n], Qp, Js[n], Ls[n]), Js[n], Ls[n]);
+              }
             }
           }
-        };
-        rd4 ta[NB], tb[NB];
-        int ja[NB], jb[NB];
-        if (wt < m) load_batch(ta, ja);
-        for (int q = wt; q < m; q += 2 * REJECT_T_TW * NB) {
-          const bool more = q + REJECT_T_TW * NB < m;
-          if (more) load_batch(tb, jb);
-          apply_batch(ta, ja, q);
-          if (!more) break;
-          if (q + 2 * REJECT_T_TW * NB < m) load_batch(ta, ja);
-          apply_batch(tb, jb, q + REJECT_T_TW * NB);
         }
+        // register tiles of block columns L > I
+        const int Lr = I + 1 > L0 ? I + 1 : L0;
+        if (Lr < nbk)
+          for_slots(kfirst(t0r(Lr)), nslot, [&](int k, int J, int L) { tr[k] = tupd(tr[k], Qp, J, L); });
       }
       __syncthreads();   // (2)
       const int mask = sm.bmask;
