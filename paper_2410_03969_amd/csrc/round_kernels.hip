@@ -48,13 +48,18 @@ __global__ __launch_bounds__(CHUNK) void k_init(double* __restrict__ u, double* 
                                                 const double* __restrict__ X, int64_t N, int d,
                                                 KParams kp, RoundState* st) {
   __shared__ double sh[CHUNK];
-  const int64_t j = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * CHUNK, j = j0 + threadIdx.x;
   double v = 0.0;
   if (j < N) {
     v = kappa_r2(0.0, kp);
     u[j] = v;
+  }
+  // nonfinite coordinates: this workgroup's rows are one contiguous range of
+  // X, read with consecutive threads on consecutive values
+  {
+    const int64_t q0 = j0 * d, q1 = (j0 + CHUNK < N ? j0 + CHUNK : N) * (int64_t)d;
     bool bad = false;
-    for (int t = 0; t < d; ++t) bad |= !isfinite(X[j * d + t]);
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += CHUNK) bad |= !isfinite(X[q]);
     if (bad) atomicOr(&st->nonfinite, 1);
   }
   const double s = block_sum<CHUNK>(v, sh);
@@ -295,7 +300,23 @@ __global__ __launch_bounds__(256) void k_gather_Hp(RoundJob jb0, const RoundJob*
   const double* ar = Fs + (int64_t)(ai ? i0 + l16 : 0) * ldf;
   const double* br = Fs + (int64_t)(bj ? j0 + l16 : 0) * ldf;
   rd4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t c = cbeg + 16 * w; c < cend; c += 64) {
+  int64_t c = cbeg + 16 * w;
+  // four chunks of this wavefront at a time, their loads issued before the products
+  for (; c + 3 * 64 + 16 <= cend; c += 4 * 64) {
+    double av[4][4], bv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        av[u][m] = ai ? ar[c + 64 * u + 4 * g + m] : 0.0;
+        bv[u][m] = bj ? br[c + 64 * u + 4 * g + m] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][m], bv[u][m], acc, 0, 0, 0);
+  }
+  for (; c < cend; c += 64) {
     double av[4], bv[4];
     if (c + 16 <= cend) {
 #pragma unroll
