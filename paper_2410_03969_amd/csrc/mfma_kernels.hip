@@ -171,12 +171,14 @@ __device__ inline void store_piece(typename Pol::S* __restrict__ base, int64_t r
         hi[j] = (__bf16)v[j];
       }
     }
-    *(bf8*)(base + blk_offset<Pol>(row, k, nkc, 0)) = hi;
-    if constexpr (Pol::SPLANES == 2) *(bf8*)(base + blk_offset<Pol>(row, k, nkc, 1)) = lo;
+    // non-temporal: nothing in this launch reads them back, and in L2 they
+    // would evict the panel of F that the column groups share
+    __builtin_nontemporal_store(hi, (bf8*)(base + blk_offset<Pol>(row, k, nkc, 0)));
+    if constexpr (Pol::SPLANES == 2) __builtin_nontemporal_store(lo, (bf8*)(base + blk_offset<Pol>(row, k, nkc, 1)));
   } else {
     u4 w;
     __builtin_memcpy(&w, v, 16);
-    *(u4*)(base + blk_offset<Pol>(row, k, nkc, 0)) = w;
+    __builtin_nontemporal_store(w, (u4*)(base + blk_offset<Pol>(row, k, nkc, 0)));
   }
 }
 
