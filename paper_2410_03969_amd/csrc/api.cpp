@@ -89,14 +89,18 @@ Layout layout_of(const arpc_problem& p) {
     off += align256(bytes);
     return o;
   };
-  l.st = take(sizeof(RoundState));
+  // the round state, the residual trace beside it and the round history
+  // right after: the end of a run reads all three back in one copy
+  static_assert(sizeof(RoundState) <= kTraceOff, "round state overlaps the trace slot");
+  l.st = take(kTraceOff + sizeof(double));
+  l.trace = l.st + kTraceOff;
+  l.hist = take(sizeof(int32_t) * (p.k + 1));
   l.jd = take(sizeof(RoundJob));
   l.u = take(sizeof(double) * p.N);
   l.csum = take(sizeof(double) * nch);
   l.cpre = take(sizeof(double) * nch);
   l.props = take(sizeof(int64_t) * p.b);
   l.acc = take(sizeof(int32_t) * p.b);
-  l.hist = take(sizeof(int32_t) * (p.k + 1));
   l.Fs = take(sizeof(double) * p.b * p.k);
   l.Hp = take(sizeof(double) * gather_splits(p.k) * p.b * p.b);
   l.H = take(sizeof(double) * p.b * p.b);
@@ -119,7 +123,6 @@ Layout layout_of(const arpc_problem& p) {
   l.xn8 = take(l.packed ? sizeof(float) * p.N : 0);
   l.Xp8 = take(l.dist8 ? (size_t)p.b * p.d : 0);
   l.ypn = take(l.dist8 ? sizeof(float) * p.b : 0);
-  l.trace = take(sizeof(double));
   l.total = off;
   return l;
 }
@@ -263,7 +266,7 @@ RoundJob round_job_of(const arpc_problem& p, const Layout& l, char* ws, const do
 template <typename T>
 void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char* ws, const Layout& l,
                    const double* X, T* F, const RoundJob* tab, const RoundJob& hj, const RoundGrid& g,
-                   Profiler& prof) {
+                   Profiler& prof, RoundState* look = nullptr, hipEvent_t look_ev = nullptr) {
   const int b = (int)p.b, d = (int)p.d;
   const int64_t N = p.N, k = p.k;
   RoundState* st = (RoundState*)(ws + l.st);
@@ -286,6 +289,12 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
   prof.begin(ARPC_KC_REJECT);
   launch_reject_tab(s, tab, 1, b);
   prof.end();
+  if (look) {
+    // the state once this round's pivots are known (s_r), read back while
+    // the rest of the round runs
+    (void)hipMemcpyAsync(look, st, sizeof(RoundState), hipMemcpyDeviceToHost, s);
+    (void)hipEventRecord(look_ev, s);
+  }
   if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
     prof.begin(ARPC_KC_PREP);
     launch_prep_xp_tab(s, tab, 1);
@@ -424,9 +433,10 @@ struct Job final : JobBase {
 
   // Rounds and the end of the run enqueued without reading anything back
   // (the asynchronous entry points): rounds past the end exit on the device.
-  arpc_status enqueue_rounds(int64_t rounds) override {
+  arpc_status enqueue_rounds(int64_t rounds, RoundState* look, hipEvent_t look_ev) override {
     for (int64_t r = 0; r < rounds; ++r)
-      enqueue_round<T>(s, p, kp, ws, l, X, F, (const RoundJob*)(ws + l.jd), hj, g, *prof);
+      enqueue_round<T>(s, p, kp, ws, l, X, F, (const RoundJob*)(ws + l.jd), hj, g, *prof,
+                       r + 1 == rounds ? look : nullptr, look_ev);
     HIPCHK(hipGetLastError());
     return ARPC_OK;
   }
@@ -453,11 +463,9 @@ struct Job final : JobBase {
     double* tr = (double*)(ws + l.trace);
     launch_trace(s, (double*)(ws + l.csum), nch, tr);
     HIPCHK(hipMemcpyAsync(htrace, tr, sizeof(double), hipMemcpyDeviceToHost, s));
-    const int64_t k_out = h.k_r;
-    if (k_out < p.k && !h.nonfinite) {
-      HIPCHK(hipMemsetAsync(F + k_out * N, 0, sizeof(T) * (size_t)(p.k - k_out) * N, s));
-      HIPCHK(hipMemsetAsync(pivots + k_out, 0xff, sizeof(int64_t) * (size_t)(p.k - k_out), s));
-    }
+    // zero tails of F and pivots past k_r, from the device state (which h copies)
+    if (h.k_r < p.k && !h.nonfinite)
+      launch_zero_tail(s, (const RoundState*)(ws + l.st), p.k, N, (int)sizeof(T), F, pivots);
     HIPCHK(hipGetLastError());
     return ARPC_OK;
   }
@@ -478,6 +486,35 @@ struct Job final : JobBase {
     return ret;
   }
 
+  size_t end_read_bytes() const override { return l.hist - l.st + sizeof(int32_t) * (size_t)(p.k + 1); }
+
+  arpc_status enqueue_end_read(char* dst) override {
+    arpc_status e = enqueue_end();
+    if (e != ARPC_OK) return e;
+    HIPCHK(hipMemcpyAsync(dst, ws + l.st, end_read_bytes(), hipMemcpyDeviceToHost, s));
+    return ARPC_OK;
+  }
+
+  // src: what enqueue_end_read copied, after the stream has passed it
+  arpc_status finish_read(const char* src, arpc_stats* stats, double ms_total) override {
+    RoundState h;
+    std::memcpy(&h, src, sizeof(h));
+    if (h.nonfinite) return ARPC_ENUMERIC;
+    double trace_resid;
+    std::memcpy(&trace_resid, src + (l.trace - l.st), sizeof(double));
+    const int32_t* hist = (const int32_t*)(src + (l.hist - l.st));
+    const arpc_status ret = status_of(p, h);
+    fill_stats(p, l, h, hist, trace_resid, stats);
+    if (stats) {
+      for (int c = 0; c < ARPC_NUM_KC; ++c) {
+        stats->ms_kernel[c] = prof->ms[c];
+        stats->launches[c] = prof->n[c];
+      }
+      stats->ms_total = ms_total;
+    }
+    return ret;
+  }
+
   arpc_status finish(arpc_stats* stats, double ms_total) override {
     const RoundState h = *hstate;
     if (h.nonfinite) return ARPC_ENUMERIC;
@@ -490,11 +527,7 @@ struct Job final : JobBase {
     std::vector<int32_t> hist((size_t)h.round + 1, 0);
     if (h.round > 0)
       HIPCHK(hipMemcpyAsync(hist.data(), ws + l.hist, sizeof(int32_t) * h.round, hipMemcpyDeviceToHost, s));
-    const int64_t k_out = h.k_r;
-    if (k_out < p.k) {
-      HIPCHK(hipMemsetAsync(F + k_out * N, 0, sizeof(T) * (size_t)(p.k - k_out) * N, s));
-      HIPCHK(hipMemsetAsync(pivots + k_out, 0xff, sizeof(int64_t) * (size_t)(p.k - k_out), s));
-    }
+    if (h.k_r < p.k) launch_zero_tail(s, (const RoundState*)(ws + l.st), p.k, N, (int)sizeof(T), F, pivots);
     HIPCHK(hipStreamSynchronize(s));
 
     const arpc_status ret = status_of(p, h);
@@ -532,23 +565,104 @@ arpc_status check_factor_args(const arpc_problem* p, const double* X, const void
 
 namespace arpc {
 
+// Pinned host memory for the synchronous driver's read-backs, one buffer per
+// host thread, grown on demand and held until the process ends (a release at
+// exit could run after the runtime has been torn down).
+static char* sync_staging(size_t bytes) {
+  thread_local char* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    const size_t n = (bytes + 65535) & ~size_t(65535);
+    if (hipHostMalloc((void**)&buf, n, hipHostMallocDefault) != hipSuccess) {
+      buf = nullptr;
+      return nullptr;
+    }
+    cap = n;
+  }
+  return buf;
+}
+
+// Pivots and rounds at a look at the state taken after a round's rejection
+// step: what the run will hold once that round ends.
+struct Look {
+  int64_t pivots = 0, rounds = 0;
+};
+
+// Rounds to enqueue after the round in flight, from the state m read back
+// after its rejection step (its s_r known) and the previous look: the pivots
+// still missing, at the rate the rounds since that look added them, less
+// one.  The last of them looks again, so the count never needs to run over:
+// it only has to keep the stream from draining.
+static int64_t rounds_to_add(const arpc_problem& p, const Look& prev, const RoundState& m, int64_t enqueued) {
+  if (m.status != ST_RUNNING || m.s_r == 0) return 0;
+  const Look now{m.k_r + m.s_r, m.round + 1};
+  if (now.pivots >= p.k) return 0;
+  if (p.max_rounds > 0 && enqueued >= p.max_rounds) return 0;
+  const int64_t dr = now.rounds - prev.rounds;
+  double rate = dr > 0 ? (double)(now.pivots - prev.pivots) / (double)dr : (double)p.b;
+  if (rate < 1.0) rate = 1.0;
+  int64_t r = (int64_t)std::ceil((double)(p.k - now.pivots) / rate) - 1;
+  if (r < 1) r = 1;
+  if (p.max_rounds > 0 && enqueued + r > p.max_rounds) r = p.max_rounds - enqueued;
+  return r;
+}
+
+// The synchronous factorization.  The host never lets the stream drain
+// between rounds: the last round of each batch reads the state back after its
+// rejection step, and while the rest of that round runs the host enqueues
+// more rounds if that round leaves pivots missing, or else the end of the
+// run, and waits for it.  No round past the last one is enqueued.
 static arpc_status run_sync(const arpc_problem& p, const double* X, void* F, int64_t* pivots, char* ws,
                             const Layout& l, hipStream_t s, const Unif& un, arpc_stats* stats, unsigned classes) {
   const auto t0 = std::chrono::steady_clock::now();
   Profiler prof(s, classes);
-  RoundState h{};
-  auto job = make_job(p, X, F, pivots, ws, l, s, un, &h, &prof);
+  auto job = make_job(p, X, F, pivots, ws, l, s, un, nullptr, &prof);
+  char* stg = sync_staging(256 + job->end_read_bytes());
+  if (!stg) return ARPC_ENOMEM;
+  RoundState* look = (RoundState*)stg;
+  char* endb = stg + 256;
+  hipEvent_t ev;
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { (void)hipEventDestroy(e); }
+  } guard{ev};
+
   arpc_status e = job->begin();
   if (e != ARPC_OK) return e;
+  int64_t enq = 0;
+  int64_t want = (p.k + p.b - 1) / p.b;   // the fewest rounds that could suffice
+  if (p.max_rounds > 0 && want > p.max_rounds) want = p.max_rounds;
+  if (want < 1) want = 1;
+  Look prev;
   for (;;) {
-    e = job->enqueue_batch();
+    e = job->enqueue_rounds(want - enq, look, ev);
+    if (e != ARPC_OK) return e;
+    enq = want;
+    HIPCHK(hipEventSynchronize(ev));
+    const RoundState m = *look;
+    const int64_t more = rounds_to_add(p, prev, m, enq);
+    if (m.status == ST_RUNNING) prev = Look{m.k_r + m.s_r, m.round + 1};
+    if (more > 0) {
+      want = enq + more;
+      continue;
+    }
+    e = job->enqueue_end_read(endb);
     if (e != ARPC_OK) return e;
     HIPCHK(hipStreamSynchronize(s));
-    prof.collect();
-    if (!job->running()) break;
+    RoundState f;
+    std::memcpy(&f, endb, sizeof(f));
+    if (f.status != ST_RUNNING) break;
+    // cannot happen: the look saw the last round's pivots, and the round
+    // limit ends the run on the device; one more batch keeps it safe
+    want = enq + 1;
   }
+  prof.collect();
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return job->finish(stats, ms);
+  return job->finish_read(endb, stats, ms);
 }
 
 arpc_status factor_impl(const arpc_problem* p, const double* X, void* F, int64_t* pivots, void* ws,

@@ -15,6 +15,10 @@
 
 namespace arpc {
 
+// Byte offset of the residual trace inside the round state's slot of the
+// workspace; the round history follows that slot at the next 256-byte boundary.
+constexpr size_t kTraceOff = 128;
+
 // Offsets of the buffers carved from one factorization's workspace.
 struct Layout {
   size_t st, jd, u, csum, cpre, props, acc, hist, Fs, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, Xp8,
@@ -89,12 +93,20 @@ struct JobBase {
   virtual arpc_status begin() = 0;
   virtual arpc_status capture_round() = 0;
   virtual arpc_status enqueue_batch() = 0;
-  virtual arpc_status enqueue_rounds(int64_t rounds) = 0;
+  // look, look_ev: if set, the last round copies the round state into *look
+  // after its rejection step and records look_ev
+  virtual arpc_status enqueue_rounds(int64_t rounds, RoundState* look = nullptr, hipEvent_t look_ev = nullptr) = 0;
   virtual arpc_status enqueue_end() = 0;
   virtual bool running() = 0;
   virtual arpc_status finish(arpc_stats* stats, double ms_total) = 0;
   virtual arpc_status finish_enqueue(const RoundState& h, double* htrace) = 0;
   virtual arpc_status finish_stats(const RoundState& h, double trace_resid, arpc_stats* stats) = 0;
+  // synchronous driver: the end of the run (residual trace, zero tails)
+  // followed by one copy of the state, trace and round history
+  // (end_read_bytes) into host memory
+  virtual size_t end_read_bytes() const = 0;
+  virtual arpc_status enqueue_end_read(char* dst) = 0;
+  virtual arpc_status finish_read(const char* src, arpc_stats* stats, double ms_total) = 0;
 };
 
 extern unsigned g_profiling;   // timed kernel classes (arpc_set_profiling*)
