@@ -329,7 +329,7 @@ __device__ inline void linv_column(const LFactor& L, int s, int c, int lane, dou
 }
 
 // Largest b whose RejectionSampleSubmatrix runs in the tiled form, which also
-// leaves the inverses of its 16 x 16 diagonal blocks in H (see linv_blocks).
+// leaves the inverses of its 16 x 16 diagonal blocks in H (see linv_blocks_ahead).
 constexpr int REJECT_TILED_BMAX = 512;
 
 // Column c of the inverse of the accepted factor L(T,T) (s x s), in proposal
@@ -342,53 +342,97 @@ constexpr int REJECT_TILED_BMAX = 512;
 // H[(16 J + r) b + 16 J + q], r > q; its diagonal is 1 / H(p, p), zero where
 // that column is zero).  With p = acc[c] and e = e_p,
 //   x_J = X_J (e_J - sum_{K < J} L_JK x_K),  J = block(p) .. block(acc[s - 1]),
-// so the chain is one step per block, not per proposal.  One wavefront: lane
-// (g, r) takes row r of a block and a quarter of each sum.  x: b doubles in
-// LDS, written by this wavefront only.
-__device__ inline void linv_blocks(const double* __restrict__ H, const int32_t* __restrict__ acc, int b, int s,
-                                   int c, int lane, double* x) {
-  const int g = lane >> 4, r = lane & 15;
+// so the chain is one step per block, not per proposal.
+// On NW wavefronts, each block's operands loaded one block ahead: the loads
+// of step J + 1 (its row of L blocks and X_{J+1}) go out before the
+// arithmetic of step J, so the chain waits for about one L2 round trip in all
+// instead of one per block.  Lane (w, g, r) of the 64 NW takes row r of a
+// block and the blocks K = J0 + 4 w + g + 4 NW t (t < 2: at most 8 NW + 1
+// blocks); the wavefronts' partial sums meet in ysum (2 x NW x 16 doubles of
+// LDS, by step parity), one barrier per step, and every wavefront then forms
+// x_J (the same values in the same order) and stores it.  x: b doubles of
+// LDS.  Every thread of the workgroup must call it.
+template <int NW>
+__device__ __attribute__((always_inline)) inline void linv_blocks_ahead(const double* __restrict__ H,
+                                                                        const int32_t* __restrict__ acc, int b, int s,
+                                                                        int c, int tid, double* x, double* ysum) {
+  constexpr int KS = 2;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, r = lane & 15;
   const int p = acc[c];
   const int J0 = p >> 4, J1 = acc[s - 1] >> 4;
-  for (int i = lane; i < b; i += 64) x[i] = 0.0;
-  for (int J = J0; J <= J1; ++J) {
+  for (int i = tid; i < b; i += 64 * NW) x[i] = 0.0;
+  __syncthreads();
+  struct Ops {
+    double l[KS][16];   // L_JK(r, q) for K = J0 + 4 w + g + 4 NW t < J
+    double xq[4];       // X_J(r, 4 g + j) below the diagonal, H(row, row) on it
+  };
+  auto load = [&](Ops& o, int J) __attribute__((always_inline)) {
     const int row = 16 * J + r;
     const int rowc = row < b ? row : b - 1;
-    // e_J(r) - sum over the earlier blocks (K = J0 + g, J0 + g + 4, ...)
-    double y = 0.0;
-    for (int K = J0 + g; K < J; K += 4) {
-      const double* hc = H + (int64_t)(16 * K) * b + rowc;   // column 16 K, row `row`
-      double t0 = 0.0, t1 = 0.0;
+    // a uniform base per column q and one 32-bit offset per lane and block
+    // (b <= 8 NW + 1 blocks: every offset fits), so the addresses cost no
+    // registers per load
 #pragma unroll
-      for (int q = 0; q < 16; q += 2) {
-        t0 = fma(hc[(int64_t)q * b], x[16 * K + q], t0);
-        t1 = fma(hc[(int64_t)(q + 1) * b], x[16 * K + q + 1], t1);
+    for (int t = 0; t < KS; ++t) {
+      const int K = J0 + 4 * w + g + 4 * NW * t;
+      const unsigned off = (unsigned)(16 * K * b + rowc);
+      if (K < J) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) o.l[t][q] = (H + q * b)[off];
       }
-      y += t0 + t1;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * g + j;
+      double v = 0.0;
+      if (row < b && 16 * J + q < b && q <= r) v = H[(unsigned)(row * b + (q < r ? 16 * J + q : row))];
+      o.xq[j] = v;
+    }
+  };
+  auto step = [&](const Ops& o, int J) __attribute__((always_inline)) {
+    const int row = 16 * J + r;
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      const int K = J0 + 4 * w + g + 4 * NW * t;
+      if (K < J) {
+#pragma unroll
+        for (int q = 0; q < 16; q += 2) {
+          t0 = fma(o.l[t][q], x[16 * K + q], t0);
+          t1 = fma(o.l[t][q + 1], x[16 * K + q + 1], t1);
+        }
+      }
+    }
+    double y = t0 + t1;
     y += __shfl_xor(y, 16, 64);
     y += __shfl_xor(y, 32, 64);
-    y = (row == p ? 1.0 : 0.0) - y;
-    // x_J(r) = sum_q X_J(r, q) y(q), lane (g, r) taking q = 4 g .. 4 g + 3
+    double* ys = ysum + (J & 1) * (16 * NW);
+    if (g == 0) ys[w * 16 + r] = y;
+    __syncthreads();
+    double ya = 0.0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) ya += ys[16 * v + r];
+    y = (row == p ? 1.0 : 0.0) - ya;
     double xr = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = 4 * g + j;
-      const double yq = __shfl(y, q, 64);   // lane q holds y(q)
-      double xq = 0.0;
-      if (row < b && 16 * J + q < b) {
-        if (q < r) {
-          xq = H[(int64_t)row * b + 16 * J + q];
-        } else if (q == r) {
-          const double dg = H[(int64_t)row * b + row];
-          xq = dg > 0.0 ? 1.0 / dg : 0.0;
-        }
-      }
+      const double yq = __shfl(y, q, 64);
+      const double xq = q < r ? o.xq[j] : (q == r && o.xq[j] > 0.0 ? 1.0 / o.xq[j] : 0.0);
       xr = fma(xq, yq, xr);
     }
     xr += __shfl_xor(xr, 16, 64);
     xr += __shfl_xor(xr, 32, 64);
     if (g == 0 && row < b) x[row] = xr;
+  };
+  Ops a, bb;
+  load(a, J0);
+  for (int J = J0; J <= J1; J += 2) {
+    if (J + 1 <= J1) load(bb, J + 1);
+    step(a, J);
+    if (J + 1 > J1) break;
+    if (J + 2 <= J1) load(a, J + 2);
+    step(bb, J + 1);
   }
 }
 

@@ -624,13 +624,13 @@ __global__ __launch_bounds__(256) void k_fused_bm1(RoundJob j0, const RoundJob* 
 }
 
 // Inverse of the s x s lower factor L (read from H through the accepted
-// indices), one workgroup per column t: forward substitution, then Linv(i, t)
-// stored at chunk t / 32, slot
-// solve_slot(t % 32), column i (zero outside i, t < s and below the diagonal).
+// indices), one workgroup per column t: block forward substitution from the
+// blocks' inverses that the tiled rejection kernel leaves in H (b <= 256 here),
+// then Linv(i, t) stored at chunk t / 32, slot solve_slot(t % 32), column i
+// (zero outside i, t < s and below the diagonal).
 template <int SPL, bool RES, bool TAB>
-__global__ __launch_bounds__(64) void k_fused_linv(RoundJob j0, const RoundJob* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_fused_linv(RoundJob j0, const RoundJob* __restrict__ tab) {
   ConstRoundJob& RJ = job_of<TAB>(j0, tab);
-  const LFactor L{RJ.H, RJ.acc, RJ.b};
   const int CP = RJ.CP;
   unsigned char* __restrict__ Bm2 = RJ.Bm2;
   const RoundState* st = RJ.st;
@@ -638,31 +638,25 @@ __global__ __launch_bounds__(64) void k_fused_linv(RoundJob j0, const RoundJob* 
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   __shared__ double x[256];
-  __shared__ double xp[256];   // proposal-indexed column (block solve)
-  if (L.b <= REJECT_TILED_BMAX) {
-    if (c < s) {
-      linv_blocks(L.H, L.acc, L.b, s, c, lane, xp);
-      for (int i = lane; i < s; i += 64) x[i] = xp[L.acc[i]];
-    }
-  } else {
-    double r[4];
-    linv_column(L, s, c, lane, r);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
+  __shared__ double xp[256];   // proposal-indexed column
+  __shared__ double ys[128];
+  if (c < s) {   // uniform
+    linv_blocks_ahead<4>(RJ.H, RJ.acc, RJ.b, s, c, tid, xp, ys);
+    for (int i = tid; i < s; i += 256) x[i] = xp[RJ.acc[i]];
   }
   __syncthreads();
   const int tc = c / FKC, slot = solve_slot(c % FKC);
   if constexpr (RES) {
     // rows 32 tc .. CP - 1 of the blocks (i / 16, tc) of the resident triangle
-    for (int i = FKC * tc + lane; i < CP; i += 64) {
+    for (int i = FKC * tc + tid; i < CP; i += 256) {
       const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
       unsigned char* base = Bm2 + (size_t)(tri_base(i / 16) + tc) * 16 * FCROW + (size_t)(i % 16) * FCROW + slot * 2;
       *(__bf16*)base = (__bf16)(float)v;
     }
   } else {
-    for (int i = lane; i < CP; i += 64) {
+    for (int i = tid; i < CP; i += 256) {
       const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
       __bf16 hi, lo;
       split_hi_lo((float)v, hi, lo);
@@ -774,10 +768,10 @@ void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, 
   const int nt = (ncbt + 1) / 2;
   if (prec == 2) {
     hipLaunchKernelGGL((k_fused_bm1<2, true>), dim3(512, n), dim3(256), 0, s, RoundJob{}, tab);
-    hipLaunchKernelGGL((k_fused_linv<2, false, true>), dim3(nt * FKC, n), dim3(64), 0, s, RoundJob{}, tab);
+    hipLaunchKernelGGL((k_fused_linv<2, false, true>), dim3(nt * FKC, n), dim3(256), 0, s, RoundJob{}, tab);
   } else {
     hipLaunchKernelGGL((k_fused_bm1<1, true>), dim3(512, n), dim3(256), 0, s, RoundJob{}, tab);
-    hipLaunchKernelGGL((k_fused_linv<1, true, true>), dim3(nt * FKC, n), dim3(64), 0, s, RoundJob{}, tab);
+    hipLaunchKernelGGL((k_fused_linv<1, true, true>), dim3(nt * FKC, n), dim3(256), 0, s, RoundJob{}, tab);
   }
 }
 

@@ -1140,52 +1140,58 @@ __global__ __launch_bounds__(256) void k_prep_bm(const double* __restrict__ Fs, 
 }
 
 // Inverse of the s x s lower factor L (read from H through the accepted
-// indices): workgroup c
-// computes column c by forward substitution with wavefront dot products and
-// stores Linv(i, c) as element (k = c, column i) of the chunked operand of the
-// triangular-solve product.  Workgroups c >= s write the zero padding.
+// indices): workgroup c (four wavefronts) computes column c by forward
+// substitution and stores Linv(i, c) as element (k = c, column i) of the
+// chunked operand of the triangular-solve product.  Workgroups c >= s write
+// the zero padding.  b <= 512: by blocks, operands one block ahead (the tiled
+// rejection kernel has left the blocks' inverses in H); else column by column.
 template <class Pol, int PASSES>
-__global__ __launch_bounds__(64) void k_trinv_bm(LFactor L, int Ctot, unsigned char* __restrict__ Bm,
-                                                 const RoundState* st) {
+__global__ __launch_bounds__(256) void k_trinv_bm(LFactor L, int Ctot, unsigned char* __restrict__ Bm,
+                                                  const RoundState* st) {
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   const int c = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   __shared__ double x[BMAX];
   __shared__ double xp[REJECT_TILED_BMAX];   // proposal-indexed column (block solve)
+  __shared__ double ys[128];
   if (L.b <= REJECT_TILED_BMAX) {
-    if (c < s) {
-      linv_blocks(L.H, L.acc, L.b, s, c, lane, xp);
-      for (int i = lane; i < s; i += 64) x[i] = xp[L.acc[i]];
+    if (c < s) {   // uniform
+      linv_blocks_ahead<4>(L.H, L.acc, L.b, s, c, tid, xp, ys);
+      for (int i = tid; i < s; i += 256) x[i] = xp[L.acc[i]];
     }
-    __syncthreads();
   } else if (s <= 256) {
-    double r[4];
-    linv_column(L, s, c, lane, r);
+    if (w == 0) {
+      double r[4];
+      linv_column(L, s, c, lane, r);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
-    __syncthreads();
+      for (int m = 0; m < 4; ++m) x[lane + 64 * m] = r[m];
+    }
   } else if (s <= 512) {
-    double r[8];
-    linv_column(L, s, c, lane, r);
+    if (w == 0) {
+      double r[8];
+      linv_column(L, s, c, lane, r);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[lane + 64 * m] = r[m];
+      for (int m = 0; m < 8; ++m) x[lane + 64 * m] = r[m];
+    }
+  } else if (c < s) {   // uniform
+    for (int i = tid; i < s; i += 256) x[i] = 0.0;
     __syncthreads();
-  } else if (c < s) {
-    for (int i = lane; i < s; i += 64) x[i] = 0.0;
-    __syncthreads();
-    if (lane == 0) x[c] = 1.0 / L.at(c, c);
+    if (tid == 0) x[c] = 1.0 / L.at(c, c);
     __syncthreads();
     for (int i = c + 1; i < s; ++i) {
-      double p = 0.0;
-      for (int t = c + lane; t < i; t += 64) p += L.at(i, t) * x[t];
+      if (w == 0) {
+        double p = 0.0;
+        for (int t = c + lane; t < i; t += 64) p += L.at(i, t) * x[t];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      if (lane == 0) x[i] = -p / L.at(i, i);
+        for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+        if (lane == 0) x[i] = -p / L.at(i, i);
+      }
       __syncthreads();
     }
   }
-  for (int i = lane; i < Ctot; i += 64) {
+  __syncthreads();
+  for (int i = tid; i < Ctot; i += 256) {
     const double v = (c < s && i >= c && i < s) ? x[i] : 0.0;
     if constexpr (Pol::KC == 32) {
       __bf16 hi, lo;
@@ -1264,7 +1270,7 @@ static void prep_impl(hipStream_t s, const MfmaRound& r, const RoundState* st) {
   hipLaunchKernelGGL((k_prep_bm<Pol, PASSES>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r.Fs, r.ldf,
                      r.acc, r.Ctot, r.Bm1, st);
   const int nblk = (r.b + Pol::KC - 1) / Pol::KC * Pol::KC;
-  hipLaunchKernelGGL((k_trinv_bm<Pol, PASSES>), dim3(nblk), dim3(64), 0, s, LFactor{r.H, r.acc, r.b}, r.Ctot, r.Bm2,
+  hipLaunchKernelGGL((k_trinv_bm<Pol, PASSES>), dim3(nblk), dim3(256), 0, s, LFactor{r.H, r.acc, r.b}, r.Ctot, r.Bm2,
                      st);
 }
 
