@@ -297,7 +297,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
   }
   if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
     prof.begin(ARPC_KC_PREP);
-    launch_prep_xp_tab(s, tab, 1);
+    launch_prep_xp_tab(s, tab, 1, p.b * p.d);
     launch_fused_prep_tab(s, gemm_prec(p.prec), tab, 1, l.ncbt);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
@@ -321,7 +321,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
                  l.dist8 ? (const unsigned char*)(ws + l.Xp8) : nullptr,
                  l.dist8 ? (const float*)(ws + l.ypn) : nullptr};
     prof.begin(ARPC_KC_PREP);
-    launch_prep_xp_tab(s, tab, 1);
+    launch_prep_xp_tab(s, tab, 1, p.b * p.d);
     if (l.dist8)   // the accepted points as e4m3 codes for the update GEMM's epilogue
       launch_pack_e4m3(s, Xp, b, d, (unsigned*)(ws + l.Xp8), (float*)(ws + l.ypn));
     launch_mfma_prep(s, gemm_prec(p.prec), mr, st);

@@ -89,7 +89,5 @@ bool mfma_dist_in_epilogue(int d);
 void launch_pack_e4m3(hipStream_t s, const double* Xq, int64_t N, int d, unsigned* X8, float* xn);
 void launch_dist(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
 void launch_mfma_trsm(hipStream_t s, int prec, const MfmaRound& r, const RoundState* st);
-void launch_prep_xp(hipStream_t s, const int32_t* acc, const int64_t* props, const double* X, int d,
-                    double* Xp, const RoundState* st);
 
 }  // namespace arpc

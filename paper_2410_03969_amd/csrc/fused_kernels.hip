@@ -119,6 +119,12 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   if (st->status != ST_RUNNING) return;
   const int s = st->s_r;
   if (s == 0) return;
+  // the last column block holds accepted columns (else its update and solve
+  // products are exactly zero and are skipped: the accumulators keep their
+  // zeros).  The solve's skip is compiled where it leaves the register
+  // allocation as it is (one product, d <= 16).
+  const bool lastcb = s > 16 * (NCBT - 1);
+  constexpr bool SKIP_SOLVE = PASSES == 1 && DX <= 16;
   const int64_t kr = st->k_r;
   const int64_t nk = (kr + FKC - 1) / FKC;      // contraction chunks of the update GEMM
   const int64_t N = a.N;
@@ -304,6 +310,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
             const bf8 ah = ap[cb % PD];
             bf8 al;
             if constexpr (PASSES == 3) al = alp[cb % PD];
+            if (cb + 1 < NCBT || lastcb)
 #pragma unroll
             for (int nb = 0; nb < FNB; ++nb) {
               acc[nb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr[u][nb][0], acc[nb][cb], 0, 0, 0);
@@ -452,7 +459,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         const unsigned char* L = lds + (q & 1) * STAGE;
 #pragma unroll
         for (int mt = 0; mt < NCBT; ++mt) {
-          if (32 * tc <= 16 * mt + 15) {
+          if (32 * tc <= 16 * mt + 15 && (!SKIP_SOLVE || mt + 1 < NCBT || lastcb)) {
             bf8 ah, al;
             if constexpr (RES) {
               ah = *(const bf8*)(lds + RING + (tri_base(mt) + tc) * 16 * FCROW + l16 * FCROW + g * 16);

@@ -1508,20 +1508,14 @@ __global__ __launch_bounds__(256) void k_prep_xp(RoundJob j0, const RoundJob* __
   }
 }
 
-void launch_prep_xp(hipStream_t s, const int32_t* acc, const int64_t* props, const double* X, int d, double* Xp,
-                    const RoundState* st) {
-  RoundJob j{};
-  j.acc = const_cast<int32_t*>(acc);
-  j.props = const_cast<int64_t*>(props);
-  j.X = X;
-  j.d = d;
-  j.Xp = Xp;
-  j.st = const_cast<RoundState*>(st);
-  hipLaunchKernelGGL(k_prep_xp<false>, dim3(8), dim3(256), 0, s, j, nullptr);
+// one element per thread (the gather is a chain of three dependent loads)
+static unsigned prep_xp_blocks(int64_t bd) {
+  const int64_t g = (bd + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
-void launch_prep_xp_tab(hipStream_t s, const RoundJob* tab, int n) {
-  hipLaunchKernelGGL(k_prep_xp<true>, dim3(8, n), dim3(256), 0, s, RoundJob{}, tab);
+void launch_prep_xp_tab(hipStream_t s, const RoundJob* tab, int n, int64_t bd) {
+  hipLaunchKernelGGL(k_prep_xp<true>, dim3(prep_xp_blocks(bd), n), dim3(256), 0, s, RoundJob{}, tab);
 }
 
 // out[i] = the round state of table row i (out: host memory mapped for the
