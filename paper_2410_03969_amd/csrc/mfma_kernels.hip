@@ -406,31 +406,32 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
       }
     }
   } else {
+    // BF16: the N-row operand FD - 1 chunks ahead in FD register buffers
+    // taken in turn (three in the one-product mode, whose registers allow
+    // it: the epilogue sets the kernel's peak), the small operand one chunk
+    // ahead.  Straight-line as in the FP64 and FP32 loop: the loads and the
+    // commit are unconditional (clamped chunk index; past the last chunk
+    // the commit fills the LDS buffer no product reads again), only the
+    // products are guarded, so the waits stay exact and the loads stay in
+    // flight across iterations.
+    constexpr int FD = PASSES == 1 ? 3 : 2;
+    F fq[FD][NB];
+    const int64_t last = nchunks > 0 ? nchunks - 1 : 0;
     if (nchunks > 0) {
       fetch(0);
       commit(0);
-      load(fr[0], 0);
+#pragma unroll
+      for (int u = 0; u < FD - 1; ++u) load(fq[u], u < last ? u : last);
     }
     __syncthreads();
-    for (int64_t ch = 0; ch < nchunks; ch += 2) {
-      {
-        const bool more = ch + 1 < nchunks;
-        if (more) {
-          fetch(ch + 1);
-          load(fr[1], ch + 1);
-        }
-        compute(fr[0], lds);
-        if (more) commit(1);
-        __syncthreads();
-      }
-      if (ch + 1 < nchunks) {
-        const bool more = ch + 2 < nchunks;
-        if (more) {
-          fetch(ch + 2);
-          load(fr[0], ch + 2);
-        }
-        compute(fr[1], lds + STAGE);
-        if (more) commit(0);
+    for (int64_t ch0 = 0; ch0 < nchunks; ch0 += FD) {
+#pragma unroll
+      for (int u = 0; u < FD; ++u) {
+        const int64_t ch = ch0 + u;
+        fetch(ch + 1 < last ? ch + 1 : last);
+        load(fq[(u + FD - 1) % FD], ch + FD - 1 < last ? ch + FD - 1 : last);
+        if (ch < nchunks) compute(fq[u], lds + (ch & 1) * STAGE);
+        commit((ch + 1) & 1);
         __syncthreads();
       }
     }
