@@ -223,6 +223,33 @@ constexpr int panel_lds_bytes() {
 // update GEMM, so C = kappa - F F(S_r,:)^T is formed in the registers.  r^2 =
 // |x|^2 + |y|^2 - 2 x.y, with the direct-difference fallback where it cancels
 // (as in k_dist).
+// Squared distance of two points given as e4m3 codes, d % 16 == 0: x from
+// LDS (4-byte aligned), y from global memory (16-byte aligned).  The
+// difference of two e4m3 values is exact in FP32 and the squares are summed in
+// FP32, so where the expanded form cancels this keeps the relative accuracy
+// of direct differences.  It reads the codes the products read, not the FP64
+// points, so a lane that takes it waits for 16-byte loads, not d scattered
+// 8-byte ones.
+__device__ __attribute__((always_inline)) inline float sqdist_e4m3(const unsigned* x, const unsigned char* y, int d) {
+  float s = 0.f;
+  for (int q = 0; q < d / 16; ++q) {
+    const u4 yv = *(const u4*)(y + 16 * q);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int xw = (int)x[4 * q + w], yw = (int)yv[w];
+      const float e0 = __builtin_amdgcn_cvt_f32_fp8(xw, 0) - __builtin_amdgcn_cvt_f32_fp8(yw, 0);
+      const float e1 = __builtin_amdgcn_cvt_f32_fp8(xw, 1) - __builtin_amdgcn_cvt_f32_fp8(yw, 1);
+      const float e2 = __builtin_amdgcn_cvt_f32_fp8(xw, 2) - __builtin_amdgcn_cvt_f32_fp8(yw, 2);
+      const float e3 = __builtin_amdgcn_cvt_f32_fp8(xw, 3) - __builtin_amdgcn_cvt_f32_fp8(yw, 3);
+      s = fmaf(e0, e0, s);
+      s = fmaf(e1, e1, s);
+      s = fmaf(e2, e2, s);
+      s = fmaf(e3, e3, s);
+    }
+  }
+  return s;
+}
+
 template <class Pol, int NCB, int MODE, int PASSES, bool DIST8 = false>
 __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
   using T = typename Pol::T;
@@ -543,8 +570,14 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_panel(PanelArgs a) {
           for (int nb = 0; nb < NB; ++nb) {
             const int64_t rr = row_w + 16 * nb + l16;
             float r2 = xn[nb] + y - 2.f * dp[nb][i];
-            if (__builtin_expect(r2 < frac * (xn[nb] + y), 0))   // cancellation: direct differences
-              r2 = (float)sqdist(a.X + (rr < N ? rr : N - 1) * dd, a.Xp + (int64_t)(c < s ? c : s - 1) * dd, dd);
+            if (__builtin_expect(r2 < frac * (xn[nb] + y), 0)) {   // cancellation: direct differences
+              // from the codes (the 13-block group, an override, keeps the
+              // FP64 points: the code form inlined there spills)
+              if constexpr (NCB <= 8)
+                r2 = sqdist_e4m3(rowsL + ((16 * nb + l16) * RS) / 4, a.Xp8 + (size_t)(c < s ? c : s - 1) * dd, dd);
+              else
+                r2 = (float)sqdist(a.X + (rr < N ? rr : N - 1) * dd, a.Xp + (int64_t)(c < s ? c : s - 1) * dd, dd);
+            }
             acc[nb][cb][i] = kappa_fast(r2 > 0.f ? r2 : 0.f, a.kf) - acc[nb][cb][i];
           }
         }
