@@ -38,8 +38,8 @@ PREC_BY_NAME = {v: k for k, v in W.PREC_NAMES.items()}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16", choices=sorted(PREC_BY_NAME))
     ap.add_argument("--workload", default="mixture", choices=["mixture", "laplace", "small", "sparse_hd"])
     ap.add_argument("--method", default="accel", choices=sorted(W.METHOD_NAMES.values()),
