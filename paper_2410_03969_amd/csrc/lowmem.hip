@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_lm_z(const double* __restrict__ W, int6
 // column l16 of the tile); the squares of each 64-column group are summed
 // over its four tiles and then across the 16 lanes of a row.  XR: the row's
 // coordinates in registers (d <= 16).
-template <bool XR>
+template <int XR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_lm_rows(const double* __restrict__ X, int d, KParams kp,
                                                  const double* __restrict__ XS, const double* __restrict__ Z,
                                                  int b, double* __restrict__ P, int64_t N, const RoundState* st) {
@@ -259,10 +259,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;   // this wavefront's 16 rows
   const int64_t myrow = row0 + l16;                          // the row whose kernel values this lane forms
   const double* xrow = X + (myrow < N ? myrow : N - 1) * d;
-  double xr[16];
-  if constexpr (XR) {
+  double xr[XR > 0 ? XR : 1];
+  if constexpr (XR > 0) {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) xr[t] = t < d ? xrow[t] : 0.0;
+    for (int t = 0; t < XR; ++t) xr[t] = t < d ? xrow[t] : 0.0;
   }
   rd4 acc[CT];
 #pragma unroll
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int e = tid + 256 * r, jj = e / LM_CS, m = e % LM_CS;
       zn[r] = (j0 + jj < kt && c0 + m < s) ? Z[(int64_t)(j0 + jj) * b + c0 + m] : 0.0;
     }
-    if constexpr (XR) {
+    if constexpr (XR > 0) {
 #pragma unroll
       for (int r = 0; r < XPT; ++r) {
         const int e = tid + 256 * r;
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int e = tid + 256 * r;
       zs[e / LM_CS][e % LM_CS] = zn[r];
     }
-    if constexpr (XR) {
+    if constexpr (XR > 0) {
 #pragma unroll
       for (int r = 0; r < XPT; ++r) {
         const int e = tid + 256 * r;
@@ -310,14 +310,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __syncthreads();
     if (j0 + LM_JC < kt) fetch(j0 + LM_JC);
     // pivots past kt have zero rows of Z (their coordinates are staged as 0,
-    // so their kernel values are finite)
-#pragma unroll 1
-    for (int q = 0; q < LM_JC / 4; ++q) {
+    // so their kernel values are finite).  Each step's kernel value is
+    // formed one step ahead, so its arithmetic runs beside the previous
+    // step's products instead of in front of its own.
+    auto kval = [&](int q) __attribute__((always_inline)) {
       const double* xp = xs + (4 * q + g) * d;
       double r2 = 0.0;
-      if constexpr (XR) {
+      if constexpr (XR > 0) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
+        for (int t = 0; t < XR; ++t)
           if (t < d) {
             const double e = xr[t] - xp[t];
             r2 += e * e;
@@ -328,10 +329,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           r2 += e * e;
         }
       }
-      const double kv = kappa_r2(r2, kp);
+      return kappa_r2(r2, kp);
+    };
+    double kv = kval(0);
+#pragma unroll
+    for (int q = 0; q < LM_JC / 4; ++q) {
+      const double kvn = q + 1 < LM_JC / 4 ? kval(q + 1) : 0.0;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
         acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, zs[4 * q + g][16 * ct + l16], acc[ct], 0, 0, 0);
+      kv = kvn;
     }
   }
   // |G(row, group)|^2 for the slice's 64-column groups
@@ -454,9 +461,10 @@ void lm_round(hipStream_t s, const arpc_problem& p, const KParams& kp, const Uni
   prof.begin(ARPC_KC_COLGEMM);
   const dim3 grows((unsigned)((N + 63) / 64), (unsigned)((b + LM_CS - 1) / LM_CS));
   if (d <= 16)
-    hipLaunchKernelGGL(k_lm_rows<true>, grows, dim3(256), 0, s, X, d, kp, XS, Z, b, P, N, st);
+    if (d <= 8) hipLaunchKernelGGL(k_lm_rows<8>, grows, dim3(256), 0, s, X, d, kp, XS, Z, b, P, N, st);
+    else hipLaunchKernelGGL(k_lm_rows<16>, grows, dim3(256), 0, s, X, d, kp, XS, Z, b, P, N, st);
   else
-    hipLaunchKernelGGL(k_lm_rows<false>, grows, dim3(256), 0, s, X, d, kp, XS, Z, b, P, N, st);
+    hipLaunchKernelGGL(k_lm_rows<0>, grows, dim3(256), 0, s, X, d, kp, XS, Z, b, P, N, st);
   prof.end();
   prof.begin(ARPC_KC_DIAG);
   launch_diag(s, u, csum, P, LM_CG, N, nch, st);
