@@ -178,30 +178,12 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(RoundJob j0, const RoundJo
 // index with u_j > 0 (in the last positive chunk) is taken.
 constexpr int PROPOSE_WAVES = 4;
 
-template <bool TAB>
-__global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(RoundJob j0, const RoundJob* __restrict__ tab) {
-  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
-  const double* __restrict__ u = RJ.u;
-  const double* __restrict__ cpre = RJ.cpre;
-  const int64_t nchunks = RJ.nchunks, N = RJ.N;
-  const int b = RJ.b;
-  const Unif un = ldc(RJ.un);
-  const RoundState* st = RJ.st;
-  int64_t* __restrict__ props = RJ.props;
-  if (st->status != ST_RUNNING) return;
-  const int lane = threadIdx.x & 63;
-  const int l = blockIdx.x * PROPOSE_WAVES + (threadIdx.x >> 6);
-  if (l >= b) return;
-  const double T = st->T;
-  const double x = stream_uniform(un, 2 * (int64_t)b * st->round + l) * T;
-  // first chunk whose inclusive prefix exceeds x
-  int64_t lo = 0, hi = nchunks;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (cpre[mid] > x) hi = mid; else lo = mid + 1;
-  }
-  const int64_t c = (lo < nchunks) ? lo : (int64_t)st->lastpos;
-  const double base = (c > 0) ? cpre[c - 1] : 0.0;
+// Draw l inside chunk c: the smallest j whose running sum (base + the sums of
+// the chunk's entries before it) exceeds x, else the last index with u_j > 0
+// in the chunk.  One wavefront; lane 0 stores props[l].
+__device__ __attribute__((always_inline)) inline void draw_in_chunk(const double* __restrict__ u, int64_t N, int64_t c,
+                                                                    double base, double x, int lane, int l,
+                                                                    int64_t* __restrict__ props) {
   // lane l owns elements [16 lane, 16 lane + 16) of the chunk
   const int64_t e0 = c * CHUNK + 16 * lane;
   double v[16];
@@ -240,6 +222,122 @@ __global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(RoundJob j0, con
   }
   pick = pick < 0 ? 0 : (pick >= N ? N - 1 : pick);
   if (lane == 0) props[l] = pick;
+}
+
+template <bool TAB>
+__global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const double* __restrict__ cpre = RJ.cpre;
+  const int64_t nchunks = RJ.nchunks;
+  const int b = RJ.b;
+  const Unif un = ldc(RJ.un);
+  const RoundState* st = RJ.st;
+  if (st->status != ST_RUNNING) return;
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * PROPOSE_WAVES + (threadIdx.x >> 6);
+  if (l >= b) return;
+  const double T = st->T;
+  const double x = stream_uniform(un, 2 * (int64_t)b * st->round + l) * T;
+  // first chunk whose inclusive prefix exceeds x
+  int64_t lo = 0, hi = nchunks;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (cpre[mid] > x) hi = mid; else lo = mid + 1;
+  }
+  const int64_t c = (lo < nchunks) ? lo : (int64_t)st->lastpos;
+  draw_in_chunk(RJ.u, RJ.N, c, (c > 0) ? cpre[c - 1] : 0.0, x, lane, l, RJ.props);
+}
+
+// k_scan_chunks and k_propose in one launch, for up to PS_MAXCH chunks: every
+// workgroup forms the inclusive prefix of the chunk sums in its LDS (thread t
+// sums a contiguous run of chunks, then the 256 run totals are scanned; the
+// same fixed order in every workgroup, so all of them hold the same prefix
+// and the same T), and its proposals search it there instead of in global
+// memory.  Workgroup 0 records T and the last positive chunk, and the early
+// stop (T <= 0) or the exhausted explicit stream as k_scan_chunks does.
+constexpr int PS_MAXCH = 4096;
+
+template <bool TAB>
+__global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose_scan(RoundJob j0, const RoundJob* __restrict__ tab) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const double* __restrict__ csum = RJ.csum;
+  const int64_t nch = RJ.nchunks;
+  const int b = RJ.b;
+  const Unif un = ldc(RJ.un);
+  RoundState* st = RJ.st;
+  if (st->status != ST_RUNNING) return;
+  if ((int)blockIdx.x * PROPOSE_WAVES >= b) return;   // uniform: a table's grid fits its largest b
+  constexpr int NT = 64 * PROPOSE_WAVES;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t round = st->round;
+  if (un.U && 2 * (int64_t)b * (round + 1) > un.nU) {   // uniform
+    if (blockIdx.x == 0 && tid == 0) st->status = ST_NOUNIF;
+    return;
+  }
+  __shared__ double pre[PS_MAXCH];
+  __shared__ double wsum[PROPOSE_WAVES];
+  __shared__ int lsh[PROPOSE_WAVES];
+  const int per = (int)((nch + NT - 1) / NT);
+  const int cb = tid * per;
+  double v = 0.0;
+  int lastp = -1;
+  for (int i = 0; i < per; ++i) {
+    const int c = cb + i;
+    if (c < nch) {
+      const double x = csum[c];
+      v += x;
+      pre[c] = v;
+      if (x > 0.0) lastp = c;
+    }
+  }
+  const double incl = wave_incl_scan(v);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int t = __shfl_xor(lastp, o, 64);
+    lastp = t > lastp ? t : lastp;
+  }
+  if (lane == 63) wsum[w] = incl;
+  if (lane == 0) lsh[w] = lastp;
+  double lane_excl = __shfl_up(incl, 1, 64);   // the run totals of the lanes before this one
+  if (lane == 0) lane_excl = 0.0;
+  __syncthreads();
+  double woff = 0.0;
+  int lastpos = -1;
+#pragma unroll
+  for (int q = 0; q < PROPOSE_WAVES; ++q) {
+    if (q < w) woff += wsum[q];
+    lastpos = lsh[q] > lastpos ? lsh[q] : lastpos;
+  }
+  const double excl = woff + lane_excl;
+  for (int i = 0; i < per; ++i) {
+    const int c = cb + i;
+    if (c < nch) pre[c] += excl;
+  }
+  __syncthreads();
+  // T is the prefix's last entry, so a draw below T always finds its chunk
+  const double T = pre[nch - 1];
+  if (!(T > 0.0) || lastpos < 0) {   // uniform
+    if (blockIdx.x == 0 && tid == 0) {
+      st->T = T;
+      st->lastpos = lastpos;
+      st->status = ST_EARLY;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    st->T = T;
+    st->lastpos = lastpos;
+  }
+  const int l = blockIdx.x * PROPOSE_WAVES + w;
+  if (l >= b) return;
+  const double x = stream_uniform(un, 2 * (int64_t)b * round + l) * T;
+  int lo = 0, hi = (int)nch;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] > x) hi = mid; else lo = mid + 1;
+  }
+  const int64_t c = (lo < nch) ? lo : lastpos;
+  draw_in_chunk(RJ.u, RJ.N, c, (c > 0) ? pre[c - 1] : 0.0, x, lane, l, RJ.props);
 }
 
 // ------------------------------------------------------- gathers at proposals
@@ -1429,6 +1527,10 @@ void round_grid_max(RoundGrid& g, const RoundGrid& o) {
 }
 
 void launch_propose_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g) {
+  if (g.diag <= (unsigned)PS_MAXCH) {   // g.diag: the largest chunk count of the table
+    hipLaunchKernelGGL(k_propose_scan<true>, dim3(g.propose, n), dim3(64 * PROPOSE_WAVES), 0, s, RoundJob{}, tab);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_chunks<true>, dim3(1, n), dim3(1024), 0, s, RoundJob{}, tab);
   hipLaunchKernelGGL(k_propose<true>, dim3(g.propose, n), dim3(64 * PROPOSE_WAVES), 0, s, RoundJob{}, tab);
 }
