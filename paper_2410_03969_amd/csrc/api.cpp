@@ -297,8 +297,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
   }
   if (l.ncbt > 0) {  // BF16 modes: one kernel for the update GEMM, the solve and the stores
     prof.begin(ARPC_KC_PREP);
-    launch_prep_xp_tab(s, tab, 1, p.b * p.d);
-    launch_fused_prep_tab(s, gemm_prec(p.prec), tab, 1, l.ncbt);
+    launch_fused_prep_tab(s, gemm_prec(p.prec), tab, 1, l.ncbt, p.b * p.d);
     prof.end();
     prof.begin(ARPC_KC_COLGEMM);
     launch_fused_round_tab(s, gemm_prec(p.prec), l.ncbt, d, hj.fa, tab, 1, fused_grid_of(gemm_prec(p.prec), hj.fa, l.grid));

@@ -436,6 +436,21 @@ __device__ __attribute__((always_inline)) inline void linv_blocks_ahead(const do
   }
 }
 
+// Accepted points Xp(j, :) = X(S_r(j), :), element q = j d + t taken by
+// virtual workgroup vb of vg (256 threads each): one element per thread,
+// since each is a chain of three dependent loads.
+__device__ __attribute__((always_inline)) inline void prep_xp_range(ConstRoundJob& RJ, int s, int vb, int vg) {
+  const int32_t* __restrict__ acc = RJ.acc;
+  const int64_t* __restrict__ props = RJ.props;
+  const double* __restrict__ X = RJ.X;
+  const int d = RJ.d;
+  double* __restrict__ Xp = RJ.Xp;
+  for (int q = vb * 256 + (int)threadIdx.x; q < s * d; q += vg * 256) {
+    const int j = q / d, t = q % d;
+    Xp[q] = X[props[acc[j]] * d + t];
+  }
+}
+
 // Squared distance by direct differences (a point paired with itself gives 0).
 __device__ __attribute__((always_inline)) inline double sqdist(const double* __restrict__ x, const double* __restrict__ y, int d) {
   double s = 0.0;

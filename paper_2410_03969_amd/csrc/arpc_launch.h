@@ -51,6 +51,7 @@ void launch_propose_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGr
 void launch_gather_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g, bool fdouble, bool tiled);
 void launch_reject_tab(hipStream_t s, const RoundJob* tab, int n, int bmax);
 void launch_prep_xp_tab(hipStream_t s, const RoundJob* tab, int n, int64_t bd);   // bd: the largest b d
+unsigned prep_xp_blocks(int64_t bd);   // its workgroups: one element per thread
 void launch_diag_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGrid& g);
 void launch_finish_tab(hipStream_t s, const RoundJob* tab, int n);
 // *dst = j by a kernel (graph-capturable; j need not outlive the call).

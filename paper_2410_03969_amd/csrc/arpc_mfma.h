@@ -66,11 +66,12 @@ size_t fused_operand_bytes(int prec, int64_t kmax, int b);
 // its persistent grid given two workgroups per compute unit (grid2).
 FusedArgs fused_args_of(int prec, const FusedRound& r, const RoundState* st);
 int fused_grid_of(int prec, const FusedArgs& a, int grid2);
-// F(S_r,:)^T chunks and the permuted inverse factor, then the round product,
-// over a device table of n jobs with the same mode and column-block count
-// (and, for the product, the same coordinate class d <= 8 or <= 16 and the
-// same kernel form as `any`); grid: workgroups per job.
-void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, int ncbt);
+// F(S_r,:)^T chunks, the permuted inverse factor and the accepted points (one
+// launch; bd: the largest b d of the table), then the round product, over a
+// device table of n jobs with the same mode and column-block count (and, for
+// the product, the same coordinate class d <= 8 or <= 16 and the same kernel
+// form as `any`); grid: workgroups per job.
+void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, int ncbt, int64_t bd);
 void launch_fused_round_tab(hipStream_t s, int prec, int ncbt, int d, const FusedArgs& any, const RoundJob* tab,
                             int n, int grid);
 

@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "arpc_common.h"
+#include "arpc_launch.h"
 #include "arpc_mfma.h"
 
 namespace arpc {
@@ -602,22 +603,19 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   }
 }
 
-// Bm1 chunk j, column c: the blocked slice of F at row S_r(c) (zero for c >= s).
-template <int SPL, bool TAB>
-__global__ __launch_bounds__(256) void k_fused_bm1(RoundJob j0, const RoundJob* __restrict__ tab) {
-  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+// Bm1 chunk j, column c: the blocked slice of F at row S_r(c) (zero for c >=
+// s), 16-byte pieces taken by virtual workgroup vb of vg.
+template <int SPL>
+__device__ __attribute__((always_inline)) inline void bm1_range(ConstRoundJob& RJ, int s, int64_t kr, int vb, int vg) {
   const __bf16* __restrict__ Fb = (const __bf16*)RJ.Fb;
   const int64_t nkc = RJ.nkc;
   const int64_t* __restrict__ props = RJ.props;
   const int32_t* __restrict__ acc = RJ.acc;
   const int CP = RJ.CP;
   unsigned char* __restrict__ Bm1 = RJ.Bm1;
-  const RoundState* st = RJ.st;
-  if (st->status != ST_RUNNING) return;
-  const int s = st->s_r;
-  const int64_t nk = (st->k_r + FKC - 1) / FKC;
+  const int64_t nk = (kr + FKC - 1) / FKC;
   const int64_t per_chunk = (int64_t)SPL * CP * 4;  // 16-byte pieces
-  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nk * per_chunk; o += (int64_t)gridDim.x * 256) {
+  for (int64_t o = (int64_t)vb * 256 + threadIdx.x; o < nk * per_chunk; o += (int64_t)vg * 256) {
     const int64_t j = o / per_chunk;
     const int rem = (int)(o % per_chunk);
     const int plane = rem / (CP * 4), c = (rem / 4) % CP, q = rem & 3;
@@ -631,20 +629,14 @@ __global__ __launch_bounds__(256) void k_fused_bm1(RoundJob j0, const RoundJob* 
 }
 
 // Inverse of the s x s lower factor L (read from H through the accepted
-// indices), one workgroup per column t: block forward substitution from the
+// indices), column t by one workgroup: block forward substitution from the
 // blocks' inverses that the tiled rejection kernel leaves in H (b <= 256 here),
 // then Linv(i, t) stored at chunk t / 32, slot solve_slot(t % 32), column i
 // (zero outside i, t < s and below the diagonal).
-template <int SPL, bool RES, bool TAB>
-__global__ __launch_bounds__(256) void k_fused_linv(RoundJob j0, const RoundJob* __restrict__ tab) {
-  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+template <int SPL, bool RES>
+__device__ __attribute__((always_inline)) inline void linv_column_to_bm2(ConstRoundJob& RJ, int s, int c) {
   const int CP = RJ.CP;
   unsigned char* __restrict__ Bm2 = RJ.Bm2;
-  const RoundState* st = RJ.st;
-  if ((int)blockIdx.x >= RJ.nt * FKC) return;
-  if (st->status != ST_RUNNING) return;
-  const int s = st->s_r;
-  const int c = blockIdx.x;
   const int tid = threadIdx.x;
   __shared__ double x[256];
   __shared__ double xp[256];   // proposal-indexed column
@@ -671,6 +663,27 @@ __global__ __launch_bounds__(256) void k_fused_linv(RoundJob j0, const RoundJob*
       *(__bf16*)base = hi;
       if (SPL == 2) *(__bf16*)(base + (size_t)CP * FGROW) = lo;
     }
+  }
+}
+
+// The round product's operands in one launch, in three ranges of workgroups:
+// [0, nl) the inverse factor (a column each), [nl, nl + nb) the Bm1 chunks,
+// [nl + nb, ...) the accepted points.  The three read only the rejection
+// step's outputs and write disjoint buffers.
+template <int SPL, bool RES, bool TAB>
+__global__ __launch_bounds__(256) void k_fused_prep(RoundJob j0, const RoundJob* __restrict__ tab, int nl, int nb,
+                                                    int nx) {
+  ConstRoundJob& RJ = job_of<TAB>(j0, tab);
+  const RoundState* st = RJ.st;
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int v = blockIdx.x;
+  if (v < nl) {
+    if (v < RJ.nt * FKC) linv_column_to_bm2<SPL, RES>(RJ, s, v);   // uniform
+  } else if (v < nl + nb) {
+    bm1_range<SPL>(RJ, s, st->k_r, v - nl, nb);
+  } else {
+    prep_xp_range(RJ, s, v - nl - nb, nx);
   }
 }
 
@@ -771,15 +784,13 @@ int fused_grid_of(int prec, const FusedArgs& a, int grid2) {
   return g > a.ntiles ? a.ntiles : (g < 1 ? 1 : g);
 }
 
-void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, int ncbt) {
-  const int nt = (ncbt + 1) / 2;
-  if (prec == 2) {
-    hipLaunchKernelGGL((k_fused_bm1<2, true>), dim3(512, n), dim3(256), 0, s, RoundJob{}, tab);
-    hipLaunchKernelGGL((k_fused_linv<2, false, true>), dim3(nt * FKC, n), dim3(256), 0, s, RoundJob{}, tab);
-  } else {
-    hipLaunchKernelGGL((k_fused_bm1<1, true>), dim3(512, n), dim3(256), 0, s, RoundJob{}, tab);
-    hipLaunchKernelGGL((k_fused_linv<1, true, true>), dim3(nt * FKC, n), dim3(256), 0, s, RoundJob{}, tab);
-  }
+void launch_fused_prep_tab(hipStream_t s, int prec, const RoundJob* tab, int n, int ncbt, int64_t bd) {
+  const int nl = (ncbt + 1) / 2 * FKC, nb = 512, nx = (int)prep_xp_blocks(bd);
+  const dim3 grid((unsigned)(nl + nb + nx), (unsigned)n);
+  if (prec == 2)
+    hipLaunchKernelGGL((k_fused_prep<2, false, true>), grid, dim3(256), 0, s, RoundJob{}, tab, nl, nb, nx);
+  else
+    hipLaunchKernelGGL((k_fused_prep<1, true, true>), grid, dim3(256), 0, s, RoundJob{}, tab, nl, nb, nx);
 }
 
 void launch_fused_round_tab(hipStream_t s, int prec, int ncbt, int d, const FusedArgs& any, const RoundJob* tab,

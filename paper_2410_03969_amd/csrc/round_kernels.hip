@@ -1596,22 +1596,13 @@ void launch_diag(hipStream_t s, double* u, double* csum, const double* P, int pa
 template <bool TAB>
 __global__ __launch_bounds__(256) void k_prep_xp(RoundJob j0, const RoundJob* __restrict__ tab) {
   ConstRoundJob& RJ = job_of<TAB>(j0, tab);
-  const int32_t* __restrict__ acc = RJ.acc;
-  const int64_t* __restrict__ props = RJ.props;
-  const double* __restrict__ X = RJ.X;
-  const int d = RJ.d;
-  double* __restrict__ Xp = RJ.Xp;
   const RoundState* st = RJ.st;
   if (st->status != ST_RUNNING) return;
-  const int s = st->s_r;
-  for (int q = blockIdx.x * 256 + threadIdx.x; q < s * d; q += gridDim.x * 256) {
-    const int j = q / d, t = q % d;
-    Xp[q] = X[props[acc[j]] * d + t];
-  }
+  prep_xp_range(RJ, st->s_r, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // one element per thread (the gather is a chain of three dependent loads)
-static unsigned prep_xp_blocks(int64_t bd) {
+unsigned prep_xp_blocks(int64_t bd) {
   const int64_t g = (bd + 255) / 256;
   return (unsigned)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }

@@ -219,12 +219,10 @@ bool arpc_ctx_s::launch_tick() {
   std::stable_sort(t.jobs.begin(), t.jobs.end(), [&](ServedJob* a, ServedJob* b) { return key(a) < key(b); });
   RoundGrid g{};
   int bmax = 1;
-  int64_t bdmax = 1;
   for (int i = 0; i < n; ++i) {
     t.htab[i] = t.jobs[i]->run->row();
     round_grid_max(g, round_grid_of(t.htab[i]));
     if (t.htab[i].b > bmax) bmax = t.htab[i].b;
-    bdmax = std::max(bdmax, (int64_t)t.htab[i].b * t.htab[i].d);
   }
   hipStream_t s = ts;
   if (hipMemcpyAsync(t.dtab, t.htab, sizeof(RoundJob) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -232,14 +230,15 @@ bool arpc_ctx_s::launch_tick() {
   launch_propose_tab(s, t.dtab, n, g);
   launch_gather_tab(s, t.dtab, n, g, false, false);
   launch_reject_tab(s, t.dtab, n, bmax);
-  launch_prep_xp_tab(s, t.dtab, n, bdmax);
-  for (int i0 = 0; i0 < n;) {   // per mode: the inverse factor and F(S_r,:)^T chunks
+  for (int i0 = 0; i0 < n;) {   // per mode: the inverse factor, F(S_r,:)^T chunks, accepted points
     int i1 = i0, ncbt = 0;
+    int64_t bd = 1;
     while (i1 < n && t.jobs[i1]->p.prec == t.jobs[i0]->p.prec) {
       ncbt = std::max(ncbt, t.jobs[i1]->l.ncbt);
+      bd = std::max(bd, (int64_t)t.htab[i1].b * t.htab[i1].d);
       ++i1;
     }
-    launch_fused_prep_tab(s, gemm_prec(t.jobs[i0]->p.prec), t.dtab + i0, i1 - i0, ncbt);
+    launch_fused_prep_tab(s, gemm_prec(t.jobs[i0]->p.prec), t.dtab + i0, i1 - i0, ncbt, bd);
     i0 = i1;
   }
   for (int i0 = 0; i0 < n;) {   // per compiled shape: the round product
