@@ -144,8 +144,12 @@ arpc_status arpc_workspace_size(const arpc_problem* problem, size_t* bytes);
  * keyed by problem->seed (block q of four words at counter q+1, uniform =
  * (word >> 11) * 2^-53).
  *
- * Blocks the calling thread until the factorization is complete (the host
- * checks the device-side round state between batches of rounds).  Returns
+ * Blocks the calling thread until the factorization is complete.  The host
+ * reads the device-side round state back after the rejection step of the
+ * last round of each batch and enqueues the next rounds, or the end of the
+ * run, while that round finishes, so the stream does not drain between
+ * rounds.  Uses a pinned host buffer per calling thread (a few KB, grown to
+ * the round history's size, kept until the process ends).  Returns
  * ARPC_OK, or ARPC_EARLY_STOP when the residual trace reached zero or a round
  * accepted nothing; then columns k_out..k-1 of F are zero and
  * pivots[k_out..k-1] = -1.  Errors: ARPC_EINVAL, ARPC_ENUMERIC (non-finite
