@@ -80,6 +80,18 @@ def test_small_workload_fp64():
     print(f"relF={err:.2e} rounds={st['rounds']}")
 
 
+def test_more_chunks_than_the_one_launch_proposal_form():
+    """N = 4.3e6 gives 4200 chunk sums, past the 4096 that the one-launch
+    proposal kernel stages in LDS, so the proposals take the two-launch form
+    (prefix in global memory); FP64 parity as everywhere else."""
+    rng = np.random.default_rng(11)
+    N = 4_300_000
+    X = rng.random((N, 3))
+    prob = W.Problem(N=N, d=3, k=16, b=8, kernel=W.GAUSSIAN, sigma=0.5, seed=5)
+    F, piv, out = gpu_factor(X, prob)
+    assert_parity(F, piv, out, oracle_run(X, prob))
+
+
 def test_block_size_one():
     rng = np.random.default_rng(1)
     X = rng.random((1500, 2))
