@@ -1,4 +1,4 @@
-// C ABI and host driver of the accelerated RPCholesky library.
+// C ABI and host code of the accelerated RPCholesky library.
 //
 // arpc_factor validates the problem, carves the caller's workspace, and
 // enqueues rounds of Alg. 2 (each: proposals, residual submatrix,
@@ -564,7 +564,7 @@ arpc_status check_factor_args(const arpc_problem* p, const double* X, const void
 
 namespace arpc {
 
-// Pinned host memory for the synchronous driver's read-backs, one buffer per
+// Pinned host memory for the synchronous form's read-backs, one buffer per
 // host thread, grown on demand and held until the process ends (a release at
 // exit could run after the runtime has been torn down).
 static char* sync_staging(size_t bytes) {

@@ -1,4 +1,4 @@
-// Internal definitions shared by the kernels and the host driver of the
+// Internal definitions shared by the kernels and the host code of the
 // accelerated RPCholesky library (not part of the public ABI).
 #pragma once
 

@@ -1,4 +1,4 @@
-// Host-side driver types shared by the factorization entry points and the
+// Host-side types shared by the factorization entry points and the
 // serving scheduler (internal).
 #pragma once
 
@@ -101,7 +101,7 @@ struct JobBase {
   virtual arpc_status finish(arpc_stats* stats, double ms_total) = 0;
   virtual arpc_status finish_enqueue(const RoundState& h, double* htrace) = 0;
   virtual arpc_status finish_stats(const RoundState& h, double trace_resid, arpc_stats* stats) = 0;
-  // synchronous driver: the end of the run (residual trace, zero tails)
+  // synchronous form: the end of the run (residual trace, zero tails)
   // followed by one copy of the state, trace and round history
   // (end_read_bytes) into host memory
   virtual size_t end_read_bytes() const = 0;

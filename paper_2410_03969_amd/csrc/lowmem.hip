@@ -1,5 +1,5 @@
 // Accelerated RPCholesky, low-memory implementation (Alg. 3, Section 2.4):
-// the kernels and the host driver of arpc_factor_lowmem.
+// the kernels and the host code of arpc_factor_lowmem.
 //
 // No N x k factor is kept.  The state between rounds is the pivot list S,
 // their coordinates, the lower Cholesky factor L of A(S,S) (k x k, the
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_lm_append_l(double* __restrict__ L, int
   }
 }
 
-// ------------------------------------------------------------ host driver
+// ------------------------------------------------------------ host code
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct LmLayout {

@@ -1,5 +1,5 @@
-// Accelerated randomly pivoted QR (Alg. 5, Section 5): kernels and host
-// driver of arpc_qr_factor.
+// Accelerated randomly pivoted QR (Alg. 5, Section 5): kernels and the
+// host code of arpc_qr_factor.
 //
 // B is a dense M x N FP64 matrix (column-major).  A round proposes b columns
 // from the residual squared column norms u (the shared proposal kernels),

@@ -5,7 +5,7 @@
 // order whenever a slot is free and the job's workspace fits the unallocated
 // part of the budget, and retires a job as soon as it is finished, which
 // frees its slot and memory for the next one.  Each job is driven by the same
-// host driver as arpc_factor (make_job), so its kernels and results are those
+// host code as arpc_factor (make_job), so its kernels and results are those
 // of a factorization alone.  Jobs advance in one of two ways:
 //  - Ticks (the BF16 modes with the one-kernel round product: d <= 16 and
 //    b <= 256, or one product with d <= 32 and b <= 208).  Every such job's table row

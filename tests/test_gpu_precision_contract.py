@@ -6,7 +6,7 @@ relative trace errors are compared (accuracy measure of Section 1.4):
 1. from the factor: (tr A - |F|_F^2) / tr A, F as the run stored it;
 2. from the pivots alone: the Nystrom residual sum_j (A_jj - |L_S^{-1} A(S,j)|^2)
    of the pivot set, re-evaluated in FP64 by the oracle on the TRUE points
-   (so an FP8 run, which factors the e4m3-rounded points, is judged on the
+   (so an FP8 run, which factors the e4m3-rounded points, is measured on the
    matrix the user asked for), estimated on 20000 seeded rows, the same rows for
    both runs: N / n * sum over the sampled rows.
 
