@@ -342,6 +342,17 @@ FUSED_CASES = [(20, 3), (50, 8), (120, 12), (200, 8), (250, 16)]
 FUSED_TOL = {W.BF16X3: 2e-4, W.BF16: 5e-2}
 
 
+def assert_elementwise(F, ref, prec, label):
+    """Every sampled entry within 4 FUSED_TOL of the largest one.  A localized
+    mistake (one tile, one lane group, one store window) shifts a Frobenius
+    norm over many rows only a little, but moves its own entries by about
+    their size, and every entry is at most 1 here (|F(i,:)|^2 <= A_ii = 1)."""
+    emax = float(np.max(np.abs(F - ref)))
+    scale = float(np.max(np.abs(ref)))
+    print(f"  {label}: max entry error {emax:.3e} ({emax / scale:.3e} of the largest entry)")
+    assert emax <= 4 * FUSED_TOL[prec] * scale, (emax, scale)
+
+
 @pytest.mark.parametrize("prec", [W.BF16X3, W.BF16])
 @pytest.mark.parametrize("b,d", FUSED_CASES)
 def test_fused_round_factor_consistent_with_its_pivots(prec, b, d):
@@ -365,6 +376,7 @@ def test_fused_round_factor_consistent_with_its_pivots(prec, b, d):
     err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
     print(f"fused prec={prec} b={b} d={d} cols={ncols} relF={err:.3e}")
     assert err < FUSED_TOL[prec], err
+    assert_elementwise(F[rows, :ncols], ref, prec, f"fused prec={prec} b={b} d={d}")
     # the residual trace from the factor stays a valid bound
     trA = out["stats"]["trace_A"]
     assert np.sum(F ** 2) <= trA * (1 + 1e-3)
@@ -390,6 +402,7 @@ def test_fused_round_wide_points(prec, b, d):
     err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
     print(f"fused wide prec={prec} b={b} d={d} cols={ncols} relF={err:.3e}")
     assert err < FUSED_TOL[prec], err
+    assert_elementwise(F[rows, :ncols], ref, prec, f"fused wide prec={prec} b={b} d={d}")
     assert np.sum(F ** 2) <= out["stats"]["trace_A"] * (1 + 1e-3)
 
 
@@ -403,7 +416,17 @@ def test_wide_points_outside_the_one_kernel_form(prec, b, d):
     prob = W.Problem(N=3001, d=d, k=2 * b, b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=13, prec=prec)
     F, piv, out = gpu_factor(X, prob)
     assert out["stats"]["fused"] == 0
-    assert out["stats"]["k_out"] == prob.k
+    k_out = out["stats"]["k_out"]
+    assert k_out == prob.k and len(set(piv[:k_out].tolist())) == k_out
+    # the factor against the FP64 factor of its pivots, as for the one-kernel form
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
+    rows = np.concatenate([np.random.default_rng(2).choice(3001, 150, replace=False), np.arange(3001 - 40, 3001)])
+    ncols = min(k_out, 2 * b)
+    ref = factor_from_pivots(acc, piv[:ncols], rows=rows)
+    err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
+    print(f"two-kernel prec={prec} b={b} d={d} cols={ncols} relF={err:.3e}")
+    assert err < FUSED_TOL[prec], err
+    assert_elementwise(F[rows, :ncols], ref, prec, f"two-kernel prec={prec} b={b} d={d}")
 
 
 def test_fused_and_two_kernel_paths_agree_on_exact_matrix(monkeypatch):
@@ -469,3 +492,7 @@ def test_fp8_mode_factors_the_rounded_points(d):
     err_x = np.linalg.norm(F[rows, :ncols] - ref_x) / np.linalg.norm(ref_x)
     print(f"fp8 d={d}: relF vs rounded points {err_q:.3e}, vs unrounded {err_x:.3e}")
     assert err_q < 2e-2 and err_q < 0.25 * err_x
+    # every entry, as in assert_elementwise (FP8 mode: 4 x 2e-2 of the largest entry)
+    emax = float(np.max(np.abs(F[rows, :ncols] - ref_q)))
+    print(f"  fp8 d={d}: max entry error {emax:.3e}")
+    assert emax <= 4 * 2e-2 * float(np.max(np.abs(ref_q)))
