@@ -387,10 +387,14 @@ struct Job final : JobBase {
     HIPCHK(hipMemsetAsync(st, 0, sizeof(RoundState), s));
     launch_store_job(s, hj, (RoundJob*)(ws + l.jd));
     prof->begin(ARPC_KC_INIT);
-    if (p.prec == ARPC_FP8) launch_round_e4m3(s, Xin, (double*)(ws + l.Xq), p.N * p.d);
+    // FP8 mode: the rounded points (and, d % 4 == 0, their codes, norms and
+    // the non-finite flag in the same pass, so the initialisation scans none)
     if (l.packed)
-      launch_pack_e4m3(s, (const double*)(ws + l.Xq), p.N, (int)p.d, (unsigned*)(ws + l.X8), (float*)(ws + l.xn8));
-    launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, p.N, (int)p.d, kp, st, nch);
+      launch_round_pack_e4m3(s, Xin, p.N, (int)p.d, (double*)(ws + l.Xq), (unsigned*)(ws + l.X8),
+                             (float*)(ws + l.xn8), st);
+    else if (p.prec == ARPC_FP8)
+      launch_round_e4m3(s, Xin, (double*)(ws + l.Xq), p.N * p.d);
+    launch_init(s, (double*)(ws + l.u), (double*)(ws + l.csum), X, p.N, l.packed ? 0 : (int)p.d, kp, st, nch);
     prof->end();
     HIPCHK(hipGetLastError());
     return ARPC_OK;

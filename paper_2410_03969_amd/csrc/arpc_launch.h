@@ -13,6 +13,10 @@ void launch_init_from_diag(hipStream_t s, const double* u, int64_t N, double* cs
                            int64_t nchunks);
 // Xq = X with every coordinate rounded to FP8 e4m3 (the FP8 mode's points), n values.
 void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n);
+// The same rounding with the e4m3 codes and FP32 norms of the rows (d % 4 == 0)
+// and the non-finite flag in st, in one pass.
+void launch_round_pack_e4m3(hipStream_t s, const double* X, int64_t N, int d, double* Xq, unsigned* X8, float* xn,
+                            RoundState* st);
 void launch_propose(hipStream_t s, const double* u, const double* csum, double* cpre, int64_t nchunks,
                     int64_t N, int b, Unif un, RoundState* st, int64_t* props);
 // Partitions of the contraction index in the product F(S',:) F(S',:)^T of

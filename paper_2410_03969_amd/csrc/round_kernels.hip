@@ -88,6 +88,43 @@ __global__ __launch_bounds__(256) void k_round_e4m3(const double* __restrict__ X
     Xq[i] = round_e4m3(X[i]);
 }
 
+// The FP8 mode's setup in one pass over the points when d % 4 == 0: each row
+// rounded to e4m3 and stored in FP64, its codes packed four to a word with the
+// FP32 squared norm of the rounded row (the operands of the distances on the
+// FP8 matrix cores, summed in the same order as k_pack_e4m3), and any
+// non-finite coordinate flagged in the round state, so the initialisation
+// scans nothing.  One wavefront per row.
+__global__ __launch_bounds__(256) void k_round_pack_e4m3(const double* __restrict__ X, int64_t N, int d,
+                                                         double* __restrict__ Xq, unsigned* __restrict__ X8,
+                                                         float* __restrict__ xn, RoundState* st) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int dw = d / 4;
+  const double* x = X + row * d;
+  double* xq = Xq + row * d;
+  float s = 0.f;
+  bool bad = false;
+  for (int q = lane; q < dw; q += 64) {
+    double v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double a = x[4 * q + j];
+      bad |= !isfinite(a);
+      v[j] = round_e4m3(a);
+      xq[4 * q + j] = v[j];
+    }
+    int pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0], (float)v[1], 0, false);
+    pk = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2], (float)v[3], pk, true);
+    X8[row * dw + q] = (unsigned)pk;
+    s += (float)v[0] * (float)v[0] + (float)v[1] * (float)v[1] + (float)v[2] * (float)v[2] + (float)v[3] * (float)v[3];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) xn[row] = s;
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(&st->nonfinite, 1);
+}
+
 // Chunk sums of a residual diagonal u given by the caller (the squared column
 // norms in the QR method).
 __global__ __launch_bounds__(CHUNK) void k_chunk_sums(const double* __restrict__ u, int64_t N,
@@ -1418,6 +1455,11 @@ __global__ __launch_bounds__(1024) void k_trace(const double* __restrict__ csum,
 // ------------------------------------------------------------------ launchers
 void launch_trace(hipStream_t s, const double* csum, int64_t nchunks, double* out) {
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(1024), 0, s, csum, nchunks, out);
+}
+
+void launch_round_pack_e4m3(hipStream_t s, const double* X, int64_t N, int d, double* Xq, unsigned* X8, float* xn,
+                            RoundState* st) {
+  hipLaunchKernelGGL(k_round_pack_e4m3, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, X, N, d, Xq, X8, xn, st);
 }
 
 void launch_round_e4m3(hipStream_t s, const double* X, double* Xq, int64_t n) {

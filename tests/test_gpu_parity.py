@@ -280,6 +280,20 @@ def test_nonfinite_points_rejected():
         binding.factor(X, prob)
 
 
+@pytest.mark.parametrize("d,bad", [(8, np.nan), (8, np.inf), (3, -np.inf)])
+def test_nonfinite_points_rejected_fp8(d, bad):
+    """The FP8 mode flags non-finite coordinates while it rounds the points
+    (d % 4 == 0: in the same pass that packs the codes; else in the
+    initialisation's scan of the rounded copy)."""
+    from paper_2410_03969_amd import binding
+    rng = np.random.default_rng(21)
+    X = rng.random((3000, d))
+    X[2999, d - 1] = bad
+    prob = W.Problem(N=3000, d=d, k=40, b=10, kernel=W.GAUSSIAN, sigma=0.5, seed=2, prec=W.FP8)
+    with pytest.raises(RuntimeError, match="non-finite"):
+        binding.factor(X, prob)
+
+
 def test_fp32_mode_factor_consistent_with_its_pivots():
     """FP32 storage: the factor equals the exact FP64 factor of the pivots it
     chose, to FP32 accuracy, on sampled rows."""
