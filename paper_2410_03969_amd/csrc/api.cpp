@@ -102,6 +102,7 @@ Layout layout_of(const arpc_problem& p) {
   l.props = take(sizeof(int64_t) * p.b);
   l.acc = take(sizeof(int32_t) * p.b);
   l.Fs = take(sizeof(double) * p.b * p.k);
+  l.Fs32 = take(es == sizeof(float) ? sizeof(float) * p.b * fs32_ld(p.k) : 0);
   l.Hp = take(sizeof(double) * gather_splits(p.k) * p.b * p.b);
   l.H = take(sizeof(double) * p.b * p.b);
   l.Xp = take(sizeof(double) * p.b * p.d);
@@ -238,6 +239,7 @@ RoundJob round_job_of(const arpc_problem& p, const Layout& l, char* ws, const do
   j.part_cols = l.part_cols;
   j.F = F;
   j.Fs = (double*)(ws + l.Fs);
+  j.Fs32 = elem_size(p.prec) == sizeof(float) ? (float*)(ws + l.Fs32) : nullptr;
   j.ldf = k;
   j.Hp = (double*)(ws + l.Hp);
   j.parts = gather_splits(k);

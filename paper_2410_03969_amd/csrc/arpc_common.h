@@ -194,6 +194,7 @@ struct RoundJob {
   int part_cols;          // columns per partial row-norm group of P
   const void* F;          // N x k column-major factor (FP64 or FP32)
   double* Fs;             // F rows at the proposals, FP64, ld ldf
+  float* Fs32;            // the same rows in FP32 (F stored in FP32), else null; ld fs32_ld(ldf)
   int64_t ldf;
   double* Hp;             // partial products of F(S',:) F(S',:)^T
   int64_t W;              // contraction columns per partition of Hp
@@ -210,6 +211,10 @@ struct RoundJob {
   int nt;                 // 32-column chunks of the inverse factor
   FusedArgs fa;
 };
+
+// Leading dimension of the FP32 copy of F(S',:): a multiple of four, so four
+// consecutive entries of a row are one aligned 16-byte load.
+__host__ __device__ inline int64_t fs32_ld(int64_t ldf) { return (ldf + 3) & ~(int64_t)3; }
 
 // A table row read as kernel arguments are: through the constant address
 // space, so the compiler uses scalar loads into scalar registers (the table

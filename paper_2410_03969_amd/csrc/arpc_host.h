@@ -21,7 +21,7 @@ constexpr size_t kTraceOff = 128;
 
 // Offsets of the buffers carved from one factorization's workspace.
 struct Layout {
-  size_t st, jd, u, csum, cpre, props, acc, hist, Fs, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, Xp8,
+  size_t st, jd, u, csum, cpre, props, acc, hist, Fs, Fs32, Hp, H, Xp, Bt, Bt2, Bm1, Bm2, Fb, C, C0, P, Xq, X8, xn8, Xp8,
       ypn, trace, total;
   bool dist;  // kernel columns precomputed on the matrix cores (two-kernel path, d > 16 or FP8 mode)
   bool packed;  // FP8 mode, d % 4 == 0: the points also as e4m3 codes (X8) with their norms (xn8)

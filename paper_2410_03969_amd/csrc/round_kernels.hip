@@ -380,7 +380,9 @@ __global__ __launch_bounds__(64 * PROPOSE_WAVES) void k_propose_scan(RoundJob j0
 // ------------------------------------------------------- gathers at proposals
 typedef double rd4 __attribute__((ext_vector_type(4)));
 
-// Fs(i, c) = F(props_i, c) in FP64, row-major with leading dimension ldf;
+// Fs(i, c) = F(props_i, c) in FP64, row-major with leading dimension ldf
+// (and the same rows in FP32 into Fs32 where F is stored in FP32: the product
+// term of H reads those, half the bytes, with no rounding);
 // ceil(kmax / 256) workgroups per proposal.
 template <typename T, bool TAB>
 __global__ __launch_bounds__(256) void k_gather_rows(RoundJob j0, const RoundJob* __restrict__ tab) {
@@ -397,7 +399,9 @@ __global__ __launch_bounds__(256) void k_gather_rows(RoundJob j0, const RoundJob
   const int i = (int)(blockIdx.x / gx);
   const int64_t c = (int64_t)(blockIdx.x % gx) * 256 + threadIdx.x;
   if (c >= kr) return;
-  Fs[(int64_t)i * ldf + c] = (double)F[c * N + props[i]];
+  const T v = F[c * N + props[i]];
+  Fs[(int64_t)i * ldf + c] = (double)v;
+  if constexpr (sizeof(T) == sizeof(float)) RJ.Fs32[(int64_t)i * fs32_ld(ldf) + c] = v;
 }
 
 // H = A(S',S') - F(S',:) F(S',:)^T (Alg. 2 step 2), FP64, column-major b x b
@@ -406,18 +410,26 @@ __global__ __launch_bounds__(256) void k_gather_rows(RoundJob j0, const RoundJob
 // (x, y, p) with x <= y forms the 16 x 16 tile of rows 16 y .., columns
 // 16 x .. of partition p's partial product and writes it and its transpose
 // into Hp(p) (workgroups above the diagonal have nothing to do).  Wavefront w
-// contracts the 16-column chunks w, w + 4, .. of the partition as four
-// 16x16x4 products (lane (g, l16) holds row l16 at column c + 4 g + m of
-// product m); the four partial tiles are then added in wavefront order, so
-// the result does not depend on scheduling, and a diagonal tile takes every
+// of eight contracts the 16-column chunks w, w + 8, .. of the partition as
+// four 16x16x4 products (lane (g, l16) holds row l16 at column c + 4 g + m of
+// product m), so each wavefront's chain of dependent products stays short; the
+// eight partial tiles are then added in wavefront order, so the result does
+// not depend on scheduling, and a diagonal tile takes every
 // entry from its lower half, so each Hp(p), and H, is exactly symmetric.
-// The split keeps enough workgroups busy at any k_r.
-template <bool TAB>
-__global__ __launch_bounds__(256) void k_gather_Hp(RoundJob jb0, const RoundJob* __restrict__ tab) {
+// The split keeps enough workgroups busy at any k_r.  The cache-line requests
+// of the row loads, not the products, set the kernel's pace: where F is
+// stored in FP32 (FT = float) the rows come from their FP32 copy, whose
+// leading dimension is a multiple of four, so a lane's four columns of a chunk
+// are one 16-byte load (FP32 products are exact in FP64).
+constexpr int HP_WAVES = 8;
+template <bool TAB, typename FT>
+__global__ __launch_bounds__(64 * HP_WAVES) void k_gather_Hp(RoundJob jb0, const RoundJob* __restrict__ tab) {
   ConstRoundJob& RJ = job_of<TAB>(jb0, tab);
   const int b = RJ.b;
-  const double* __restrict__ Fs = RJ.Fs;
-  const int64_t ldf = RJ.ldf, W = RJ.W;
+  const FT* __restrict__ Fs;
+  if constexpr (sizeof(FT) == sizeof(float)) Fs = RJ.Fs32;
+  else Fs = RJ.Fs;
+  const int64_t ldf = sizeof(FT) == sizeof(float) ? fs32_ld(RJ.ldf) : RJ.ldf, W = RJ.W;
   double* __restrict__ Hp = RJ.Hp;
   const RoundState* st = RJ.st;
   // workgroup (x, y, z) of an nb x nb x parts grid, folded into blockIdx.x
@@ -432,53 +444,85 @@ __global__ __launch_bounds__(256) void k_gather_Hp(RoundJob jb0, const RoundJob*
   const int64_t cend = (cbeg + W < kr) ? cbeg + W : kr;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const bool ai = i0 + l16 < b, bj = j0 + l16 < b;
-  const double* ar = Fs + (int64_t)(ai ? i0 + l16 : 0) * ldf;
-  const double* br = Fs + (int64_t)(bj ? j0 + l16 : 0) * ldf;
+  const FT* ar = Fs + (int64_t)(ai ? i0 + l16 : 0) * ldf;
+  const FT* br = Fs + (int64_t)(bj ? j0 + l16 : 0) * ldf;
   rd4 acc = {0.0, 0.0, 0.0, 0.0};
   int64_t c = cbeg + 16 * w;
   // four chunks of this wavefront at a time, their loads issued before the products
-  for (; c + 3 * 64 + 16 <= cend; c += 4 * 64) {
+  constexpr int CS = 16 * HP_WAVES;   // columns per step of all the wavefronts
+  for (; c + 3 * CS + 16 <= cend; c += 4 * CS) {
     double av[4][4], bv[4][4];
+    if constexpr (sizeof(FT) == sizeof(float)) {
+      // c is a multiple of 16 and the row starts 16-byte aligned
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        av[u][m] = ai ? ar[c + 64 * u + 4 * g + m] : 0.0;
-        bv[u][m] = bj ? br[c + 64 * u + 4 * g + m] : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const float4 a4 = *reinterpret_cast<const float4*>(ar + c + CS * u + 4 * g);
+        const float4 b4 = *reinterpret_cast<const float4*>(br + c + CS * u + 4 * g);
+        av[u][0] = ai ? (double)a4.x : 0.0;
+        av[u][1] = ai ? (double)a4.y : 0.0;
+        av[u][2] = ai ? (double)a4.z : 0.0;
+        av[u][3] = ai ? (double)a4.w : 0.0;
+        bv[u][0] = bj ? (double)b4.x : 0.0;
+        bv[u][1] = bj ? (double)b4.y : 0.0;
+        bv[u][2] = bj ? (double)b4.z : 0.0;
+        bv[u][3] = bj ? (double)b4.w : 0.0;
       }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          av[u][m] = ai ? (double)ar[c + CS * u + 4 * g + m] : 0.0;
+          bv[u][m] = bj ? (double)br[c + CS * u + 4 * g + m] : 0.0;
+        }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][m], bv[u][m], acc, 0, 0, 0);
   }
-  for (; c < cend; c += 64) {
+  for (; c < cend; c += CS) {
     double av[4], bv[4];
-    if (c + 16 <= cend) {
+    if (sizeof(FT) == sizeof(float) && c + 16 <= cend) {
+      const float4 a4 = *reinterpret_cast<const float4*>(ar + c + 4 * g);
+      const float4 b4 = *reinterpret_cast<const float4*>(br + c + 4 * g);
+      av[0] = ai ? (double)a4.x : 0.0;
+      av[1] = ai ? (double)a4.y : 0.0;
+      av[2] = ai ? (double)a4.z : 0.0;
+      av[3] = ai ? (double)a4.w : 0.0;
+      bv[0] = bj ? (double)b4.x : 0.0;
+      bv[1] = bj ? (double)b4.y : 0.0;
+      bv[2] = bj ? (double)b4.z : 0.0;
+      bv[3] = bj ? (double)b4.w : 0.0;
+    } else if (c + 16 <= cend) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        av[m] = ai ? ar[c + 4 * g + m] : 0.0;
-        bv[m] = bj ? br[c + 4 * g + m] : 0.0;
+        av[m] = ai ? (double)ar[c + 4 * g + m] : 0.0;
+        bv[m] = bj ? (double)br[c + 4 * g + m] : 0.0;
       }
     } else {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int64_t k = c + 4 * g + m;
-        av[m] = (ai && k < cend) ? ar[k] : 0.0;
-        bv[m] = (bj && k < cend) ? br[k] : 0.0;
+        av[m] = (ai && k < cend) ? (double)ar[k] : 0.0;
+        bv[m] = (bj && k < cend) ? (double)br[k] : 0.0;
       }
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[m], acc, 0, 0, 0);
   }
   // entry e of lane (g, l16): row 16 y + g + 4 e, column 16 x + l16
-  __shared__ double red[4][16][17];
+  __shared__ double red[HP_WAVES][16][17];
 #pragma unroll
   for (int e = 0; e < 4; ++e) red[w][g + 4 * e][l16] = acc[e];
   __syncthreads();
+  if (tid >= 256) return;
   const int r = tid >> 4, cc = tid & 15;
   const bool up = x == y && cc > r;
   const int rr = up ? cc : r, ck = up ? r : cc;
-  const double v = ((red[0][rr][ck] + red[1][rr][ck]) + red[2][rr][ck]) + red[3][rr][ck];
+  double v = red[0][rr][ck];
+#pragma unroll
+  for (int q = 1; q < HP_WAVES; ++q) v += red[q][rr][ck];
   const int i = i0 + r, j = j0 + cc;
   if (i < b && j < b) {
     double* hp = Hp + (int64_t)z * b * b;
@@ -1584,7 +1628,10 @@ void launch_gather_tab(hipStream_t s, const RoundJob* tab, int n, const RoundGri
     else
       hipLaunchKernelGGL((k_gather_rows<float, true>), dim3(g.gather_rows, n), dim3(256), 0, s, RoundJob{}, tab);
   }
-  hipLaunchKernelGGL(k_gather_Hp<true>, dim3(g.gather_hp, n), dim3(256), 0, s, RoundJob{}, tab);
+  if (fdouble)
+    hipLaunchKernelGGL((k_gather_Hp<true, double>), dim3(g.gather_hp, n), dim3(64 * HP_WAVES), 0, s, RoundJob{}, tab);
+  else
+    hipLaunchKernelGGL((k_gather_Hp<true, float>), dim3(g.gather_hp, n), dim3(64 * HP_WAVES), 0, s, RoundJob{}, tab);
   if (tiled) hipLaunchKernelGGL(k_gather_Hs_tiled<true>, dim3(g.gather_hs, n), dim3(256), 0, s, RoundJob{}, tab);
   else hipLaunchKernelGGL(k_gather_Hs<true>, dim3(g.gather_hs, n), dim3(256), 0, s, RoundJob{}, tab);
 }
