@@ -576,6 +576,10 @@ __global__ __launch_bounds__(256) void k_gather_Hs_tiled(RoundJob jb0, const Rou
   __shared__ double xs[2][HS_T][HS_DC + 1];   // [0]: rows i of the block, [1]: rows j
   const int tid = threadIdx.x, ti = tid % HS_T, tj = tid / HS_T;
   const int i0 = ((int)blockIdx.x % nbt) * HS_T, j0 = ((int)blockIdx.x / nbt) * HS_T;
+  // blocks above the diagonal: their entries are written by the block below
+  // it (the same sums and the same partial products, so H stays exactly
+  // symmetric)
+  if (j0 > i0) return;
   const int i = i0 + ti, j = j0 + tj;
   // staging: thread tid copies dims (tid % 64) of rows (tid / 64) + 4 m, m < 8, of the 32 rows
   const int sd = tid % HS_DC, sr = tid / HS_DC;
@@ -586,26 +590,41 @@ __global__ __launch_bounds__(256) void k_gather_Hs_tiled(RoundJob jb0, const Rou
     const int li = r < HS_T ? i0 + r : j0 + r - HS_T;
     src[m] = X + props[li < b ? li : b - 1] * d;
   }
+  // the partial products, summed in partition order, loaded beside the first
+  // chunk's coordinates
+  const bool in = i < b && j < b;
+  const int64_t q = (int64_t)j * b + i;
+  double acc = 0.0;
+  if (in)
+    for (int p = 0; p < parts; ++p) acc += Hp[(int64_t)p * b * b + q];
   double sum = 0.0;
+  // each chunk's coordinates are loaded into registers one chunk ahead, so
+  // their loads overlap the previous chunk's sums
+  double nx[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) nx[m] = sd < d ? src[m][sd] : 0.0;
   for (int k0 = 0; k0 < d; k0 += HS_DC) {
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int r = sr + 4 * m;
-      xs[r / HS_T][r % HS_T][sd] = k0 + sd < d ? src[m][k0 + sd] : 0.0;
+      xs[r / HS_T][r % HS_T][sd] = nx[m];
     }
     __syncthreads();
+    if (k0 + HS_DC < d) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) nx[m] = k0 + HS_DC + sd < d ? src[m][k0 + HS_DC + sd] : 0.0;
+    }
     const int ke = d - k0 < HS_DC ? d - k0 : HS_DC;
     for (int t = 0; t < ke; ++t) {
       const double e = xs[0][ti][t] - xs[1][tj][t];
       sum += e * e;
     }
   }
-  if (i < b && j < b) {
-    const int64_t q = (int64_t)j * b + i;
-    double acc = 0.0;
-    for (int p = 0; p < parts; ++p) acc += Hp[(int64_t)p * b * b + q];
-    H[q] = kappa_r2(sum, kp) - acc;
+  if (in) {
+    const double h = kappa_r2(sum, kp) - acc;
+    H[q] = h;
+    if (j0 < i0) H[(int64_t)i * b + j] = h;
   }
 }
 
