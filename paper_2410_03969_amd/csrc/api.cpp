@@ -321,6 +321,7 @@ void enqueue_round(hipStream_t s, const arpc_problem& p, const KParams& kp, char
                  l.packed ? (const unsigned*)(ws + l.X8) : nullptr, l.packed ? (const float*)(ws + l.xn8) : nullptr,
                  l.dist8 ? (const unsigned char*)(ws + l.Xp8) : nullptr,
                  l.dist8 ? (const float*)(ws + l.ypn) : nullptr};
+    if (elem_size(p.prec) == sizeof(float)) mr.Fs32 = (const float*)(ws + l.Fs32);
     prof.begin(ARPC_KC_PREP);
     launch_prep_xp_tab(s, tab, 1, p.b * p.d);
     if (l.dist8)   // the accepted points as e4m3 codes for the update GEMM's epilogue

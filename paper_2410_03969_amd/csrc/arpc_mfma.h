@@ -37,6 +37,7 @@ struct MfmaRound {
   const unsigned char* Xp8;  // FP8 mode with the distances in the update GEMM's epilogue: the
                              // accepted points as e4m3 codes (b x d bytes), else null
   const float* ypn;        // their squared norms (FP32)
+  const float* Fs32 = nullptr;   // F rows at the proposals in FP32 (F stored in FP32), ld fs32_ld(ldf)
 };
 
 // Device pointers and sizes of the one-kernel round product of the BF16

@@ -1173,6 +1173,60 @@ __global__ __launch_bounds__(256) void k_prep_bm(const double* __restrict__ Fs, 
   }
 }
 
+// The same from the FP32 copy of the rows (F stored in FP32; the values, and
+// so Bm, are the same): a thread takes eight consecutive k of one column, two
+// aligned 16-byte loads from one row of the copy and one 16-byte store per
+// BF16 plane (32 bytes for FP32), where the form above reads one element of a
+// different row per lane.
+template <class Pol, int PASSES>
+__global__ __launch_bounds__(256) void k_prep_bm32(const float* __restrict__ Fs32, int64_t ld32, int64_t nk8,
+                                                   const int32_t* __restrict__ acc, int Ctot,
+                                                   unsigned char* __restrict__ Bm, const RoundState* st) {
+  static_assert(Pol::KC % 8 == 0, "a thread's eight k stay in one chunk");
+  if (st->status != ST_RUNNING) return;
+  const int s = st->s_r;
+  const int64_t K = st->k_r;
+  const int64_t Kpad = (K + Pol::KC - 1) / Pol::KC * Pol::KC;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c64 = e / nk8, k0 = 8 * (e % nk8);
+  if (c64 >= Ctot || k0 >= Kpad) return;
+  const int c = (int)c64;
+  float v[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+  if (c < s && k0 < K) {
+    // the row starts 16-byte aligned and k0 is a multiple of 8
+    const float* src = Fs32 + (int64_t)acc[c] * ld32 + k0;
+    if (k0 + 8 <= K) {
+      const float4 a = *reinterpret_cast<const float4*>(src);
+      const float4 b = *reinterpret_cast<const float4*>(src + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (k0 + t < K) v[t] = src[t];
+    }
+  }
+  if constexpr (Pol::KC == 32) {
+    __bf16 hi[8], lo[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) split_bf16(v[t], hi[t], lo[t]);
+    uint4 w;
+    __builtin_memcpy(&w, hi, sizeof(w));
+    *(uint4*)(Bm + chunk_offset<Pol>(k0, c, Ctot, 0)) = w;
+    if (PASSES == 3) {
+      __builtin_memcpy(&w, lo, sizeof(w));
+      *(uint4*)(Bm + chunk_offset<Pol>(k0, c, Ctot, 1)) = w;
+    }
+  } else {
+    static_assert(sizeof(typename Pol::T) == sizeof(float), "FP32 elements");
+    float4* dst = (float4*)(Bm + chunk_offset<Pol>(k0, c, Ctot, 0));
+    dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+    dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+  }
+}
+
 // Inverse of the s x s lower factor L (read from H through the accepted
 // indices): workgroup c (four wavefronts) computes column c by forward
 // substitution and stores Linv(i, c) as element (k = c, column i) of the
@@ -1300,9 +1354,20 @@ static void dispatch(hipStream_t s, const MfmaRound& r, const RoundState* st, in
 template <class Pol, int PASSES>
 static void prep_impl(hipStream_t s, const MfmaRound& r, const RoundState* st) {
   const int64_t kpad = (r.kmax + Pol::KC - 1) / Pol::KC * Pol::KC;
-  const int64_t n = kpad * r.Ctot;
-  hipLaunchKernelGGL((k_prep_bm<Pol, PASSES>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r.Fs, r.ldf,
-                     r.acc, r.Ctot, r.Bm1, st);
+  bool done = false;
+  if constexpr (std::is_same<typename Pol::T, float>::value) {
+    if (r.Fs32) {
+      const int64_t nk8 = kpad / 8, n = nk8 * r.Ctot;
+      hipLaunchKernelGGL((k_prep_bm32<Pol, PASSES>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r.Fs32,
+                         fs32_ld(r.ldf), nk8, r.acc, r.Ctot, r.Bm1, st);
+      done = true;
+    }
+  }
+  if (!done) {
+    const int64_t n = kpad * r.Ctot;
+    hipLaunchKernelGGL((k_prep_bm<Pol, PASSES>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r.Fs, r.ldf,
+                       r.acc, r.Ctot, r.Bm1, st);
+  }
   const int nblk = (r.b + Pol::KC - 1) / Pol::KC * Pol::KC;
   hipLaunchKernelGGL((k_trinv_bm<Pol, PASSES>), dim3(nblk), dim3(256), 0, s, LFactor{r.H, r.acc, r.b}, r.Ctot, r.Bm2,
                      st);

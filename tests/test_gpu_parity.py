@@ -396,6 +396,35 @@ def test_fused_round_factor_consistent_with_its_pivots(prec, b, d):
     assert np.sum(F ** 2) <= trA * (1 + 1e-3)
 
 
+@pytest.mark.parametrize("prec", [W.FP32, W.BF16X3, W.BF16])
+def test_product_term_rows_unaligned_k(prec):
+    """Where F is stored in FP32, H's product term F(S',:) F(S',:)^T reads the
+    proposals' rows from an FP32 copy whose leading dimension is k rounded up
+    to a multiple of four, four columns per 16-byte load.  k = 301 leaves
+    three pad columns per row, the contraction splits into two partitions
+    (k > 256), and k_r ends inside a 16-column chunk in most rounds; the
+    first 2b columns (k_r up to 300, into the second partition) equal the
+    FP64 factor of the same pivots."""
+    rng = np.random.default_rng(301)
+    N, b, d = 5003, 150, 8
+    X = rng.uniform(0.0, 1.0, size=(N, d))
+    prob = W.Problem(N=N, d=d, k=301, b=b, kernel=W.LAPLACE_L2, sigma=0.5, seed=13, prec=prec)
+    print(f"[gpu parity] product term rows, prec={prec} N={N} k=301 b={b}", flush=True)
+    F, piv, out = gpu_factor(X, prob)
+    k_out = out["stats"]["k_out"]
+    assert k_out == prob.k and len(set(piv[:k_out].tolist())) == k_out
+    acc = PointsAccess(X, prob.kernel, prob.sigma)
+    rows = np.concatenate([np.random.default_rng(3).choice(N, 150, replace=False), np.arange(N - 40, N)])
+    ncols = 2 * b
+    ref = factor_from_pivots(acc, piv[:ncols], rows=rows)
+    err = np.linalg.norm(F[rows, :ncols] - ref) / np.linalg.norm(ref)
+    tol = {W.FP32: 1e-4, **FUSED_TOL}[prec]
+    print(f"product term rows prec={prec}: relF={err:.3e} (tol {tol:g})")
+    assert err < tol, err
+    if prec != W.FP32:
+        assert_elementwise(F[rows, :ncols], ref, prec, f"product term rows prec={prec}")
+
+
 @pytest.mark.parametrize("prec,b,d", [(W.BF16, 20, 17), (W.BF16, 60, 24), (W.BF16, 120, 32), (W.BF16, 200, 32)])
 def test_fused_round_wide_points(prec, b, d):
     """The one-product BF16 mode also runs one kernel per round for
